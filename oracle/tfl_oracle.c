@@ -1,0 +1,513 @@
+/*
+ * tfl_oracle.c -- plain FP64 CPU oracle of the two-fluid (Maxwell + London)
+ * FDTD scheme.
+ *
+ * TEST INFRASTRUCTURE ONLY.  It is built into oracle/liboracle.so and is
+ * loaded by tests/, by the smoke check and by the CPU-baseline leg of the
+ * benchmark.  The product library never links, loads or calls it, and the
+ * two share no source, header or table.
+ *
+ * What it computes (paper: Sec. 2 Eqs. Ampere, Faraday, London1a; Sec. 3 and
+ * Algorithm 1):
+ *   State at integer time n: E^n on cell edges, B^n on cell faces, Js^n on
+ *   the superconducting cell edges (Yee staggering, Sec. 3).  One time step is
+ *   the five sub-steps of Algorithm 1 in the paper's order:
+ *     1. B^{n+1/2}  = B^n - dt/2 curl E^n
+ *     2. Js^{n+1/2} = Js^n + dt/2 * E^n / (lambda^2 mu0)        (SC edges only)
+ *     3. E^{n+1}    = (1 + theta s)^-1 (E^n + dt/eps curl H^{n+1/2}
+ *                      - (1 - theta) s E^n - dt/eps Js^{n+1/2}),  s = sigma dt/eps
+ *     4. Js^{n+1}   = Js^{n+1/2} + dt/2 * E^{n+1} / (lambda^2 mu0)
+ *     5. B^{n+1}    = B^{n+1/2} - dt/2 curl E^{n+1}
+ *   with H = B / mu0 (mu_r = 1, Sec. 4.2 and Sec. 5).
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   - per-edge material: an edge whose four sharing cells include any
+ *     superconducting cell (ell > 0) is superconducting and takes the mean of
+ *     (eps_r, sigma, ell) over those superconducting cells; any other edge takes
+ *     the mean of (eps_r, sigma) over all four cells and ell = 0 (Sec. 3: every
+ *     edge on an SC interface is superconducting and carries Js; this choice
+ *     reproduces the first-order strip errors of Table 4);
+ *   - open boundaries: convolutional PML (Roden and Gedney 2000) with a
+ *     polynomial grading, backed by a PEC wall on node plane 0 of every PML
+ *     axis (tangential E held at 0); indexing wraps on every axis;
+ *   - the PML auxiliary variable of the B update is advanced whenever a new E
+ *     is available (at initialisation and in sub-step 5), so that sub-steps 1
+ *     and 5 use the same stretched curl;
+ *   - soft sources add A g(t_{n+1}) to E^{n+1} at the end of sub-step 3;
+ *   - probes sum E over an index box; series index n holds time level n,
+ *     sample 0 is the state passed to oracle_set_fields.
+ *
+ * The code favours plain loops over speed: every array is a full grid and
+ * every neighbour index is wrapped explicitly.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define O_EPS0 8.8541878128e-12
+#define O_MU0 1.25663706212e-6
+
+#define O_MAXSRC 64
+#define O_MAXPROBE 64
+
+typedef struct {
+    int comp;
+    long box[6]; /* i0 i1 j0 j1 k0 k1, half-open, edge indices of the component */
+    double amp;
+    int kind;    /* 0 sin(2 pi f t), 1 gauss, 2 gauss * sin(2 pi f t) */
+    double f, t0, tw;
+} o_source;
+
+typedef struct {
+    int comp;
+    long box[6];
+    long cap;
+    double *series;
+    int nfreq;
+    double *freq;
+    double *dft_re, *dft_im;
+} o_probe;
+
+typedef struct {
+    long n[3];
+    double d[3];
+    double dt, theta;
+    int pml[3];
+    long npml_lo[3], npml_hi[3];
+    double pml_order, pml_scale, kappa_max, alpha_max;
+
+    double *eps[3], *sig[3], *ell[3]; /* per edge of component c */
+    double *E[3], *B[3], *J[3];
+    double *psiB[3][3]; /* [component][derivative axis] */
+    double *psiE[3][3];
+    /* 1-D PML coefficients per axis: at nodes (integer) and at half nodes */
+    double *bn[3], *cn[3], *kin[3];
+    double *bh[3], *ch[3], *kih[3];
+
+    long step;
+    int sampled0;
+    int nsrc;
+    o_source src[O_MAXSRC];
+    int nprobe;
+    o_probe probe[O_MAXPROBE];
+} oracle_sim;
+
+static long o_wrap(long i, long n) { long r = i % n; return r < 0 ? r + n : r; }
+
+static long o_idx(const oracle_sim *s, long i, long j, long k)
+{
+    return (o_wrap(k, s->n[2]) * s->n[1] + o_wrap(j, s->n[1])) * s->n[0] + o_wrap(i, s->n[0]);
+}
+
+static long o_cells(const oracle_sim *s) { return s->n[0] * s->n[1] * s->n[2]; }
+
+static double *o_zeros(long m) { return (double *)calloc((size_t)m, sizeof(double)); }
+
+/* Position of a component's sample along an axis is half-integer when the
+ * component is E and the axis is its own direction, or when the component is
+ * B and the axis is not its own direction. */
+
+/* ---- convolutional PML profile (Roden and Gedney 2000) ------------------ */
+static void o_pml_coeffs(const oracle_sim *s, int ax, double pos, double *b, double *c, double *kinv)
+{
+    double depth = -1.0;
+    long n = s->n[ax];
+    long lo = s->npml_lo[ax], hi = s->npml_hi[ax];
+    *b = 1.0; *c = 0.0; *kinv = 1.0;
+    if (!s->pml[ax]) return;
+    if (lo > 0 && pos < (double)lo) depth = ((double)lo - pos) / (double)lo;
+    else if (hi > 0 && pos > (double)(n - hi)) depth = (pos - (double)(n - hi)) / (double)hi;
+    if (depth <= 0.0) return;
+    double eta0 = sqrt(O_MU0 / O_EPS0);
+    double m = s->pml_order;
+    double smax = s->pml_scale * 0.8 * (m + 1.0) / (eta0 * s->d[ax]);
+    double sg = smax * pow(depth, m);
+    double kp = 1.0 + (s->kappa_max - 1.0) * pow(depth, m);
+    double al = s->alpha_max * (1.0 - depth);
+    *b = exp(-(sg / kp + al) * s->dt / O_EPS0);
+    *c = (sg > 0.0) ? sg / (sg * kp + kp * kp * al) * (*b - 1.0) : 0.0;
+    *kinv = 1.0 / kp;
+}
+
+oracle_sim *oracle_create(const long *n, const double *d, double dt, double theta,
+                          const int *pml, const long *npml_lo, const long *npml_hi,
+                          double pml_order, double pml_scale, double kappa_max, double alpha_max)
+{
+    oracle_sim *s = (oracle_sim *)calloc(1, sizeof(oracle_sim));
+    for (int a = 0; a < 3; ++a) {
+        s->n[a] = n[a]; s->d[a] = d[a];
+        s->pml[a] = pml[a]; s->npml_lo[a] = npml_lo[a]; s->npml_hi[a] = npml_hi[a];
+    }
+    s->dt = dt; s->theta = theta;
+    s->pml_order = pml_order; s->pml_scale = pml_scale;
+    s->kappa_max = kappa_max; s->alpha_max = alpha_max;
+    long N = o_cells(s);
+    for (int c = 0; c < 3; ++c) {
+        s->eps[c] = o_zeros(N); s->sig[c] = o_zeros(N); s->ell[c] = o_zeros(N);
+        s->E[c] = o_zeros(N); s->B[c] = o_zeros(N); s->J[c] = o_zeros(N);
+        for (int a = 0; a < 3; ++a) {
+            if (a != c && pml[a]) { s->psiB[c][a] = o_zeros(N); s->psiE[c][a] = o_zeros(N); }
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        long m = n[a];
+        s->bn[a] = o_zeros(m); s->cn[a] = o_zeros(m); s->kin[a] = o_zeros(m);
+        s->bh[a] = o_zeros(m); s->ch[a] = o_zeros(m); s->kih[a] = o_zeros(m);
+        for (long i = 0; i < m; ++i) {
+            o_pml_coeffs(s, a, (double)i, &s->bn[a][i], &s->cn[a][i], &s->kin[a][i]);
+            o_pml_coeffs(s, a, (double)i + 0.5, &s->bh[a][i], &s->ch[a][i], &s->kih[a][i]);
+        }
+    }
+    return s;
+}
+
+void oracle_destroy(oracle_sim *s)
+{
+    if (!s) return;
+    for (int c = 0; c < 3; ++c) {
+        free(s->eps[c]); free(s->sig[c]); free(s->ell[c]);
+        free(s->E[c]); free(s->B[c]); free(s->J[c]);
+        for (int a = 0; a < 3; ++a) { free(s->psiB[c][a]); free(s->psiE[c][a]); }
+    }
+    for (int a = 0; a < 3; ++a) {
+        free(s->bn[a]); free(s->cn[a]); free(s->kin[a]);
+        free(s->bh[a]); free(s->ch[a]); free(s->kih[a]);
+    }
+    for (int p = 0; p < s->nprobe; ++p) {
+        free(s->probe[p].series); free(s->probe[p].freq);
+        free(s->probe[p].dft_re); free(s->probe[p].dft_im);
+    }
+    free(s);
+}
+
+/* Per-edge material.  An edge of component c at index (i,j,k) runs along
+ * axis c; the four cells sharing it are offset by 0 or -1 along each of the
+ * two other axes.  If any of them is superconducting (ell > 0) the edge is
+ * superconducting and takes the mean over the superconducting ones;
+ * otherwise it takes the mean over all four. */
+void oracle_set_materials(oracle_sim *s, const double *eps_r, const double *sigma, const double *ell)
+{
+    for (int c = 0; c < 3; ++c) {
+        int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+        for (long k = 0; k < s->n[2]; ++k)
+            for (long j = 0; j < s->n[1]; ++j)
+                for (long i = 0; i < s->n[0]; ++i) {
+                    long e = o_idx(s, i, j, k);
+                    long cells[4];
+                    int nsc = 0;
+                    for (int u = 0; u < 2; ++u)
+                        for (int v = 0; v < 2; ++v) {
+                            long o[3] = {i, j, k};
+                            o[a1] -= u;
+                            o[a2] -= v;
+                            cells[2 * u + v] = o_idx(s, o[0], o[1], o[2]);
+                            if (ell[cells[2 * u + v]] > 0.0) nsc += 1;
+                        }
+                    double se = 0.0, ss = 0.0, sl = 0.0;
+                    int cnt = 0;
+                    for (int q = 0; q < 4; ++q) {
+                        long cc = cells[q];
+                        if (nsc > 0 && !(ell[cc] > 0.0)) continue;
+                        se += eps_r[cc]; ss += sigma[cc]; sl += ell[cc];
+                        cnt += 1;
+                    }
+                    s->eps[c][e] = O_EPS0 * se / (double)cnt;
+                    s->sig[c][e] = ss / (double)cnt;
+                    s->ell[c][e] = sl / (double)cnt;
+                }
+    }
+}
+
+/* Is the edge of component c at (i,j,k) on the PEC wall (node plane 0 of a
+ * PML axis that is not the edge's own direction)? */
+static int o_on_wall(const oracle_sim *s, int c, const long *ijk)
+{
+    for (int a = 0; a < 3; ++a)
+        if (a != c && s->pml[a] && ijk[a] == 0) return 1;
+    return 0;
+}
+
+/* Stretched derivative of F along axis a at a B_c sample: forward difference.
+ * Advances the PML variable first when advance != 0. */
+static double o_dB(oracle_sim *s, int c, int a, const double *F, const long *ijk, long e, int advance)
+{
+    long p[3] = {ijk[0], ijk[1], ijk[2]};
+    p[a] += 1;
+    double dF = (F[o_idx(s, p[0], p[1], p[2])] - F[e]) / s->d[a];
+    long ia = ijk[a];
+    double val = s->kih[a][ia] * dF;
+    if (s->psiB[c][a]) {
+        if (advance) s->psiB[c][a][e] = s->bh[a][ia] * s->psiB[c][a][e] + s->ch[a][ia] * dF;
+        val += s->psiB[c][a][e];
+    }
+    return val;
+}
+
+/* curl E at B_c samples, with PML stretching (Faraday's law, Eq. Faraday). */
+static double o_curlE(oracle_sim *s, int c, const long *ijk, long e, int advance)
+{
+    int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+    /* (curl E)_c = d_{a1} E_{a2} - d_{a2} E_{a1} */
+    return o_dB(s, c, a1, s->E[a2], ijk, e, advance) - o_dB(s, c, a2, s->E[a1], ijk, e, advance);
+}
+
+static void o_half_B(oracle_sim *s, int advance_psi)
+{
+    double h = 0.5 * s->dt;
+    for (int c = 0; c < 3; ++c) {
+#pragma omp parallel for
+        for (long k = 0; k < s->n[2]; ++k)
+            for (long j = 0; j < s->n[1]; ++j)
+                for (long i = 0; i < s->n[0]; ++i) {
+                    long ijk[3] = {i, j, k};
+                    long e = o_idx(s, i, j, k);
+                    double cE = o_curlE(s, c, ijk, e, advance_psi);
+                    s->B[c][e] -= h * cE;
+                }
+    }
+}
+
+/* Advance only the PML variables of the B update with the current E. */
+static void o_advance_psiB(oracle_sim *s)
+{
+    for (int c = 0; c < 3; ++c) {
+#pragma omp parallel for
+        for (long k = 0; k < s->n[2]; ++k)
+            for (long j = 0; j < s->n[1]; ++j)
+                for (long i = 0; i < s->n[0]; ++i) {
+                    long ijk[3] = {i, j, k};
+                    long e = o_idx(s, i, j, k);
+                    (void)o_curlE(s, c, ijk, e, 1);
+                }
+    }
+}
+
+static void o_half_J(oracle_sim *s)
+{
+    for (int c = 0; c < 3; ++c) {
+        long N = o_cells(s);
+        for (long e = 0; e < N; ++e) {
+            if (s->ell[c][e] > 0.0) /* superconducting edges only */
+                s->J[c][e] += 0.5 * s->dt * s->E[c][e] * s->ell[c][e] / O_MU0;
+        }
+    }
+}
+
+static double o_dE(oracle_sim *s, int c, int a, const double *F, const long *ijk, long e)
+{
+    long p[3] = {ijk[0], ijk[1], ijk[2]};
+    p[a] -= 1;
+    double dF = (F[e] - F[o_idx(s, p[0], p[1], p[2])]) / s->d[a];
+    long ia = ijk[a];
+    double val = s->kin[a][ia] * dF;
+    if (s->psiE[c][a]) {
+        s->psiE[c][a][e] = s->bn[a][ia] * s->psiE[c][a][e] + s->cn[a][ia] * dF;
+        val += s->psiE[c][a][e];
+    }
+    return val;
+}
+
+static double o_waveform(const o_source *q, double t)
+{
+    const double twopi = 2.0 * 3.14159265358979323846;
+    switch (q->kind) {
+    case 0: return sin(twopi * q->f * t);
+    case 1: return exp(-(t - q->t0) * (t - q->t0) / (2.0 * q->tw * q->tw));
+    default: return exp(-(t - q->t0) * (t - q->t0) / (2.0 * q->tw * q->tw)) * sin(twopi * q->f * t);
+    }
+}
+
+static void o_full_E(oracle_sim *s)
+{
+    double dt = s->dt, th = s->theta;
+    /* H^{n+1/2} = B^{n+1/2} / mu0, formed once so that the curl reads H. */
+    long N = o_cells(s);
+    double *H[3];
+    for (int c = 0; c < 3; ++c) {
+        H[c] = (double *)malloc((size_t)N * sizeof(double));
+        for (long e = 0; e < N; ++e) H[c][e] = s->B[c][e] / O_MU0;
+    }
+    for (int c = 0; c < 3; ++c) {
+        int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+#pragma omp parallel for
+        for (long k = 0; k < s->n[2]; ++k)
+            for (long j = 0; j < s->n[1]; ++j)
+                for (long i = 0; i < s->n[0]; ++i) {
+                    long ijk[3] = {i, j, k};
+                    long e = o_idx(s, i, j, k);
+                    /* (curl H)_c = d_{a1} H_{a2} - d_{a2} H_{a1} (Eq. Ampere) */
+                    double cH = o_dE(s, c, a1, H[a2], ijk, e) - o_dE(s, c, a2, H[a1], ijk, e);
+                    if (o_on_wall(s, c, ijk)) { s->E[c][e] = 0.0; continue; }
+                    double eps = s->eps[c][e];
+                    double sg = s->sig[c][e] * dt / eps;
+                    double js = (s->ell[c][e] > 0.0) ? s->J[c][e] : 0.0;
+                    double En = s->E[c][e];
+                    s->E[c][e] = (En + dt / eps * cH - (1.0 - th) * sg * En - dt / eps * js) / (1.0 + th * sg);
+                }
+    }
+    for (int c = 0; c < 3; ++c) free(H[c]);
+    /* soft sources at t_{n+1} */
+    double t = (double)(s->step + 1) * dt;
+    for (int q = 0; q < s->nsrc; ++q) {
+        const o_source *src = &s->src[q];
+        double g = src->amp * o_waveform(src, t);
+        for (long k = src->box[4]; k < src->box[5]; ++k)
+            for (long j = src->box[2]; j < src->box[3]; ++j)
+                for (long i = src->box[0]; i < src->box[1]; ++i)
+                    s->E[src->comp][o_idx(s, i, j, k)] += g;
+    }
+}
+
+static void o_sample(oracle_sim *s, long n)
+{
+    const double twopi = 2.0 * 3.14159265358979323846;
+    for (int p = 0; p < s->nprobe; ++p) {
+        o_probe *q = &s->probe[p];
+        double sum = 0.0;
+        for (long k = q->box[4]; k < q->box[5]; ++k)
+            for (long j = q->box[2]; j < q->box[3]; ++j)
+                for (long i = q->box[0]; i < q->box[1]; ++i)
+                    sum += s->E[q->comp][o_idx(s, i, j, k)];
+        if (n < q->cap) q->series[n] = sum;
+        for (int f = 0; f < q->nfreq; ++f) {
+            double ph = twopi * q->freq[f] * (double)n * s->dt;
+            q->dft_re[f] += sum * s->dt * cos(ph);
+            q->dft_im[f] -= sum * s->dt * sin(ph);
+        }
+    }
+}
+
+/* Integer-time state at t = 0.  Resets the step counter, the PML variables
+ * and the probe accumulators. */
+void oracle_set_fields(oracle_sim *s, double *const *E, double *const *B, double *const *J)
+{
+    long N = o_cells(s);
+    for (int c = 0; c < 3; ++c) {
+        memcpy(s->E[c], E[c], (size_t)N * sizeof(double));
+        memcpy(s->B[c], B[c], (size_t)N * sizeof(double));
+        memcpy(s->J[c], J[c], (size_t)N * sizeof(double));
+        for (int a = 0; a < 3; ++a) {
+            if (s->psiB[c][a]) memset(s->psiB[c][a], 0, (size_t)N * sizeof(double));
+            if (s->psiE[c][a]) memset(s->psiE[c][a], 0, (size_t)N * sizeof(double));
+        }
+    }
+    s->step = 0;
+    s->sampled0 = 0;
+    for (int p = 0; p < s->nprobe; ++p) {
+        o_probe *q = &s->probe[p];
+        memset(q->series, 0, (size_t)q->cap * sizeof(double));
+        memset(q->dft_re, 0, (size_t)q->nfreq * sizeof(double));
+        memset(q->dft_im, 0, (size_t)q->nfreq * sizeof(double));
+    }
+    o_advance_psiB(s);
+}
+
+void oracle_get_fields(const oracle_sim *s, double *const *E, double *const *B, double *const *J)
+{
+    long N = o_cells(s);
+    for (int c = 0; c < 3; ++c) {
+        if (E) memcpy(E[c], s->E[c], (size_t)N * sizeof(double));
+        if (B) memcpy(B[c], s->B[c], (size_t)N * sizeof(double));
+        if (J) memcpy(J[c], s->J[c], (size_t)N * sizeof(double));
+    }
+}
+
+void oracle_get_edge_materials(const oracle_sim *s, double *const *eps, double *const *sig, double *const *ell)
+{
+    long N = o_cells(s);
+    for (int c = 0; c < 3; ++c) {
+        memcpy(eps[c], s->eps[c], (size_t)N * sizeof(double));
+        memcpy(sig[c], s->sig[c], (size_t)N * sizeof(double));
+        memcpy(ell[c], s->ell[c], (size_t)N * sizeof(double));
+    }
+}
+
+int oracle_add_source(oracle_sim *s, int comp, const long *box, double amp, int kind, double f, double t0, double tw)
+{
+    if (s->nsrc >= O_MAXSRC) return -1;
+    o_source *q = &s->src[s->nsrc];
+    q->comp = comp;
+    for (int i = 0; i < 6; ++i) q->box[i] = box[i];
+    q->amp = amp; q->kind = kind; q->f = f; q->t0 = t0; q->tw = tw;
+    return s->nsrc++;
+}
+
+int oracle_add_probe(oracle_sim *s, int comp, const long *box, long cap, int nfreq, const double *freq)
+{
+    if (s->nprobe >= O_MAXPROBE) return -1;
+    o_probe *q = &s->probe[s->nprobe];
+    q->comp = comp;
+    for (int i = 0; i < 6; ++i) q->box[i] = box[i];
+    q->cap = cap;
+    q->series = o_zeros(cap > 0 ? cap : 1);
+    q->nfreq = nfreq;
+    q->freq = o_zeros(nfreq > 0 ? nfreq : 1);
+    for (int f = 0; f < nfreq; ++f) q->freq[f] = freq[f];
+    q->dft_re = o_zeros(nfreq > 0 ? nfreq : 1);
+    q->dft_im = o_zeros(nfreq > 0 ? nfreq : 1);
+    return s->nprobe++;
+}
+
+void oracle_probe_read(const oracle_sim *s, int p, double *series, double *dft_re, double *dft_im)
+{
+    const o_probe *q = &s->probe[p];
+    if (series) memcpy(series, q->series, (size_t)q->cap * sizeof(double));
+    if (dft_re) memcpy(dft_re, q->dft_re, (size_t)q->nfreq * sizeof(double));
+    if (dft_im) memcpy(dft_im, q->dft_im, (size_t)q->nfreq * sizeof(double));
+}
+
+/* Algorithm 1, nsteps times. */
+void oracle_step(oracle_sim *s, long nsteps)
+{
+    if (!s->sampled0 && s->step == 0) { o_sample(s, 0); s->sampled0 = 1; }
+    for (long it = 0; it < nsteps; ++it) {
+        o_half_B(s, 0);   /* 1. B^n -> B^{n+1/2} */
+        o_half_J(s);      /* 2. Js^n -> Js^{n+1/2} */
+        o_full_E(s);      /* 3. E^n -> E^{n+1} (+ soft sources) */
+        o_half_J(s);      /* 4. Js^{n+1/2} -> Js^{n+1} */
+        o_half_B(s, 1);   /* 5. B^{n+1/2} -> B^{n+1} (PML variable advanced with E^{n+1}) */
+        s->step += 1;
+        o_sample(s, s->step);
+    }
+}
+
+long oracle_step_index(const oracle_sim *s) { return s->step; }
+
+/* Discrete energy at integer time n, written with the integer-time state:
+ *   W^n = dV [ sum_e eps_e E_e^2 / 2
+ *            + sum_f (B_f^2 - (dt/2 curlE_f)^2) / (2 mu0)
+ *            + sum_{SC e} mu0 (J_e^2 - (dt/2 ell_e E_e / mu0)^2) / (2 ell_e) ].
+ * This equals dV [eps E^2/2 + mu0 H^{n-1/2} H^{n+1/2}/2 + mu0 J^{n-1/2} J^{n+1/2}/(2 ell)],
+ * the quantity conserved by the leap-frog of Algorithm 1 without loss (and
+ * decreased by exactly the Ohmic work with sigma > 0).  PML stretching is
+ * ignored: meaningful on periodic domains only. */
+double oracle_energy(const oracle_sim *s)
+{
+    double dV = s->d[0] * s->d[1] * s->d[2];
+    double we = 0.0, wb = 0.0, wj = 0.0;
+    long N = o_cells(s);
+    for (int c = 0; c < 3; ++c) {
+        int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+        for (long k = 0; k < s->n[2]; ++k)
+            for (long j = 0; j < s->n[1]; ++j)
+                for (long i = 0; i < s->n[0]; ++i) {
+                    long e = o_idx(s, i, j, k);
+                    long p1[3] = {i, j, k}, p2[3] = {i, j, k};
+                    p1[a1] += 1;
+                    p2[a2] += 1;
+                    double cE = (s->E[a2][o_idx(s, p1[0], p1[1], p1[2])] - s->E[a2][e]) / s->d[a1]
+                              - (s->E[a1][o_idx(s, p2[0], p2[1], p2[2])] - s->E[a1][e]) / s->d[a2];
+                    double hb = 0.5 * s->dt * cE;
+                    wb += (s->B[c][e] * s->B[c][e] - hb * hb) / (2.0 * O_MU0);
+                }
+        for (long e = 0; e < N; ++e) {
+            we += s->eps[c][e] * s->E[c][e] * s->E[c][e] / 2.0;
+            if (s->ell[c][e] > 0.0) {
+                double hj = 0.5 * s->dt * s->ell[c][e] * s->E[c][e] / O_MU0;
+                wj += O_MU0 * (s->J[c][e] * s->J[c][e] - hj * hj) / (2.0 * s->ell[c][e]);
+            }
+        }
+    }
+    return dV * (we + wb + wj);
+}
