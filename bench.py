@@ -1,0 +1,152 @@
+"""Throughput of the two-fluid FDTD step on one MI355X.
+
+Workload: the 256^3 roofline grid (dx = 20 nm, periodic, random
+superconducting boxes on ~30 % of the cells, E and H ~ N(0, 1)), stepped in
+FP64 and in FP32.  A step is one full time step of Algorithm 1 (the H pass
+and the E + Js pass).  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--n 256] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Gcell-updates/s & %HBM roofline, FP64 vs FP32; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+
+
+def sc_edge_fraction(ell):
+    """Fraction of edges that carry Js: an edge is superconducting when any of the four cells
+    sharing it is (bench-side accounting of the algorithmic bytes)."""
+    import numpy as np
+    sc = ell > 0
+    fr = []
+    # Ex edge (i,j,k): cells offset by 0/-1 in y (axis 1 of the array is y) and z (axis 0)
+    for axes in ((0, 1), (0, 2), (1, 2)):
+        m = sc.copy()
+        m |= np.roll(sc, 1, axis=axes[0])
+        m |= np.roll(sc, 1, axis=axes[1])
+        m |= np.roll(np.roll(sc, 1, axis=axes[0]), 1, axis=axes[1])
+        fr.append(m.mean())
+    return float(np.mean(fr))
+
+
+def run_gpu(wl, dtype, steps, warmup):
+    import numpy as np
+    import torch
+
+    from paper_2305_13419_amd import Simulation
+
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"])
+    sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
+    E, H, _ = wl["fields"]
+    sim.set_fields([np.asarray(a, dtype=npdt) for a in E], [np.asarray(a, dtype=npdt) for a in H])
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    # timed region: K steps, HIP events around every pass on the launch stream
+    t0 = time.perf_counter()
+    h_ms, e_ms = sim.profile_step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    W, bad = sim.energy()
+    sim.close()
+    return dict(h_ms=h_ms / steps, e_ms=e_ms / steps, step_ms=(h_ms + e_ms) / steps, wall_s=wall,
+                nonfinite=int(bad), energy=W)
+
+
+def cpu_baseline(wl, steps):
+    """The FP64 CPU oracle on the same grid, a bounded number of steps."""
+    import numpy as np
+
+    from oracle.oracle import OracleSim
+
+    E, H, _ = wl["fields"]
+    o = OracleSim(wl["shape"], wl["spacing"], wl["dt"], wl["theta"])
+    o.set_materials(*wl["maps"])
+    o.set_fields(E, [h * 1.25663706212e-6 for h in H], [np.zeros_like(E[0])] * 3)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    n = wl["shape"][0] * wl["shape"][1] * wl["shape"][2]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=n * steps / dt / 1e9, unit="Gcell-updates/s", cores=cores, kind="oracle",
+                sample=f"{steps} FP64 steps of the same {wl['shape'][0]}^3 grid ({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2305_13419_amd import workloads
+
+    wl = workloads.roofline_grid(args.n, steps=args.steps)
+    ncell = args.n**3
+    fJ = sc_edge_fraction(wl["maps"][2])
+    res = {}
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        print(f"# {name}: {args.warmup} warm-up + {args.steps} timed steps on {wl['name']}", file=sys.stderr,
+              flush=True)
+        res[name] = run_gpu(wl, dt, args.steps, args.warmup)
+    out = {}
+    for name, w in (("f64", 8), ("f32", 4)):
+        r = res[name]
+        gcell = ncell / (r["step_ms"] * 1e-3) / 1e9
+        e_bytes = w * (12 + 6 * fJ) * ncell      # E pass: H, E, maps read; E written; Js r/w on SC edges
+        h_bytes = w * 9 * ncell                   # H pass: E, H read; H written
+        step_bytes = e_bytes + h_bytes
+        e_gbs = e_bytes / (r["e_ms"] * 1e-3) / 1e9
+        out[name] = dict(
+            value=gcell, ms_per_step=r["step_ms"], h_pass_ms=r["h_ms"], e_pass_ms=r["e_ms"],
+            step_GBs=step_bytes / (r["step_ms"] * 1e-3) / 1e9,
+            h_pass_GBs=h_bytes / (r["h_ms"] * 1e-3) / 1e9, e_pass_GBs=e_gbs,
+            nonfinite=r["nonfinite"],
+            roofline=dict(bound="hbm", kernel="e_pass_kernel", achieved=e_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=e_gbs / HBM_PEAK_GBS, traffic=None,
+                          bytes_per_cell=w * (12 + 6 * fJ)),
+        )
+    f64 = out["f64"]
+    line = {
+        "metric": METRIC,
+        "value": f64["value"],
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["name"] + " roofline grid, dx=20nm, periodic, ~30% SC boxes (seed 2), "
+                               "E,H~N(0,1), theta=1", "cells": ncell, "sc_edge_fraction": fJ},
+        "roofline": f64["roofline"],
+        "f64": {k: v for k, v in f64.items() if k != "roofline"},
+        "f32": out["f32"],
+    }
+    if not args.no_cpu:
+        print(f"# cpu_baseline: oracle, {args.cpu_steps} steps", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

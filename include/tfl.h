@@ -1,0 +1,209 @@
+/*
+ * tfl.h -- C ABI of the two-fluid (Maxwell + London) FDTD library for AMD
+ * MI355X (gfx950).
+ *
+ * The method (arXiv 2305.13419, Sec. 2 and Sec. 3, Algorithm 1): Maxwell's
+ * equations on a Yee grid (Sec. 3) with the total current J = sigma E + Js
+ * (Sec. 2), where the supercurrent obeys the first London equation
+ * dJs/dt = E / (lambda_L^2 mu0) (Eq. London1a), advanced by the explicit
+ * leap-frog of Algorithm 1 with the theta-weighted Ohmic term (Algorithm 1,
+ * step 3).  The library keeps the staggered state (E^n, H^{n-1/2}, Js^{n-1/2})
+ * and applies Algorithm 1's split half steps of B and Js only where
+ * integer-time values are set or read (tfl_set_initial_integer_time,
+ * tfl_sync_integer_time); one tfl_step is analytically the same as the five
+ * sub-steps of Algorithm 1.
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns an int: TFL_OK (0) or a negative TFL_E_* code.  The
+ *    message of the last failure on a handle is returned by tfl_last_error()
+ *    and stays valid until the next call on that handle; failures of
+ *    tfl_create are reported by tfl_last_error(NULL).  Handles are not thread
+ *    safe: one host thread per handle at a time.
+ *  - Units are SI.  Fields: E in V/m, H in A/m, Js in A/m^2.  Maps: eps_r
+ *    (dimensionless, > 0), sigma_n in S/m (>= 0), inv_lambda2 = 1/lambda_L^2
+ *    in m^-2 (>= 0; 0 marks a non-superconducting cell, Sec. 3).
+ *  - Layout: every grid array is one component, nz x ny x nx, x fastest,
+ *    contiguous, element index (k*ny + j)*nx + i, in the precision chosen by
+ *    tfl_config.dtype (double for TFL_F64, float for TFL_F32).  Component c of
+ *    E and Js at index (i,j,k) lives on the edge along axis c through node
+ *    (i,j,k) (Ex at (i+1/2, j, k), Ey at (i, j+1/2, k), Ez at (i, j, k+1/2));
+ *    component c of H lives on the face normal to axis c (Hx at
+ *    (i, j+1/2, k+1/2), Hy at (i+1/2, j, k+1/2), Hz at (i+1/2, j+1/2, k)).
+ *    Material maps are per cell (i,j,k), the cell [i,i+1]x[j,j+1]x[k,k+1].
+ *    Indices wrap on every axis.
+ *  - Ownership: the library never allocates device memory.  All device
+ *    buffers (fields, maps, workspace, probe outputs, checkpoints, gradients)
+ *    belong to the caller, are passed as raw device pointers, must be
+ *    256-byte aligned, and must stay alive until tfl_destroy or a re-bind.
+ *    Host structs and arrays passed in are copied during the call.
+ *  - Streams: every call that touches the device takes a hipStream_t passed
+ *    as void* (NULL = the null stream).  Calls are asynchronous on that
+ *    stream except those documented to return host values, which
+ *    synchronise it.
+ *  - No exception crosses the ABI.
+ */
+#ifndef TFL_H
+#define TFL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tfl_sim tfl_sim;
+
+enum {
+    TFL_OK = 0,
+    TFL_E_INVAL = -1,     /* bad argument (size, pointer, value)              */
+    TFL_E_STATE = -2,     /* wrong call order or buffers not bound            */
+    TFL_E_UNSTABLE = -3,  /* dt above the stability bound of the scheme       */
+    TFL_E_NONFINITE = -4, /* NaN or Inf found in the state                     */
+    TFL_E_DEVICE = -5,    /* a HIP runtime error; the message names it        */
+    TFL_E_NOMEM = -6      /* a caller buffer is smaller than required          */
+};
+
+enum { TFL_F64 = 0, TFL_F32 = 1 };
+enum { TFL_PERIODIC = 0, TFL_CPML = 1 };
+enum { TFL_WAVE_SIN = 0, TFL_WAVE_GAUSS = 1, TFL_WAVE_MOD_GAUSS = 2 };
+
+#define TFL_MAX_SOURCES 32
+#define TFL_MAX_PROBES 32
+#define TFL_MAX_FREQS 16
+
+/* Problem statement (Sec. 3): grid, spacing, time step, theta of Algorithm 1
+ * step 3, storage precision and boundaries.
+ *  bc[a]       TFL_PERIODIC or TFL_CPML for axis a (x, y, z).  A CPML axis
+ *              has a PEC wall on node plane 0 (tangential E held at 0), which
+ *              both of its absorbing slabs back onto through the index wrap;
+ *              with zero slab cells it is a bare PEC wall (Sec. 3 lists
+ *              periodic, PEC and PML boundaries).
+ *  pml_lo[a], pml_hi[a]  absorbing cells at the low and high end of a CPML axis.
+ *  pml_order, pml_scale, kappa_max, alpha_max  grading of the convolutional
+ *              PML (Roden and Gedney 2000): sigma(d) = pml_scale *
+ *              0.8 (m+1)/(eta0 dx) * d^m, kappa(d) = 1 + (kappa_max-1) d^m,
+ *              alpha(d) = alpha_max (1-d), d in [0,1] the normalised depth. */
+typedef struct {
+    int64_t nx, ny, nz;
+    double dx, dy, dz;
+    double dt;
+    double theta;        /* in [0.5, 1]; 1 = backward Euler, 0.5 = centred     */
+    int32_t dtype;       /* TFL_F64 or TFL_F32                                */
+    int32_t bc[3];
+    int32_t pml_lo[3], pml_hi[3];
+    double pml_order, pml_scale, kappa_max, alpha_max;
+} tfl_config;
+
+/* Additive ("soft") E source (Sec. 4.1, 4.2, 5): after the E update of step
+ * n -> n+1, E_comp += amplitude * g(t_{n+1}) on every edge of the half-open
+ * index box [i0,i1) x [j0,j1) x [k0,k1), t_{n+1} = (n+1) dt, with
+ * g = sin(2 pi freq t), exp(-(t-t0)^2/(2 tw^2)), or their product. */
+typedef struct {
+    int32_t comp;        /* 0,1,2 = Ex, Ey, Ez                                */
+    int64_t box[6];      /* i0, i1, j0, j1, k0, k1                            */
+    double amplitude;
+    int32_t waveform;    /* TFL_WAVE_*                                        */
+    double freq, t0, tw;
+} tfl_source;
+
+/* Field probe (Sec. 4.2, Sec. 5): s_n = sum of E_comp over the index box at
+ * time level n, accumulated in FP64.  series[n] = s_n for n < capacity (the
+ * sample at the step index where tfl_step first runs, normally n = 0, is
+ * taken then).  For each frequency f_q the running DFT
+ * F_q += s_n * dt * exp(-i 2 pi f_q n dt) is kept in dft[2q], dft[2q+1]
+ * (real, imaginary).  series and dft are caller-owned device FP64 buffers;
+ * either may be NULL when capacity or nfreq is 0.  Calls never read them
+ * back: the caller clears them before a run. */
+typedef struct {
+    int32_t comp;
+    int64_t box[6];
+    double *series;      /* device, FP64 [capacity]                           */
+    int64_t capacity;
+    int32_t nfreq;       /* <= TFL_MAX_FREQS                                  */
+    const double *freqs; /* host, [nfreq], copied                             */
+    double *dft;         /* device, FP64 [2*nfreq]                            */
+} tfl_probe;
+
+/* Create a handle; validates sizes (>= 1), spacings and dt (> 0), theta in
+ * [0.5, 1], dtype, bc and PML cell counts (lo + hi <= n on a CPML axis).
+ * TFL_E_INVAL on bad values. */
+int tfl_create(const tfl_config *cfg, tfl_sim **out);
+int tfl_destroy(tfl_sim *sim);
+const char *tfl_last_error(const tfl_sim *sim);
+
+/* Byte sizes of the caller-owned buffers: the workspace (CPML coefficient
+ * tables and auxiliary variables; 0 when no axis is CPML), a scratch buffer
+ * for reductions, and one saved state (E, H, Js and the workspace). */
+int tfl_buffer_sizes(const tfl_sim *sim, size_t *workspace_bytes, size_t *scratch_bytes, size_t *state_bytes);
+
+/* Bind the nine state arrays (device, dtype, N elements each). */
+int tfl_bind_state(tfl_sim *sim, void *const E[3], void *const H[3], void *const J[3]);
+
+/* Bind the workspace and scratch buffers (sizes from tfl_buffer_sizes).
+ * Uploads the CPML tables and clears the auxiliary variables on `stream`.
+ * workspace may be NULL when its size is 0. */
+int tfl_bind_workspace(tfl_sim *sim, void *workspace, void *scratch, void *stream);
+
+/* Bind the per-cell maps (device, dtype, N elements each).  Validates them
+ * on the device (eps_r > 0, sigma >= 0, inv_lambda2 >= 0, all finite) and
+ * checks dt against the stability bound of the scheme with the London term,
+ * dt_max = 2 / (c0 sqrt(4/dx^2 + 4/dy^2 + 4/dz^2 + max inv_lambda2))
+ * (from the single-mode amplification matrix of Algorithm 1 with eps_r = 1).
+ * Synchronises `stream`.  TFL_E_INVAL on bad values, TFL_E_UNSTABLE when
+ * dt > dt_max.  The per-edge material is formed inside the kernels: an edge
+ * is superconducting when any of the four cells sharing it is (Sec. 3) and
+ * then takes the mean of (eps_r, sigma, inv_lambda2) over those cells;
+ * otherwise it takes the mean of (eps_r, sigma) over all four. */
+int tfl_bind_materials(tfl_sim *sim, const void *eps_r, const void *sigma_n, const void *inv_lambda2, void *stream);
+
+/* The bound H and Js hold integer-time values H^0, Js^0 (E holds E^0):
+ * replace them with H^{-1/2} and Js^{-1/2} by running the first half
+ * updates of Algorithm 1 (steps 1 and 2) backwards, and reset the step
+ * index to 0 and the CPML auxiliary variables to 0. */
+int tfl_set_initial_integer_time(tfl_sim *sim, void *stream);
+
+/* Register a source or a probe; *id receives its index.  Boxes must lie in
+ * the grid; at most TFL_MAX_SOURCES / TFL_MAX_PROBES per handle. */
+int tfl_add_source(tfl_sim *sim, const tfl_source *src, int *id);
+int tfl_add_probe(tfl_sim *sim, const tfl_probe *probe, int *id);
+int tfl_clear_sources_probes(tfl_sim *sim);
+
+/* Advance nsteps >= 0 time steps (Algorithm 1), with sources and probes. */
+int tfl_step(tfl_sim *sim, int64_t nsteps, void *stream);
+
+/* tfl_step with HIP events recorded on `stream` around each pass of every
+ * step; returns the summed device time of the H passes and of the E passes
+ * (the latter including the source and probe launches that follow them) in
+ * milliseconds.  Synchronises `stream`.  For measurement only. */
+int tfl_profile_step(tfl_sim *sim, int64_t nsteps, void *stream, double *h_ms, double *e_ms);
+
+/* Integer-time values at the current step n (Algorithm 1 steps 1 and 2 of
+ * the next step read as the end of this one): H^n = H^{n-1/2} - dt/(2 mu0)
+ * curl E^n and Js^n = Js^{n-1/2} + dt/2 inv_lambda2 E^n / mu0 on
+ * superconducting edges (0 elsewhere), written to caller buffers (device,
+ * dtype, N elements each; Hn or Jn may be NULL to skip).  The state is not
+ * modified. */
+int tfl_sync_integer_time(tfl_sim *sim, void *const Hn[3], void *const Jn[3], void *stream);
+
+/* Discrete energy W^n = dV [sum_e eps_e E_e^2/2 + sum_f mu0 H^{n-1/2}_f H^{n+1/2}_f/2
+ * + sum_{SC e} mu0 Js^{n-1/2}_e Js^{n+1/2}_e/(2 inv_lambda2_e)] in FP64 (the
+ * quantity the lossless leap-frog conserves exactly on periodic grids;
+ * H^{n+1/2}, Js^{n+1/2} formed on the fly without PML stretching), and the
+ * number of non-finite values in E, H and Js.  Synchronises `stream`. */
+int tfl_energy(tfl_sim *sim, double *energy, int64_t *nonfinite, void *stream);
+
+/* Step index n (the state is at E^n) and its override (for restarts). */
+int tfl_get_step(const tfl_sim *sim, int64_t *step);
+int tfl_set_step(tfl_sim *sim, int64_t step);
+
+/* Copy the state (E, H, Js, workspace) to / from a caller device buffer of
+ * state_bytes (tfl_buffer_sizes).  The step index is not part of the copy. */
+int tfl_save_state(tfl_sim *sim, void *dst, void *stream);
+int tfl_load_state(tfl_sim *sim, const void *src, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFL_H */

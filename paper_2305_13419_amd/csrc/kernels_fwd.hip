@@ -1,0 +1,693 @@
+// Forward kernels of the two-fluid FDTD step for gfx950.
+//
+// One time step (Algorithm 1, steps 1-5 of step n-1 fused with steps 1-2 of
+// step n, Sec. 3) is two HBM-bound sweeps:
+//   H pass:   H^{n+1/2} = H^{n-1/2} - dt/mu0 curl E^n                (Faraday)
+//   E pass:   Js^{n+1/2} = Js^{n-1/2} + dt ell_e/mu0 E^n              (London)
+//             E^{n+1} = a_e E^n + b_e (curl H^{n+1/2} - Js^{n+1/2})     (Ampere, theta scheme)
+// with a_e = (eps_e - (1-theta) sigma_e dt)/(eps_e + theta sigma_e dt) and
+// b_e = dt/(eps_e + theta sigma_e dt), i.e. Algorithm 1 step 3 multiplied out.
+// Per-edge materials are formed on the fly from the per-cell maps.
+//
+// Each block owns a 64 x 4 column tile of the x-y plane and marches 32
+// planes along z, so the z neighbour of every stencil comes from registers
+// and each word of a sweep is read from HBM once; x and y neighbours hit
+// L1/L2.  Blocks are renumbered so that each XCD (blocks are dealt to the 8
+// XCDs round robin) receives a contiguous range of tiles, keeping the halo
+// rows of neighbouring tiles in the same L2.
+#include "tfl_internal.h"
+
+namespace tfl {
+namespace {
+
+__device__ __forceinline__ int logical_block(int b, int nblocks)
+{
+    const int q = nblocks >> 3, r = nblocks & 7;
+    const int x = b & 7, m = b >> 3;
+    return x * q + min(x, r) + m;
+}
+
+__device__ __forceinline__ int slab_slot(int i, int lo, int hi, int n)
+{
+    if (i < lo) return i;
+    if (i >= n - hi) return lo + i - (n - hi);
+    return -1;
+}
+
+template <typename T>
+__device__ __forceinline__ T inv_count(int c)
+{
+    return c == 1 ? T(1) : (c == 2 ? T(0.5) : (c == 3 ? T(1) / T(3) : T(0.25)));
+}
+
+// Per-edge material of the four cells q0..q3 sharing an edge (Sec. 3): if any
+// cell is superconducting (ell > 0) the edge takes the mean over those cells,
+// otherwise the mean over all four.  Summed in q order.
+template <typename T>
+__device__ __forceinline__ void edge_material(const T e[4], const T s[4], const T l[4], T &eps, T &sig, T &ell)
+{
+    const bool anysc = (l[0] > T(0)) | (l[1] > T(0)) | (l[2] > T(0)) | (l[3] > T(0));
+    T se = T(0), ss = T(0), sl = T(0);
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool use = !anysc || (l[q] > T(0));
+        se += use ? e[q] : T(0);
+        ss += use ? s[q] : T(0);
+        sl += use ? l[q] : T(0);
+        cnt += use ? 1 : 0;
+    }
+    const T ic = inv_count<T>(cnt);
+    eps = T(kEps0) * (se * ic);
+    sig = ss * ic;
+    ell = sl * ic;
+}
+
+// Stretched derivative: d <- kappa^-1 d + psi, psi <- b psi + c d.
+template <typename T>
+__device__ __forceinline__ T stretch(T d, T *psi, long long pidx, T b, T c, T kinv)
+{
+    const T p = b * psi[pidx] + c * d;
+    psi[pidx] = p;
+    return kinv * d + p;
+}
+
+template <typename T>
+__device__ __forceinline__ T stretch_virtual(T d, const T *psi, long long pidx, T b, T c, T kinv)
+{
+    const T p = b * psi[pidx] + c * d;
+    return kinv * d + p;
+}
+
+// ---------------------------------------------------------------------------
+// H pass (Faraday's law)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kTileX *kTileY) void h_pass_kernel(const StepArgs<T> a)
+{
+    const int nb = a.ntiles_x * a.ntiles_y * a.ntiles_z;
+    const int t = logical_block(blockIdx.x, nb);
+    const int tx = t % a.ntiles_x;
+    const int tr = t / a.ntiles_x;
+    const int ty = tr % a.ntiles_y;
+    const int tz = tr / a.ntiles_y;
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const int i = tx * kTileX + threadIdx.x;
+    const int j = ty * kTileY + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    const int k0 = tz * kTileZ;
+    const int k1 = min(k0 + kTileZ, nz);
+    const long long sxy = a.g.sxy;
+    const int ip = (i + 1 == nx) ? 0 : i + 1;
+    const int jp = (j + 1 == ny) ? 0 : j + 1;
+    const long long r0 = (long long)j * nx, r1 = (long long)jp * nx;
+    const T *__restrict__ Ex = a.E[0];
+    const T *__restrict__ Ey = a.E[1];
+    const T *__restrict__ Ez = a.E[2];
+    T *__restrict__ Hx = a.H[0];
+    T *__restrict__ Hy = a.H[1];
+    T *__restrict__ Hz = a.H[2];
+    const T rdx = a.rd[0], rdy = a.rd[1], rdz = a.rd[2], hdt = a.hdt;
+    const PmlAxis<T> &px = a.pml[0], &py = a.pml[1], &pz = a.pml[2];
+    const int sx = px.on ? slab_slot(i, px.lo, px.hi, nx) : -1;
+    const int sy = py.on ? slab_slot(j, py.lo, py.hi, ny) : -1;
+
+    T exk = Ex[(long long)k0 * sxy + r0 + i];
+    T eyk = Ey[(long long)k0 * sxy + r0 + i];
+    for (int k = k0; k < k1; ++k) {
+        const int kp = (k + 1 == nz) ? 0 : k + 1;
+        const long long b0 = (long long)k * sxy, b1 = (long long)kp * sxy;
+        const long long c = b0 + r0 + i;
+        const T exk1 = Ex[b1 + r0 + i];
+        const T eyk1 = Ey[b1 + r0 + i];
+        const T ez = Ez[c];
+        const T ez_x = Ez[b0 + r0 + ip];
+        const T ez_y = Ez[b0 + r1 + i];
+        const T ey_x = Ey[b0 + r0 + ip];
+        const T ex_y = Ex[b0 + r1 + i];
+        T dyEz = (ez_y - ez) * rdy, dzEy = (eyk1 - eyk) * rdz;  // Hx
+        T dzEx = (exk1 - exk) * rdz, dxEz = (ez_x - ez) * rdx;  // Hy
+        T dxEy = (ey_x - eyk) * rdx, dyEx = (ex_y - exk) * rdy; // Hz
+        if (sx >= 0) {
+            const long long p = ((long long)k * ny + j) * px.P + sx;
+            dxEz = stretch(dxEz, px.psiH[0], p, px.bh[i], px.ch[i], px.kh[i]);  // Hy
+            dxEy = stretch(dxEy, px.psiH[1], p, px.bh[i], px.ch[i], px.kh[i]);  // Hz
+        }
+        if (sy >= 0) {
+            const long long p = ((long long)k * py.P + sy) * nx + i;
+            dyEx = stretch(dyEx, py.psiH[0], p, py.bh[j], py.ch[j], py.kh[j]);  // Hz
+            dyEz = stretch(dyEz, py.psiH[1], p, py.bh[j], py.ch[j], py.kh[j]);  // Hx
+        }
+        if (pz.on) {
+            const int sz = slab_slot(k, pz.lo, pz.hi, nz);
+            if (sz >= 0) {
+                const long long p = ((long long)sz * ny + j) * nx + i;
+                dzEy = stretch(dzEy, pz.psiH[0], p, pz.bh[k], pz.ch[k], pz.kh[k]);  // Hx
+                dzEx = stretch(dzEx, pz.psiH[1], p, pz.bh[k], pz.ch[k], pz.kh[k]);  // Hy
+            }
+        }
+        Hx[c] = Hx[c] - hdt * (dyEz - dzEy);
+        Hy[c] = Hy[c] - hdt * (dzEx - dxEz);
+        Hz[c] = Hz[c] - hdt * (dxEy - dyEx);
+        exk = exk1;
+        eyk = eyk1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// E pass (London supercurrent + Ampere's law with the theta-weighted Ohmic term)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void update_edge(T *__restrict__ E, T *__restrict__ J, long long c, T curl,
+                                            const T e[4], const T s[4], const T l[4], T dt, T theta, T hdt,
+                                            bool wall)
+{
+    T eps, sig, ell;
+    edge_material(e, s, l, eps, sig, ell);
+    const T sdt = sig * dt;
+    const T inv = T(1) / (eps + theta * sdt);
+    const T ca = (eps - (T(1) - theta) * sdt) * inv;
+    const T cb = dt * inv;
+    const T E0 = E[c];
+    T Jn = T(0);
+    if (ell > T(0)) {
+        Jn = J[c] + hdt * ell * E0;
+        J[c] = Jn;
+    }
+    const T En = ca * E0 + cb * (curl - Jn);
+    E[c] = wall ? T(0) : En;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTileX *kTileY) void e_pass_kernel(const StepArgs<T> a)
+{
+    const int nb = a.ntiles_x * a.ntiles_y * a.ntiles_z;
+    const int t = logical_block(blockIdx.x, nb);
+    const int tx = t % a.ntiles_x;
+    const int tr = t / a.ntiles_x;
+    const int ty = tr % a.ntiles_y;
+    const int tz = tr / a.ntiles_y;
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const int i = tx * kTileX + threadIdx.x;
+    const int j = ty * kTileY + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    const int k0 = tz * kTileZ;
+    const int k1 = min(k0 + kTileZ, nz);
+    const long long sxy = a.g.sxy;
+    const int im = (i == 0) ? nx - 1 : i - 1;
+    const int jm = (j == 0) ? ny - 1 : j - 1;
+    const long long r0 = (long long)j * nx, rm = (long long)jm * nx;
+    T *__restrict__ Ex = a.E[0];
+    T *__restrict__ Ey = a.E[1];
+    T *__restrict__ Ez = a.E[2];
+    T *__restrict__ Jx = a.J[0];
+    T *__restrict__ Jy = a.J[1];
+    T *__restrict__ Jz = a.J[2];
+    const T *__restrict__ Hx = a.H[0];
+    const T *__restrict__ Hy = a.H[1];
+    const T *__restrict__ Hz = a.H[2];
+    const T *__restrict__ meps = a.eps;
+    const T *__restrict__ msig = a.sig;
+    const T *__restrict__ mell = a.ell;
+    const T rdx = a.rd[0], rdy = a.rd[1], rdz = a.rd[2];
+    const T dt = a.dt, theta = a.theta, hdt = a.hdt;
+    const PmlAxis<T> &px = a.pml[0], &py = a.pml[1], &pz = a.pml[2];
+    const int sx = px.on ? slab_slot(i, px.lo, px.hi, nx) : -1;
+    const int sy = py.on ? slab_slot(j, py.lo, py.hi, ny) : -1;
+    const bool wall_x = px.on && i == 0;
+    const bool wall_y = py.on && j == 0;
+
+    // plane k-1: H and the maps of cells (i,j), (i-1,j), (i,j-1)
+    const int km0 = (k0 == 0) ? nz - 1 : k0 - 1;
+    const long long bm = (long long)km0 * sxy;
+    T hx_km = Hx[bm + r0 + i], hy_km = Hy[bm + r0 + i];
+    T pe00 = meps[bm + r0 + i], pe10 = meps[bm + r0 + im], pe01 = meps[bm + rm + i];
+    T ps00 = msig[bm + r0 + i], ps10 = msig[bm + r0 + im], ps01 = msig[bm + rm + i];
+    T pl00 = mell[bm + r0 + i], pl10 = mell[bm + r0 + im], pl01 = mell[bm + rm + i];
+
+    for (int k = k0; k < k1; ++k) {
+        const long long b0 = (long long)k * sxy;
+        const long long c = b0 + r0 + i;
+        const long long cxm = b0 + r0 + im, cym = b0 + rm + i, cxym = b0 + rm + im;
+        const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
+        const T hz_xm = Hz[cxm], hz_ym = Hz[cym];
+        const T hy_xm = Hy[cxm], hx_ym = Hx[cym];
+        T dyHz = (hz - hz_ym) * rdy, dzHy = (hy - hy_km) * rdz;  // Ex
+        T dzHx = (hx - hx_km) * rdz, dxHz = (hz - hz_xm) * rdx;  // Ey
+        T dxHy = (hy - hy_xm) * rdx, dyHx = (hx - hx_ym) * rdy;  // Ez
+        if (sx >= 0) {
+            const long long p = ((long long)k * ny + j) * px.P + sx;
+            dxHz = stretch(dxHz, px.psiE[0], p, px.bn[i], px.cn[i], px.kn[i]);  // Ey
+            dxHy = stretch(dxHy, px.psiE[1], p, px.bn[i], px.cn[i], px.kn[i]);  // Ez
+        }
+        if (sy >= 0) {
+            const long long p = ((long long)k * py.P + sy) * nx + i;
+            dyHx = stretch(dyHx, py.psiE[0], p, py.bn[j], py.cn[j], py.kn[j]);  // Ez
+            dyHz = stretch(dyHz, py.psiE[1], p, py.bn[j], py.cn[j], py.kn[j]);  // Ex
+        }
+        bool wall_z = false;
+        if (pz.on) {
+            wall_z = (k == 0);
+            const int sz = slab_slot(k, pz.lo, pz.hi, nz);
+            if (sz >= 0) {
+                const long long p = ((long long)sz * ny + j) * nx + i;
+                dzHy = stretch(dzHy, pz.psiE[0], p, pz.bn[k], pz.cn[k], pz.kn[k]);  // Ex
+                dzHx = stretch(dzHx, pz.psiE[1], p, pz.bn[k], pz.cn[k], pz.kn[k]);  // Ey
+            }
+        }
+        const T e00 = meps[c], e10 = meps[cxm], e01 = meps[cym], e11 = meps[cxym];
+        const T s00 = msig[c], s10 = msig[cxm], s01 = msig[cym], s11 = msig[cxym];
+        const T l00 = mell[c], l10 = mell[cxm], l01 = mell[cym], l11 = mell[cxym];
+        {   // Ex: cells (j,k), (j,k-1), (j-1,k), (j-1,k-1)
+            const T e[4] = {e00, pe00, e01, pe01}, s[4] = {s00, ps00, s01, ps01}, l[4] = {l00, pl00, l01, pl01};
+            update_edge(Ex, Jx, c, dyHz - dzHy, e, s, l, dt, theta, hdt, wall_y || wall_z);
+        }
+        {   // Ey: cells (k,i), (k,i-1), (k-1,i), (k-1,i-1)
+            const T e[4] = {e00, e10, pe00, pe10}, s[4] = {s00, s10, ps00, ps10}, l[4] = {l00, l10, pl00, pl10};
+            update_edge(Ey, Jy, c, dzHx - dxHz, e, s, l, dt, theta, hdt, wall_z || wall_x);
+        }
+        {   // Ez: cells (i,j), (i,j-1), (i-1,j), (i-1,j-1)
+            const T e[4] = {e00, e01, e10, e11}, s[4] = {s00, s01, s10, s11}, l[4] = {l00, l01, l10, l11};
+            update_edge(Ez, Jz, c, dxHy - dyHx, e, s, l, dt, theta, hdt, wall_x || wall_y);
+        }
+        hx_km = hx;
+        hy_km = hy;
+        pe00 = e00; pe10 = e10; pe01 = e01;
+        ps00 = s00; ps10 = s10; ps01 = s01;
+        pl00 = l00; pl10 = l10; pl01 = l01;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Soft sources and probes
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double waveform(int wave, double f, double t0, double tw, double t)
+{
+    if (wave == TFL_WAVE_SIN) return sin(kTwoPi * f * t);
+    const double g = exp(-(t - t0) * (t - t0) / (2.0 * tw * tw));
+    return wave == TFL_WAVE_GAUSS ? g : g * sin(kTwoPi * f * t);
+}
+
+template <typename T>
+__global__ void source_kernel(const SrcArgs<T> a, int q)
+{
+    const SourceDesc &s = a.src[q];
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= s.count) return;
+    const int wx = s.i1 - s.i0, wy = s.j1 - s.j0;
+    const int i = s.i0 + (int)(idx % wx);
+    const long long r = idx / wx;
+    const int j = s.j0 + (int)(r % wy);
+    const int k = s.k0 + (int)(r / wy);
+    const double g = s.amp * waveform(s.wave, s.f, s.t0, s.tw, a.t);
+    T *E = a.E[s.comp];
+    const long long c = ((long long)k * a.g.ny + j) * a.g.nx + i;
+    E[c] = (T)((double)E[c] + g);
+}
+
+constexpr int kProbeThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kProbeThreads) void probe_kernel(const ProbeArgs<T> a)
+{
+    const ProbeDesc &p = a.p[blockIdx.x];
+    const T *E = a.E[p.comp];
+    const int wx = p.i1 - p.i0, wy = p.j1 - p.j0, wz = p.k1 - p.k0;
+    const long long cnt = (long long)wx * wy * wz;
+    double acc = 0.0;
+    for (long long idx = threadIdx.x; idx < cnt; idx += kProbeThreads) {
+        const int i = p.i0 + (int)(idx % wx);
+        const long long r = idx / wx;
+        const int j = p.j0 + (int)(r % wy);
+        const int k = p.k0 + (int)(r / wy);
+        acc += (double)E[((long long)k * a.g.ny + j) * a.g.nx + i];
+    }
+    // wave64 reduction, then across the block's waves through LDS
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    __shared__ double part[kProbeThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) part[wv] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kProbeThreads / 64; ++w) s += part[w];
+        part[0] = s;
+    }
+    __syncthreads();
+    const double s = part[0];
+    if (threadIdx.x == 0 && p.series != nullptr && a.n < p.cap) p.series[a.n] = s;
+    if ((int)threadIdx.x < p.nfreq) {
+        const int f = threadIdx.x;
+        const double ph = kTwoPi * p.freq[f] * (double)a.n * a.dt;
+        p.dft[2 * f] += s * a.dt * cos(ph);
+        p.dft[2 * f + 1] -= s * a.dt * sin(ph);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Integer-time half kick (Algorithm 1 steps 1 and 2 as half steps)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct CellMaps {
+    T e[3][4], s[3][4], l[3][4];
+};
+
+// Gather the four cells of each of the three edges of cell index (i,j,k), in
+// the q order used by the E pass.
+template <typename T>
+__device__ __forceinline__ void gather_edge_cells(const StepArgs<T> &a, int i, int j, int k, T em[3], T sm[3],
+                                                  T lm[3])
+{
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const int im = (i == 0) ? nx - 1 : i - 1;
+    const int jm = (j == 0) ? ny - 1 : j - 1;
+    const int km = (k == 0) ? nz - 1 : k - 1;
+    auto id = [&](int ii, int jj, int kk) { return ((long long)kk * ny + jj) * nx + ii; };
+    const long long c00 = id(i, j, k), c10 = id(im, j, k), c01 = id(i, jm, k), c11 = id(im, jm, k);
+    const long long p00 = id(i, j, km), p10 = id(im, j, km), p01 = id(i, jm, km);
+    const long long ex[4] = {c00, p00, c01, p01};
+    const long long ey[4] = {c00, c10, p00, p10};
+    const long long ez[4] = {c00, c01, c10, c11};
+    const long long *cells[3] = {ex, ey, ez};
+    for (int comp = 0; comp < 3; ++comp) {
+        T e[4], s[4], l[4];
+        for (int q = 0; q < 4; ++q) {
+            e[q] = a.eps[cells[comp][q]];
+            s[q] = a.sig[cells[comp][q]];
+            l[q] = a.ell[cells[comp][q]];
+        }
+        edge_material(e, s, l, em[comp], sm[comp], lm[comp]);
+    }
+}
+
+template <typename T>
+__global__ void half_kick_kernel(const StepArgs<T> a, T sgn, T *Hx_o, T *Hy_o, T *Hz_o, T *Jx_o, T *Jy_o, T *Jz_o)
+{
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const long long N = a.g.sxy * nz;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx);
+        const long long r = c / nx;
+        const int j = (int)(r % ny);
+        const int k = (int)(r / ny);
+        const int ip = (i + 1 == nx) ? 0 : i + 1;
+        const int jp = (j + 1 == ny) ? 0 : j + 1;
+        const int kp = (k + 1 == nz) ? 0 : k + 1;
+        auto id = [&](int ii, int jj, int kk) { return ((long long)kk * ny + jj) * nx + ii; };
+        const T *Ex = a.E[0], *Ey = a.E[1], *Ez = a.E[2];
+        T dyEz = (Ez[id(i, jp, k)] - Ez[c]) * a.rd[1], dzEy = (Ey[id(i, j, kp)] - Ey[c]) * a.rd[2];
+        T dzEx = (Ex[id(i, j, kp)] - Ex[c]) * a.rd[2], dxEz = (Ez[id(ip, j, k)] - Ez[c]) * a.rd[0];
+        T dxEy = (Ey[id(ip, j, k)] - Ey[c]) * a.rd[0], dyEx = (Ex[id(i, jp, k)] - Ex[c]) * a.rd[1];
+        const PmlAxis<T> &px = a.pml[0], &py = a.pml[1], &pz = a.pml[2];
+        if (px.on) {
+            const int sx = slab_slot(i, px.lo, px.hi, nx);
+            if (sx >= 0) {
+                const long long p = ((long long)k * ny + j) * px.P + sx;
+                dxEz = stretch_virtual(dxEz, px.psiH[0], p, px.bh[i], px.ch[i], px.kh[i]);
+                dxEy = stretch_virtual(dxEy, px.psiH[1], p, px.bh[i], px.ch[i], px.kh[i]);
+            }
+        }
+        if (py.on) {
+            const int sy = slab_slot(j, py.lo, py.hi, ny);
+            if (sy >= 0) {
+                const long long p = ((long long)k * py.P + sy) * nx + i;
+                dyEx = stretch_virtual(dyEx, py.psiH[0], p, py.bh[j], py.ch[j], py.kh[j]);
+                dyEz = stretch_virtual(dyEz, py.psiH[1], p, py.bh[j], py.ch[j], py.kh[j]);
+            }
+        }
+        if (pz.on) {
+            const int sz = slab_slot(k, pz.lo, pz.hi, nz);
+            if (sz >= 0) {
+                const long long p = ((long long)sz * ny + j) * nx + i;
+                dzEy = stretch_virtual(dzEy, pz.psiH[0], p, pz.bh[k], pz.ch[k], pz.kh[k]);
+                dzEx = stretch_virtual(dzEx, pz.psiH[1], p, pz.bh[k], pz.ch[k], pz.kh[k]);
+            }
+        }
+        const T hh = T(0.5) * a.hdt * sgn;
+        T *Ho[3] = {Hx_o, Hy_o, Hz_o};
+        const T curl[3] = {dyEz - dzEy, dzEx - dxEz, dxEy - dyEx};
+        if (Hx_o != nullptr)
+            for (int comp = 0; comp < 3; ++comp) Ho[comp][c] = a.H[comp][c] + hh * curl[comp];
+        if (Jx_o != nullptr) {
+            T em[3], sm[3], lm[3];
+            gather_edge_cells(a, i, j, k, em, sm, lm);
+            T *Jo[3] = {Jx_o, Jy_o, Jz_o};
+            for (int comp = 0; comp < 3; ++comp)
+                Jo[comp][c] = (lm[comp] > T(0)) ? a.J[comp][c] - hh * lm[comp] * a.E[comp][c] : T(0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Energy functional and finite check (FP64 accumulation)
+// ---------------------------------------------------------------------------
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kRedThreads / 64; ++w) s += lds[w];
+    return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void energy_kernel(const StepArgs<T> a, double *part)
+{
+    __shared__ double lds[kRedThreads / 64];
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const long long N = a.g.sxy * nz;
+    double we = 0.0, wh = 0.0, wj = 0.0, bad = 0.0;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx);
+        const long long r = c / nx;
+        const int j = (int)(r % ny);
+        const int k = (int)(r / ny);
+        const int ip = (i + 1 == nx) ? 0 : i + 1;
+        const int jp = (j + 1 == ny) ? 0 : j + 1;
+        const int kp = (k + 1 == nz) ? 0 : k + 1;
+        auto id = [&](int ii, int jj, int kk) { return ((long long)kk * ny + jj) * nx + ii; };
+        const double E0 = (double)a.E[0][c], E1 = (double)a.E[1][c], E2 = (double)a.E[2][c];
+        const double rdx = (double)a.rd[0], rdy = (double)a.rd[1], rdz = (double)a.rd[2];
+        const double cx = ((double)a.E[2][id(i, jp, k)] - E2) * rdy - ((double)a.E[1][id(i, j, kp)] - E1) * rdz;
+        const double cy = ((double)a.E[0][id(i, j, kp)] - E0) * rdz - ((double)a.E[2][id(ip, j, k)] - E2) * rdx;
+        const double cz = ((double)a.E[1][id(ip, j, k)] - E1) * rdx - ((double)a.E[0][id(i, jp, k)] - E0) * rdy;
+        const double hdt = (double)a.dt / kMu0;
+        const double H[3] = {(double)a.H[0][c], (double)a.H[1][c], (double)a.H[2][c]};
+        const double cu[3] = {cx, cy, cz};
+        for (int comp = 0; comp < 3; ++comp) wh += 0.5 * kMu0 * H[comp] * (H[comp] - hdt * cu[comp]);
+        T em[3], sm[3], lm[3];
+        gather_edge_cells(a, i, j, k, em, sm, lm);
+        const double Ev[3] = {E0, E1, E2};
+        for (int comp = 0; comp < 3; ++comp) {
+            we += 0.5 * (double)em[comp] * Ev[comp] * Ev[comp];
+            if (lm[comp] > T(0)) {
+                const double Jv = (double)a.J[comp][c];
+                const double Jp = Jv + hdt * (double)lm[comp] * Ev[comp];
+                wj += 0.5 * kMu0 * Jv * Jp / (double)lm[comp];
+            }
+            const double hv = H[comp], jv = (double)a.J[comp][c];
+            bad += (isfinite(Ev[comp]) ? 0.0 : 1.0) + (isfinite(hv) ? 0.0 : 1.0) + (isfinite(jv) ? 0.0 : 1.0);
+        }
+    }
+    const double dV = 1.0 / ((double)a.rd[0] * (double)a.rd[1] * (double)a.rd[2]);
+    const double w = block_sum(dV * (we + wh + wj), lds);
+    const double nb = block_sum(bad, lds);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = w;
+        part[2 * blockIdx.x + 1] = nb;
+    }
+}
+
+// Second stage: one block folds nblocks pairs into scratch[0..1] in a fixed order.
+__global__ __launch_bounds__(kRedThreads) void fold_pairs_kernel(double *part, int nblocks, int op_min_max)
+{
+    __shared__ double lds[kRedThreads / 64];
+    (void)op_min_max;
+    double a0 = 0.0, a1 = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kRedThreads) {
+        a0 += part[2 * b];
+        a1 += part[2 * b + 1];
+    }
+    const double s0 = block_sum(a0, lds);
+    const double s1 = block_sum(a1, lds);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[0] = s0;
+        part[1] = s1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Material map statistics (validation and the stability bound)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_min(double v, double *lds)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off, 64));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wv] = v;
+    __syncthreads();
+    double s = lds[0];
+    if (threadIdx.x == 0)
+        for (int w = 1; w < kRedThreads / 64; ++w) s = fmin(s, lds[w]);
+    return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void map_stats_kernel(const T *eps, const T *sig, const T *ell, long long n,
+                                                                double *part)
+{
+    __shared__ double lds[kRedThreads / 64];
+    double me = INFINITY, ms = INFINITY, ml = INFINITY, nl = INFINITY, bad = 0.0;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (long long)gridDim.x * blockDim.x) {
+        const double e = (double)eps[c], s = (double)sig[c], l = (double)ell[c];
+        me = fmin(me, e);
+        ms = fmin(ms, s);
+        ml = fmin(ml, l);
+        nl = fmin(nl, -l);
+        bad += (isfinite(e) && isfinite(s) && isfinite(l)) ? 0.0 : 1.0;
+    }
+    const double r0 = block_min(me, lds);
+    const double r1 = block_min(ms, lds);
+    const double r2 = block_min(ml, lds);
+    const double r3 = block_min(nl, lds);
+    const double r4 = block_sum(bad, lds);
+    if (threadIdx.x == 0) {
+        double *o = part + 5 * (size_t)blockIdx.x;
+        o[0] = r0; o[1] = r1; o[2] = r2; o[3] = r3; o[4] = r4;
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void map_stats_fold_kernel(double *part, int nblocks)
+{
+    __shared__ double lds[kRedThreads / 64];
+    double v[5] = {INFINITY, INFINITY, INFINITY, INFINITY, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += kRedThreads) {
+        for (int q = 0; q < 4; ++q) v[q] = fmin(v[q], part[5 * b + q]);
+        v[4] += part[5 * b + 4];
+    }
+    double r[5];
+    for (int q = 0; q < 4; ++q) r[q] = block_min(v[q], lds);
+    r[4] = block_sum(v[4], lds);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 5; ++q) part[q] = r[q];
+}
+
+__global__ void fill_zero_kernel(uint32_t *p, size_t nwords)
+{
+    for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += (size_t)gridDim.x * blockDim.x)
+        p[w] = 0u;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_h_pass(const StepArgs<T> &a, hipStream_t s)
+{
+    const int nb = a.ntiles_x * a.ntiles_y * a.ntiles_z;
+    hipLaunchKernelGGL(h_pass_kernel<T>, dim3(nb), dim3(kTileX, kTileY), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t s)
+{
+    const int nb = a.ntiles_x * a.ntiles_y * a.ntiles_z;
+    hipLaunchKernelGGL(e_pass_kernel<T>, dim3(nb), dim3(kTileX, kTileY), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sources(const SrcArgs<T> &a, hipStream_t s)
+{
+    for (int q = 0; q < a.nsrc; ++q) {
+        const long long cnt = a.src[q].count;
+        if (cnt <= 0) continue;
+        const int nb = (int)((cnt + 255) / 256);
+        hipLaunchKernelGGL(source_kernel<T>, dim3(nb), dim3(256), 0, s, a, q);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_probes(const ProbeArgs<T> &a, int nprobe, hipStream_t s)
+{
+    if (nprobe <= 0) return hipSuccess;
+    hipLaunchKernelGGL(probe_kernel<T>, dim3(nprobe), dim3(kProbeThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_half_kick(const StepArgs<T> &a, T sgn, T *const Hout[3], T *const Jout[3], hipStream_t s)
+{
+    const long long N = a.g.sxy * a.g.nz;
+    const long long nbl = (N + 255) / 256;
+    const int nb = (int)(nbl < 65536 ? nbl : 65536);
+    hipLaunchKernelGGL(half_kick_kernel<T>, dim3(nb), dim3(256), 0, s, a, sgn, Hout ? Hout[0] : nullptr,
+                       Hout ? Hout[1] : nullptr, Hout ? Hout[2] : nullptr, Jout ? Jout[0] : nullptr,
+                       Jout ? Jout[1] : nullptr, Jout ? Jout[2] : nullptr);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_energy(const StepArgs<T> &a, double *scratch, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(energy_kernel<T>, dim3(nblocks), dim3(kRedThreads), 0, s, a, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fold_pairs_kernel, dim3(1), dim3(kRedThreads), 0, s, scratch, nblocks, 0);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_map_stats(const T *eps, const T *sig, const T *ell, long long n, double *scratch, int nblocks,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(map_stats_kernel<T>, dim3(nblocks), dim3(kRedThreads), 0, s, eps, sig, ell, n, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(map_stats_fold_kernel, dim3(1), dim3(kRedThreads), 0, s, scratch, nblocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    const size_t nw = bytes / 4;
+    const size_t nbl = (nw + 255) / 256;
+    const int nb = (int)(nbl < 16384 ? nbl : 16384);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(nb), dim3(256), 0, s, (uint32_t *)p, nw);
+    return hipGetLastError();
+}
+
+#define TFL_INSTANTIATE(T)                                                                                  \
+    template hipError_t launch_h_pass<T>(const StepArgs<T> &, hipStream_t);                                 \
+    template hipError_t launch_e_pass<T>(const StepArgs<T> &, hipStream_t);                                 \
+    template hipError_t launch_sources<T>(const SrcArgs<T> &, hipStream_t);                                 \
+    template hipError_t launch_probes<T>(const ProbeArgs<T> &, int, hipStream_t);                           \
+    template hipError_t launch_half_kick<T>(const StepArgs<T> &, T, T *const[3], T *const[3], hipStream_t); \
+    template hipError_t launch_energy<T>(const StepArgs<T> &, double *, int, hipStream_t);                  \
+    template hipError_t launch_map_stats<T>(const T *, const T *, const T *, long long, double *, int, hipStream_t);
+
+TFL_INSTANTIATE(double)
+TFL_INSTANTIATE(float)
+
+}  // namespace tfl

@@ -1,0 +1,117 @@
+// Internal types shared by the host driver (api.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tfl.h"
+
+namespace tfl {
+
+constexpr double kEps0 = 8.8541878128e-12;  // F/m (CODATA 2018)
+constexpr double kMu0 = 1.25663706212e-6;   // H/m (CODATA 2018)
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Tile of the 2.5-D sweeps: a block covers kTileX x kTileY columns of the
+// x-y plane and marches kTileZ planes along z, keeping the z neighbour in
+// registers.  kTileX is one 64-wide wavefront.
+constexpr int kTileX = 64;
+constexpr int kTileY = 4;
+constexpr int kTileZ = 32;
+
+struct GridDims {
+    int nx, ny, nz;
+    long long sxy;  // nx * ny
+};
+
+// One axis of the convolutional PML.  Coefficient tables are indexed by the
+// node index i (integer positions, E side) or by i for the half position
+// i + 1/2 (H side).  Auxiliary variables are stored only in the absorbing
+// slabs; slot(i) maps a cell index to its slab column.
+template <typename T>
+struct PmlAxis {
+    int on;     // axis is CPML
+    int lo, hi; // slab cells
+    int P;      // lo + hi
+    int n;
+    const T *bn, *cn, *kn;  // node tables
+    const T *bh, *ch, *kh;  // half-node tables
+    T *psiH[2];             // H-side variables (two components)
+    T *psiE[2];             // E-side variables (two components)
+};
+
+template <typename T>
+struct StepArgs {
+    GridDims g;
+    T *E[3];
+    T *H[3];
+    T *J[3];
+    const T *eps, *sig, *ell;  // per-cell maps
+    T rd[3];                   // 1/dx, 1/dy, 1/dz
+    T hdt;                     // dt / mu0
+    T dt;
+    T theta;
+    T eps0dt;                  // unused slot kept for alignment
+    PmlAxis<T> pml[3];
+    int ntiles_x, ntiles_y, ntiles_z;
+};
+
+struct SourceDesc {
+    int comp;
+    int i0, i1, j0, j1, k0, k1;
+    long long count;   // cells in the box
+    long long offset;  // prefix of counts
+    double amp;
+    int wave;
+    double f, t0, tw;
+};
+
+struct ProbeDesc {
+    int comp;
+    int i0, i1, j0, j1, k0, k1;
+    double *series;
+    long long cap;
+    int nfreq;
+    double freq[TFL_MAX_FREQS];
+    double *dft;
+};
+
+template <typename T>
+struct SrcArgs {
+    GridDims g;
+    T *E[3];
+    int nsrc;
+    long long total;
+    double t;
+    SourceDesc src[TFL_MAX_SOURCES];
+};
+
+template <typename T>
+struct ProbeArgs {
+    GridDims g;
+    const T *E[3];
+    long long n;
+    double dt;
+    ProbeDesc p[TFL_MAX_PROBES];
+};
+
+// Host-side launchers (kernels_fwd.hip).
+template <typename T> hipError_t launch_h_pass(const StepArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_sources(const SrcArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_probes(const ProbeArgs<T> &a, int nprobe, hipStream_t s);
+// Integer-time half kick: Hout = Hin + sgn dt/(2 mu0) curlE (stretched, with
+// the PML variables advanced virtually), Jout = Jin - sgn dt/2 ell_e E / mu0 on
+// SC edges (0 on other edges).  sgn = +1 goes back half a step, -1 forward.
+template <typename T>
+hipError_t launch_half_kick(const StepArgs<T> &a, T sgn, T *const Hout[3], T *const Jout[3], hipStream_t s);
+// Energy partials into scratch (FP64), second stage reduces to scratch[0..1].
+template <typename T>
+hipError_t launch_energy(const StepArgs<T> &a, double *scratch, int nblocks, hipStream_t s);
+// Map statistics: min eps, min sigma, min ell, max ell, nonfinite count.
+template <typename T>
+hipError_t launch_map_stats(const T *eps, const T *sig, const T *ell, long long n, double *scratch, int nblocks,
+                            hipStream_t s);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace tfl

@@ -1,0 +1,195 @@
+"""Python front end of the two-fluid FDTD library.
+
+``Simulation`` owns the device buffers as torch tensors (torch supplies device
+memory and streams only) and forwards every operation to the C ABI of
+``libtfl.so``; all arithmetic of the time step runs in the HIP kernels.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float64: L.TFL_F64, torch.float32: L.TFL_F32}
+_WAVES = {"sin": L.TFL_WAVE_SIN, "gauss": L.TFL_WAVE_GAUSS, "mod_gauss": L.TFL_WAVE_MOD_GAUSS}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Simulation:
+    """Two-fluid Maxwell-London FDTD on an nx x ny x nz Yee grid (Sec. 3, Algorithm 1).
+
+    Parameters
+    ----------
+    shape : (nx, ny, nz)
+    spacing : (dx, dy, dz) in m
+    dt : time step in s
+    theta : weight of the Ohmic term (Algorithm 1 step 3), in [0.5, 1]
+    dtype : torch.float64 or torch.float32 (storage and arithmetic of E, H, Js and maps)
+    pml : per axis None (periodic) or (lo, hi) absorbing cells (CPML backed by a PEC wall)
+    """
+
+    def __init__(self, shape, spacing, dt, theta=1.0, dtype=torch.float64, pml=(None, None, None),
+                 pml_order=3.0, pml_scale=1.0, kappa_max=1.0, alpha_max=0.0, device="cuda"):
+        if dtype not in _DT:
+            raise ValueError("dtype must be torch.float64 or torch.float32")
+        self.nx, self.ny, self.nz = (int(v) for v in shape)
+        self.shape3 = (self.nz, self.ny, self.nx)
+        self.spacing = tuple(float(v) for v in spacing)
+        self.dt = float(dt)
+        self.theta = float(theta)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        cfg = L.tfl_config()
+        cfg.nx, cfg.ny, cfg.nz = self.nx, self.ny, self.nz
+        cfg.dx, cfg.dy, cfg.dz = self.spacing
+        cfg.dt, cfg.theta, cfg.dtype = self.dt, self.theta, _DT[dtype]
+        for a in range(3):
+            if pml[a] is None:
+                cfg.bc[a] = L.TFL_PERIODIC
+            else:
+                cfg.bc[a] = L.TFL_CPML
+                cfg.pml_lo[a], cfg.pml_hi[a] = int(pml[a][0]), int(pml[a][1])
+        cfg.pml_order, cfg.pml_scale, cfg.kappa_max, cfg.alpha_max = pml_order, pml_scale, kappa_max, alpha_max
+        self.pml = tuple(pml)
+        self._cfg = cfg
+        h = ctypes.c_void_p()
+        L.call("tfl_create", ctypes.byref(cfg), ctypes.byref(h))
+        self._h = h
+        z = lambda: torch.zeros(self.shape3, dtype=dtype, device=self.device)  # noqa: E731
+        self.E = [z() for _ in range(3)]
+        self.H = [z() for _ in range(3)]
+        self.J = [z() for _ in range(3)]
+        ws, sc, st = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        self._call("tfl_buffer_sizes", ctypes.byref(ws), ctypes.byref(sc), ctypes.byref(st))
+        self.state_bytes = st.value
+        self.workspace = torch.zeros(max(ws.value, 1), dtype=torch.uint8, device=self.device)
+        self.scratch = torch.zeros(sc.value, dtype=torch.uint8, device=self.device)
+        e3, self._ek = L.ptr3([t.data_ptr() for t in self.E])
+        h3, self._hk = L.ptr3([t.data_ptr() for t in self.H])
+        j3, self._jk = L.ptr3([t.data_ptr() for t in self.J])
+        self._call("tfl_bind_state", e3, h3, j3)
+        self._call("tfl_bind_workspace", ctypes.c_void_p(self.workspace.data_ptr() if ws.value else 0),
+                   ctypes.c_void_p(self.scratch.data_ptr()), _stream())
+        self.maps = None
+        self._probes = []
+        self._sources = []
+
+    # -- plumbing -----------------------------------------------------------
+    def _call(self, name, *args):
+        return L.call(name, self._h, *args, handle=self._h)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            L.lib().tfl_destroy(h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a):
+        t = torch.as_tensor(a)
+        if tuple(t.shape) != self.shape3:
+            raise ValueError(f"expected shape {self.shape3}, got {tuple(t.shape)}")
+        return t.to(device=self.device, dtype=self.dtype).contiguous()
+
+    # -- set-up -------------------------------------------------------------
+    def set_materials(self, eps_r, sigma, inv_lambda2):
+        """Per-cell eps_r, sigma_n (S/m) and 1/lambda_L^2 (m^-2); validated and dt-checked on the device."""
+        maps = [self._dev(m) for m in (eps_r, sigma, inv_lambda2)]
+        self._call("tfl_bind_materials", *[ctypes.c_void_p(m.data_ptr()) for m in maps], _stream())
+        self.maps = maps
+
+    def set_fields(self, E, H, J=None):
+        """Integer-time fields at t = 0 (E^0, H^0, Js^0); converted to the staggered state."""
+        for q in range(3):
+            self.E[q].copy_(self._dev(E[q]))
+            self.H[q].copy_(self._dev(H[q]))
+            self.J[q].copy_(self._dev(J[q]) if J is not None else torch.zeros_like(self.J[q]))
+        self._call("tfl_set_initial_integer_time", _stream())
+
+    def add_source(self, comp, box, amplitude, waveform="sin", freq=0.0, t0=0.0, tw=1.0):
+        s = L.tfl_source()
+        s.comp = int(comp)
+        for q in range(6):
+            s.box[q] = int(box[q])
+        s.amplitude, s.waveform = float(amplitude), _WAVES[waveform]
+        s.freq, s.t0, s.tw = float(freq), float(t0), float(tw)
+        sid = ctypes.c_int()
+        self._call("tfl_add_source", ctypes.byref(s), ctypes.byref(sid))
+        self._sources.append(s)
+        return sid.value
+
+    def add_probe(self, comp, box, capacity, freqs=()):
+        freqs = np.ascontiguousarray(np.asarray(freqs, dtype=np.float64).reshape(-1))
+        series = torch.zeros(max(int(capacity), 1), dtype=torch.float64, device=self.device)
+        dft = torch.zeros(max(2 * freqs.size, 1), dtype=torch.float64, device=self.device)
+        p = L.tfl_probe()
+        p.comp = int(comp)
+        for q in range(6):
+            p.box[q] = int(box[q])
+        p.series = series.data_ptr() if capacity > 0 else None
+        p.capacity = int(capacity)
+        p.nfreq = int(freqs.size)
+        p.freqs = freqs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if freqs.size else None
+        p.dft = dft.data_ptr() if freqs.size else None
+        pid = ctypes.c_int()
+        self._call("tfl_add_probe", ctypes.byref(p), ctypes.byref(pid))
+        self._probes.append((series, dft, int(capacity), int(freqs.size)))
+        return pid.value
+
+    # -- running ------------------------------------------------------------
+    def step(self, n=1):
+        self._call("tfl_step", ctypes.c_int64(int(n)), _stream())
+
+    def profile_step(self, n):
+        """Run n steps with HIP events around each pass; returns (H-pass ms, E-pass ms) summed."""
+        h, e = ctypes.c_double(), ctypes.c_double()
+        self._call("tfl_profile_step", ctypes.c_int64(int(n)), _stream(), ctypes.byref(h), ctypes.byref(e))
+        return h.value, e.value
+
+    @property
+    def step_index(self):
+        v = ctypes.c_int64()
+        self._call("tfl_get_step", ctypes.byref(v))
+        return v.value
+
+    def set_step(self, n):
+        self._call("tfl_set_step", ctypes.c_int64(int(n)))
+
+    # -- read-back ----------------------------------------------------------
+    def integer_time_fields(self):
+        """(E^n, H^n, Js^n) as new device tensors (Algorithm 1's state at integer time)."""
+        Hn = [torch.empty_like(t) for t in self.H]
+        Jn = [torch.empty_like(t) for t in self.J]
+        h3, hk = L.ptr3([t.data_ptr() for t in Hn])
+        j3, jk = L.ptr3([t.data_ptr() for t in Jn])
+        self._call("tfl_sync_integer_time", h3, j3, _stream())
+        return [t.clone() for t in self.E], Hn, Jn
+
+    def energy(self):
+        w, bad = ctypes.c_double(), ctypes.c_int64()
+        self._call("tfl_energy", ctypes.byref(w), ctypes.byref(bad), _stream())
+        return w.value, bad.value
+
+    def probe(self, pid):
+        series, dft, cap, nf = self._probes[pid]
+        s = series[:cap].cpu().numpy()
+        d = dft[: 2 * nf].cpu().numpy()
+        return s, d[0::2] + 1j * d[1::2]
+
+    def save_state(self, dst=None):
+        if dst is None:
+            dst = torch.empty(self.state_bytes, dtype=torch.uint8, device=self.device)
+        self._call("tfl_save_state", ctypes.c_void_p(dst.data_ptr()), _stream())
+        return dst
+
+    def load_state(self, src):
+        self._call("tfl_load_state", ctypes.c_void_p(src.data_ptr()), _stream())

@@ -1,0 +1,106 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+Input generation only: grids, spacings, time steps, per-cell material maps,
+initial fields, source and probe placements.  Nothing here evaluates the
+scheme; the same arrays are fed to the HIP path and to the CPU oracle.
+
+Every workload is a plain dict:
+  shape (nx, ny, nz), spacing (dx, dy, dz), dt, theta, pml (per axis None or
+  (lo, hi)), maps (eps_r, sigma, inv_lambda2) as float64 arrays (nz, ny, nx),
+  fields (E, H, J) at t = 0 as lists of float64 arrays or None (all zero),
+  sources and probes as lists of dicts, steps.
+"""
+import numpy as np
+
+EPS0 = 8.8541878128e-12
+MU0 = 1.25663706212e-6
+C0 = 1.0 / np.sqrt(EPS0 * MU0)
+
+
+def courant_dt(spacing, inv_lambda2_max, fraction):
+    """fraction x the largest stable dt of the scheme with a London term (eps_r >= 1):
+    2 / (c0 sqrt(sum 4/d^2 + max 1/lambda^2))."""
+    s = sum(4.0 / (d * d) for d in spacing)
+    return fraction * 2.0 / (C0 * np.sqrt(s + inv_lambda2_max))
+
+
+def random_boxes(shape, rng, fill=0.30, side=(4, 32), lam=(50e-9, 200e-9), sig=(1e3, 1e5),
+                 eps_r=None):
+    """Random axis-aligned superconducting boxes (integer sides uniform in `side`, uniform wrapped
+    positions, lambda_L and sigma_n linear-uniform), painted in order until `fill` of the cells are
+    superconducting.  Returns float64 maps (eps_r, sigma, inv_lambda2) of shape (nz, ny, nx)."""
+    nx, ny, nz = shape
+    ell = np.zeros((nz, ny, nx))
+    sg = np.zeros((nz, ny, nx))
+    er = np.ones((nz, ny, nx)) if eps_r is None else np.array(eps_r, dtype=np.float64, copy=True)
+    target = fill * nx * ny * nz
+    count = 0
+    while count < target:
+        w = rng.integers(side[0], side[1] + 1, size=3)
+        o = np.array([rng.integers(0, nx), rng.integers(0, ny), rng.integers(0, nz)])
+        lam_b = rng.uniform(*lam)
+        sig_b = rng.uniform(*sig)
+        ix = (o[0] + np.arange(min(w[0], nx))) % nx
+        iy = (o[1] + np.arange(min(w[1], ny))) % ny
+        iz = (o[2] + np.arange(min(w[2], nz))) % nz
+        sel = np.ix_(iz, iy, ix)
+        before = np.count_nonzero(ell[sel])
+        ell[sel] = 1.0 / lam_b**2
+        sg[sel] = sig_b
+        er[sel] = 1.0
+        count += ell[sel].size - before
+    return er, sg, ell
+
+
+def roofline_grid(n=256, seed=2, d=20e-9, steps=1000):
+    """Roofline workload: n^3 cells, dx = 20 nm, periodic on all sides, random superconducting boxes
+    (lambda_L in 50-200 nm, sigma_n in 1e3-1e5 S/m) filling ~30 % of the cells, eps_r = 1, E and H
+    drawn from N(0, 1), Js = 0, theta = 1, dt = 0.95 x the stable limit for lambda_L >= 50 nm."""
+    rng = np.random.default_rng(seed)
+    shape = (n, n, n) if np.isscalar(n) else tuple(n)
+    maps = random_boxes(shape, rng)
+    nz, ny, nx = shape[2], shape[1], shape[0]
+    E = [rng.standard_normal((nz, ny, nx)) for _ in range(3)]
+    H = [rng.standard_normal((nz, ny, nx)) for _ in range(3)]
+    return dict(name=f"roofline {shape[0]}x{shape[1]}x{shape[2]}", shape=shape, spacing=(d, d, d),
+                dt=courant_dt((d, d, d), 1.0 / (50e-9) ** 2, 0.95), theta=1.0, pml=(None, None, None),
+                maps=maps, fields=(E, H, None), sources=[], probes=[], steps=steps)
+
+
+def skin_depth_grid(sc=True, steps=26225, ny=4, nz=4):
+    """Skin-depth / reflection workload: 512 x 4 x 4 cells of 10 nm, periodic in y and z, CPML of 32
+    cells at both x ends; vacuum for x < 256 and a superconductor (lambda_L = 100 nm, sigma_n = 1e4
+    S/m, eps_r = 1) for x >= 256 (sc=False: all vacuum, the reference run); a soft 10 THz sine Ey
+    source of 1 V/m on node plane x = 64; dt = 0.99 dx / (c sqrt 3); theta = 1."""
+    nx, d = 512, 10e-9
+    shp = (nz, ny, nx)
+    ell = np.zeros(shp)
+    sig = np.zeros(shp)
+    if sc:
+        ell[..., 256:] = 1e14
+        sig[..., 256:] = 1e4
+    f = 10e12
+    return dict(name="skin depth 512x4x4", shape=(nx, ny, nz), spacing=(d, d, d),
+                dt=0.99 * d / (C0 * np.sqrt(3.0)), theta=1.0, pml=((32, 32), None, None),
+                maps=(np.ones(shp), sig, ell), fields=None,
+                sources=[dict(comp=1, box=(64, 65, 0, ny, 0, nz), amplitude=1.0, waveform="sin", freq=f)],
+                probes=[dict(comp=1, box=(160, 161, 0, ny, 0, nz), freqs=(f,))],
+                freq=f, steps=steps)
+
+
+def random_medium(shape, seed, pml=(None, None, None), d=(20e-9, 17e-9, 23e-9), theta=1.0, fill=0.4,
+                  field_scale=1.0, sigma_max=1e5):
+    """Small heterogeneous test medium: per-cell random eps_r in [1, 4], sigma_n in [0, sigma_max] on
+    half of the cells, superconducting cells (lambda_L 50-200 nm) on a `fill` fraction; random fields."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    shp = (nz, ny, nx)
+    ell = np.where(rng.random(shp) < fill, 1.0 / rng.uniform(50e-9, 200e-9, shp) ** 2, 0.0)
+    eps = rng.uniform(1.0, 4.0, shp)
+    sig = np.where(rng.random(shp) < 0.5, rng.uniform(0.0, sigma_max, shp), 0.0)
+    E = [field_scale * rng.standard_normal(shp) for _ in range(3)]
+    H = [field_scale * rng.standard_normal(shp) / 377.0 for _ in range(3)]
+    J = [np.where(ell > 0, 1e3 * rng.standard_normal(shp), 0.0) for _ in range(3)]
+    return dict(name=f"random medium {nx}x{ny}x{nz}", shape=shape, spacing=tuple(d),
+                dt=courant_dt(d, 1.0 / (50e-9) ** 2, 0.95), theta=theta, pml=pml,
+                maps=(eps, sig, ell), fields=(E, H, J), sources=[], probes=[], steps=20)
