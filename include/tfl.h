@@ -202,6 +202,51 @@ int tfl_set_step(tfl_sim *sim, int64_t step);
 int tfl_save_state(tfl_sim *sim, void *dst, void *stream);
 int tfl_load_state(tfl_sim *sim, const void *src, void *stream);
 
+/* ----------------------------------------------------------------------
+ * Gradients by the adjoint (reverse-time) method
+ *
+ * Objective: J = |F|^2 with F = sum_{n=n0}^{n0+N} dt exp(-i 2 pi f0 n dt) s_n,
+ * s_n the sum of E_comp over the index box at time level n (the probe of
+ * Sec. 4.2 and Sec. 5 with a single DFT frequency), n0 the step index where
+ * the run starts and N its number of steps.  Gradients are taken with respect
+ * to the per-cell maps inv_lambda2 and sigma_n, holding fixed which edges are
+ * superconducting: an edge's value is the mean over its superconducting
+ * cells (weight 1/|S| each) or over all four cells (sigma of a normal edge,
+ * weight 1/4); cells with inv_lambda2 = 0 receive no inv_lambda2 gradient.
+ * The forward run is checkpointed every `seg` steps (sqrt(N) memory); the
+ * reverse sweep recomputes one segment at a time, storing E after every
+ * step, and runs the transposed leap-frog with FP64 gradient accumulation.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t comp;
+    int64_t box[6];
+    double f0;
+} tfl_objective;
+
+/* Byte sizes of the caller-owned buffers for a run of nsteps with segments
+ * of seg steps: checkpoints (ceil(nsteps/seg) saved states), E snapshots
+ * (seg + 1 of them) and the adjoint workspace (adjoint fields, PML adjoint
+ * variables, FP64 per-edge gradient accumulators). */
+int tfl_adjoint_sizes(const tfl_sim *sim, int64_t nsteps, int64_t seg, size_t *ckpt_bytes, size_t *snap_bytes,
+                      size_t *adj_bytes);
+
+/* nsteps >= 1 forward steps from the current state, as tfl_step (sources and
+ * probes included), saving the state at the start of every segment into
+ * ckpt (segment g at byte offset g * state_bytes) and accumulating F in
+ * FP64.  F[0], F[1] receive Re F, Im F on the host; synchronises `stream`. */
+int tfl_forward_checkpointed(tfl_sim *sim, const tfl_objective *obj, int64_t nsteps, int64_t seg, void *ckpt,
+                             double F[2], void *stream);
+
+/* Reverse sweep of the last tfl_forward_checkpointed run (same obj, nsteps,
+ * seg and ckpt; F as returned by it).  Writes dJ/d inv_lambda2 and
+ * dJ/d sigma_n per cell to grad_ell and grad_sigma (device FP64, N each).
+ * snap and adj are device buffers of snap_bytes and adj_bytes.  Probes are
+ * not sampled during the recomputation.  On return the state and step index
+ * are those after the first segment of the run; restore a saved state to
+ * continue from elsewhere.  TFL_E_STATE if no matching forward run exists. */
+int tfl_adjoint(tfl_sim *sim, const tfl_objective *obj, int64_t nsteps, int64_t seg, const void *ckpt,
+                const double F[2], void *snap, void *adj, double *grad_ell, double *grad_sigma, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

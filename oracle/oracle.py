@@ -67,7 +67,7 @@ def lib():
         L.oracle_energy.argtypes = [P]
         if hasattr(L, "oracle_adjoint"):
             L.oracle_adjoint.restype = I
-            L.oracle_adjoint.argtypes = [P, Lg, I, D, pd, pd]
+            L.oracle_adjoint.argtypes = [P, Lg, I, D, pd, pd, pd]
         _lib = L
     return _lib
 
@@ -168,3 +168,14 @@ class OracleSim:
 
     def energy(self):
         return lib().oracle_energy(self._h)
+
+    def adjoint(self, nsteps, pid, f0):
+        """Run nsteps forward from the current state and return (J, F, dJ/d ell, dJ/d sigma) for
+        J = |sum_n dt exp(-i 2 pi f0 n dt) s_n|^2 of probe `pid` (per-cell FP64 gradients)."""
+        gl = np.zeros(self.shape3)
+        gs = np.zeros(self.shape3)
+        out = np.zeros(3)
+        rc = lib().oracle_adjoint(self._h, int(nsteps), int(pid), float(f0), _pd(gl), _pd(gs), _pd(out))
+        if rc != 0:
+            raise ValueError("oracle_adjoint: bad arguments")
+        return out[0], out[1] + 1j * out[2], gl, gs

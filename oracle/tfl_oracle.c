@@ -78,6 +78,7 @@ typedef struct {
     double pml_order, pml_scale, kappa_max, alpha_max;
 
     double *eps[3], *sig[3], *ell[3]; /* per edge of component c */
+    double *cell_ell;                 /* per-cell 1/lambda^2 (classification of edges) */
     double *E[3], *B[3], *J[3];
     double *psiB[3][3]; /* [component][derivative axis] */
     double *psiE[3][3];
@@ -174,6 +175,7 @@ void oracle_destroy(oracle_sim *s)
         free(s->bn[a]); free(s->cn[a]); free(s->kin[a]);
         free(s->bh[a]); free(s->ch[a]); free(s->kih[a]);
     }
+    free(s->cell_ell);
     for (int p = 0; p < s->nprobe; ++p) {
         free(s->probe[p].series); free(s->probe[p].freq);
         free(s->probe[p].dft_re); free(s->probe[p].dft_im);
@@ -188,6 +190,8 @@ void oracle_destroy(oracle_sim *s)
  * otherwise it takes the mean over all four. */
 void oracle_set_materials(oracle_sim *s, const double *eps_r, const double *sigma, const double *ell)
 {
+    if (!s->cell_ell) s->cell_ell = o_zeros(o_cells(s));
+    memcpy(s->cell_ell, ell, (size_t)o_cells(s) * sizeof(double));
     for (int c = 0; c < 3; ++c) {
         int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
         for (long k = 0; k < s->n[2]; ++k)
@@ -510,4 +514,290 @@ double oracle_energy(const oracle_sim *s)
         }
     }
     return dV * (we + wb + wj);
+}
+
+/* ======================================================================
+ * Adjoint (reverse-mode) of the run above, for the probe DFT objective
+ *   J = |F|^2,  F = sum_{n=0}^{N} w_n s_n,  w_n = dt exp(-i 2 pi f0 n dt),
+ * where s_n is the sample of probe `pid` (sum of E_comp over its box).
+ * The forward states of every step are stored (small grids only); each
+ * sub-step of Algorithm 1 is then transposed in reverse order.  Gradients
+ * are taken with respect to the per-cell maps ell = 1/lambda^2 and sigma,
+ * holding each edge's superconducting / normal classification fixed (the
+ * derivative of the per-edge rule: weight 1/|S| over the superconducting
+ * cells S of a superconducting edge, 1/4 over all cells of a normal edge).
+ * ====================================================================== */
+
+typedef struct {
+    double *E[3], *B[3], *J[3];
+    double *psiB[3][3], *psiE[3][3];
+} o_state;
+
+static void o_state_alloc(const oracle_sim *s, o_state *st)
+{
+    long N = o_cells(s);
+    for (int c = 0; c < 3; ++c) {
+        st->E[c] = o_zeros(N); st->B[c] = o_zeros(N); st->J[c] = o_zeros(N);
+        for (int a = 0; a < 3; ++a) {
+            st->psiB[c][a] = s->psiB[c][a] ? o_zeros(N) : NULL;
+            st->psiE[c][a] = s->psiE[c][a] ? o_zeros(N) : NULL;
+        }
+    }
+}
+
+static void o_state_free(o_state *st)
+{
+    for (int c = 0; c < 3; ++c) {
+        free(st->E[c]); free(st->B[c]); free(st->J[c]);
+        for (int a = 0; a < 3; ++a) { free(st->psiB[c][a]); free(st->psiE[c][a]); }
+    }
+}
+
+static void o_state_copy(const oracle_sim *s, o_state *dst, double *const *E, double *const *B, double *const *J,
+                         double *const (*psiB)[3], double *const (*psiE)[3])
+{
+    size_t bytes = (size_t)o_cells(s) * sizeof(double);
+    for (int c = 0; c < 3; ++c) {
+        memcpy(dst->E[c], E[c], bytes); memcpy(dst->B[c], B[c], bytes); memcpy(dst->J[c], J[c], bytes);
+        for (int a = 0; a < 3; ++a) {
+            if (dst->psiB[c][a]) memcpy(dst->psiB[c][a], psiB[c][a], bytes);
+            if (dst->psiE[c][a]) memcpy(dst->psiE[c][a], psiE[c][a], bytes);
+        }
+    }
+}
+
+static void o_state_load(oracle_sim *s, const o_state *src)
+{
+    o_state tmp;
+    for (int c = 0; c < 3; ++c) {
+        tmp.E[c] = s->E[c]; tmp.B[c] = s->B[c]; tmp.J[c] = s->J[c];
+        for (int a = 0; a < 3; ++a) { tmp.psiB[c][a] = s->psiB[c][a]; tmp.psiE[c][a] = s->psiE[c][a]; }
+    }
+    o_state_copy(s, &tmp, src->E, src->B, src->J, src->psiB, src->psiE);
+}
+
+static double o_probe_sum(const oracle_sim *s, int comp, const long *box)
+{
+    double sum = 0.0;
+    for (long k = box[4]; k < box[5]; ++k)
+        for (long j = box[2]; j < box[3]; ++j)
+            for (long i = box[0]; i < box[1]; ++i) sum += s->E[comp][o_idx(s, i, j, k)];
+    return sum;
+}
+
+/* Transpose of one stretched B half update (sub-steps 1 and 5):
+ *   psi' = b psi + c D_a E_c'   (only when advance)
+ *   B_c -= dt/2 * sgn * (k D_a E_c' + psi')
+ * for every face of component c and both curl terms.  aB is the adjoint of
+ * B (unchanged), aE and apsi are updated in place. */
+static void o_adj_half_B(oracle_sim *s, double **aE, double **aB, double *(*apsi)[3], int advance)
+{
+    double h = 0.5 * s->dt;
+    for (int c = 0; c < 3; ++c) {
+        int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+        /* (curl E)_c = D_{a1} E_{a2} - D_{a2} E_{a1} */
+        int ax[2] = {a1, a2};
+        int ec[2] = {a2, a1};
+        double sg[2] = {1.0, -1.0};
+        for (int t = 0; t < 2; ++t) {
+            int a = ax[t];
+            for (long k = 0; k < s->n[2]; ++k)
+                for (long j = 0; j < s->n[1]; ++j)
+                    for (long i = 0; i < s->n[0]; ++i) {
+                        long ijk[3] = {i, j, k};
+                        long e = o_idx(s, i, j, k);
+                        long ia = ijk[a];
+                        double coefB = -h * sg[t];         /* dB / d(stretched derivative) */
+                        double w = coefB * s->kih[a][ia] * aB[c][e];
+                        if (apsi[c][a]) {
+                            double tot = apsi[c][a][e] + coefB * aB[c][e];
+                            if (advance) {
+                                w += s->ch[a][ia] * tot;
+                                apsi[c][a][e] = s->bh[a][ia] * tot;
+                            } else {
+                                apsi[c][a][e] = tot;
+                            }
+                        }
+                        /* D_a E at e: (E[p + e_a] - E[p]) / d_a; transpose scatters w/d */
+                        long p[3] = {i, j, k};
+                        p[a] += 1;
+                        aE[ec[t]][o_idx(s, p[0], p[1], p[2])] += w / s->d[a];
+                        aE[ec[t]][e] -= w / s->d[a];
+                    }
+        }
+    }
+}
+
+int oracle_adjoint(oracle_sim *s, long nsteps, int pid, double f0, double *grad_ell, double *grad_sig, double *out)
+{
+    const double twopi = 2.0 * 3.14159265358979323846;
+    if (pid < 0 || pid >= s->nprobe || nsteps < 1) return -1;
+    const o_probe *q = &s->probe[pid];
+    long N = o_cells(s);
+    double dt = s->dt, th = s->theta;
+
+    /* forward, storing every state and the samples */
+    o_state *traj = (o_state *)calloc((size_t)nsteps + 1, sizeof(o_state));
+    double *samp = (double *)calloc((size_t)nsteps + 1, sizeof(double));
+    double *Epre[3];
+    for (long n = 0; n <= nsteps; ++n) o_state_alloc(s, &traj[n]);
+    o_state_copy(s, &traj[0], s->E, s->B, s->J, s->psiB, s->psiE);
+    long step0 = s->step;
+    samp[0] = o_probe_sum(s, q->comp, q->box);
+    for (long n = 0; n < nsteps; ++n) {
+        oracle_step(s, 1);
+        o_state_copy(s, &traj[n + 1], s->E, s->B, s->J, s->psiB, s->psiE);
+        samp[n + 1] = o_probe_sum(s, q->comp, q->box);
+    }
+    double Fr = 0.0, Fi = 0.0;
+    for (long n = 0; n <= nsteps; ++n) {
+        double ph = twopi * f0 * (double)n * dt;
+        Fr += samp[n] * dt * cos(ph);
+        Fi -= samp[n] * dt * sin(ph);
+    }
+
+    /* adjoint state and per-edge gradients */
+    double *aE[3], *aB[3], *aJ[3], *aH[3], *gl[3], *gs[3];
+    double *apsiB[3][3], *apsiE[3][3];
+    for (int c = 0; c < 3; ++c) {
+        aE[c] = o_zeros(N); aB[c] = o_zeros(N); aJ[c] = o_zeros(N); aH[c] = o_zeros(N);
+        gl[c] = o_zeros(N); gs[c] = o_zeros(N); Epre[c] = o_zeros(N);
+        for (int a = 0; a < 3; ++a) {
+            apsiB[c][a] = s->psiB[c][a] ? o_zeros(N) : NULL;
+            apsiE[c][a] = s->psiE[c][a] ? o_zeros(N) : NULL;
+        }
+    }
+    double *Hn[3];
+    for (int c = 0; c < 3; ++c) Hn[c] = o_zeros(N);
+
+    for (long n = nsteps; n >= 0; --n) {
+        /* objective source at E^n: dJ/ds_n = 2 Re(conj(F) w_n) */
+        double ph = twopi * f0 * (double)n * dt;
+        double gn = 2.0 * dt * (Fr * cos(ph) - Fi * sin(ph));
+        for (long k = q->box[4]; k < q->box[5]; ++k)
+            for (long j = q->box[2]; j < q->box[3]; ++j)
+                for (long i = q->box[0]; i < q->box[1]; ++i) aE[q->comp][o_idx(s, i, j, k)] += gn;
+        if (n == 0) break;
+        long m = n - 1; /* transpose step m -> m+1 */
+        /* recompute the intermediates of step m: B^{m+1/2} (for H) and E^{m+1} before the sources */
+        o_state_load(s, &traj[m]);
+        s->step = step0 + m;
+        o_half_B(s, 0);
+        o_half_J(s);
+        {
+            int nsrc = s->nsrc;
+            s->nsrc = 0;
+            o_full_E(s);
+            s->nsrc = nsrc;
+        }
+        for (int c = 0; c < 3; ++c) memcpy(Epre[c], s->E[c], (size_t)N * sizeof(double));
+        const o_state *X0 = &traj[m], *X1 = &traj[m + 1];
+
+        /* 5^T */
+        o_adj_half_B(s, aE, aB, apsiB, 1);
+        /* 4^T: Js^{m+1} = Js^{m+1/2} + dt/2 ell E^{m+1}/mu0 */
+        for (int c = 0; c < 3; ++c)
+            for (long e = 0; e < N; ++e)
+                if (s->ell[c][e] > 0.0) {
+                    aE[c][e] += 0.5 * dt * s->ell[c][e] / O_MU0 * aJ[c][e];
+                    gl[c][e] += 0.5 * dt * X1->E[c][e] / O_MU0 * aJ[c][e];
+                }
+        /* 3^T: E^{m+1} = alpha [(1-(1-th) s) E^m + dt/eps (curlH - Js)], curlH from H = B^{m+1/2}/mu0 */
+        for (int c = 0; c < 3; ++c) memset(aH[c], 0, (size_t)N * sizeof(double));
+        for (int c = 0; c < 3; ++c) {
+            int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+            int ax[2] = {a1, a2};
+            int hc[2] = {a2, a1};
+            double sg[2] = {1.0, -1.0};
+            for (long k = 0; k < s->n[2]; ++k)
+                for (long j = 0; j < s->n[1]; ++j)
+                    for (long i = 0; i < s->n[0]; ++i) {
+                        long ijk[3] = {i, j, k};
+                        long e = o_idx(s, i, j, k);
+                        if (o_on_wall(s, c, ijk)) aE[c][e] = 0.0;
+                        double eps = s->eps[c][e];
+                        double sgm = s->sig[c][e] * dt / eps;
+                        double alpha = 1.0 / (1.0 + th * sgm);
+                        double aEp = aE[c][e];
+                        gs[c][e] += aEp * (dt / eps) * (-(1.0 - th) * X0->E[c][e] - th * Epre[c][e]) * alpha;
+                        if (s->ell[c][e] > 0.0) aJ[c][e] -= alpha * (dt / eps) * aEp;
+                        double cbar = alpha * (dt / eps) * aEp;
+                        for (int t = 0; t < 2; ++t) {
+                            int a = ax[t];
+                            long ia = ijk[a];
+                            double w = sg[t] * s->kin[a][ia] * cbar;
+                            if (apsiE[c][a]) {
+                                double tot = apsiE[c][a][e] + sg[t] * cbar;
+                                w += s->cn[a][ia] * tot;
+                                apsiE[c][a][e] = s->bn[a][ia] * tot;
+                            }
+                            /* D*_a H at e: (H[p] - H[p - e_a]) / d_a */
+                            long p[3] = {i, j, k};
+                            p[a] -= 1;
+                            aH[hc[t]][e] += w / s->d[a];
+                            aH[hc[t]][o_idx(s, p[0], p[1], p[2])] -= w / s->d[a];
+                        }
+                        aE[c][e] = alpha * (1.0 - (1.0 - th) * sgm) * aEp;
+                    }
+        }
+        for (int c = 0; c < 3; ++c)
+            for (long e = 0; e < N; ++e) aB[c][e] += aH[c][e] / O_MU0;
+        /* 2^T: Js^{m+1/2} = Js^m + dt/2 ell E^m / mu0 */
+        for (int c = 0; c < 3; ++c)
+            for (long e = 0; e < N; ++e)
+                if (s->ell[c][e] > 0.0) {
+                    aE[c][e] += 0.5 * dt * s->ell[c][e] / O_MU0 * aJ[c][e];
+                    gl[c][e] += 0.5 * dt * X0->E[c][e] / O_MU0 * aJ[c][e];
+                }
+        /* 1^T */
+        o_adj_half_B(s, aE, aB, apsiB, 0);
+    }
+    /* restore the forward end state */
+    o_state_load(s, &traj[nsteps]);
+    s->step = step0 + nsteps;
+
+    /* per-edge -> per-cell (the derivative of the edge material rule) */
+    memset(grad_ell, 0, (size_t)N * sizeof(double));
+    memset(grad_sig, 0, (size_t)N * sizeof(double));
+    for (int c = 0; c < 3; ++c) {
+        int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+        for (long k = 0; k < s->n[2]; ++k)
+            for (long j = 0; j < s->n[1]; ++j)
+                for (long i = 0; i < s->n[0]; ++i) {
+                    long e = o_idx(s, i, j, k);
+                    long cells[4];
+                    int nsc = 0;
+                    for (int u = 0; u < 2; ++u)
+                        for (int v = 0; v < 2; ++v) {
+                            long o[3] = {i, j, k};
+                            o[a1] -= u;
+                            o[a2] -= v;
+                            cells[2 * u + v] = o_idx(s, o[0], o[1], o[2]);
+                        }
+                    (void)nsc;
+                    double ls[4];
+                    int cnt = 0;
+                    const double *ellc = s->cell_ell;
+                    for (int t = 0; t < 4; ++t) { ls[t] = ellc[cells[t]]; if (ls[t] > 0.0) cnt++; }
+                    for (int t = 0; t < 4; ++t) {
+                        if (cnt > 0) {
+                            if (ls[t] > 0.0) {
+                                grad_ell[cells[t]] += gl[c][e] / (double)cnt;
+                                grad_sig[cells[t]] += gs[c][e] / (double)cnt;
+                            }
+                        } else {
+                            grad_sig[cells[t]] += gs[c][e] / 4.0;
+                        }
+                    }
+                }
+    }
+    if (out) { out[0] = Fr * Fr + Fi * Fi; out[1] = Fr; out[2] = Fi; }
+
+    for (long n = 0; n <= nsteps; ++n) o_state_free(&traj[n]);
+    free(traj); free(samp);
+    for (int c = 0; c < 3; ++c) {
+        free(aE[c]); free(aB[c]); free(aJ[c]); free(aH[c]); free(gl[c]); free(gs[c]); free(Epre[c]); free(Hn[c]);
+        for (int a = 0; a < 3; ++a) { free(apsiB[c][a]); free(apsiE[c][a]); }
+    }
+    return 0;
 }

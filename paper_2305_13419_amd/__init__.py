@@ -5,6 +5,7 @@ The time step (Algorithm 1 of arXiv 2305.13419) runs in the HIP kernels of
 (``include/tfl.h``).  Importing the package requires the built library.
 """
 from . import _lib  # noqa: F401
+from .autograd import AdjointProblem, TwoFluidObjective  # noqa: F401
 from .sim import Simulation  # noqa: F401
 
-__all__ = ["Simulation"]
+__all__ = ["Simulation", "AdjointProblem", "TwoFluidObjective"]

@@ -65,6 +65,10 @@ class tfl_probe(ctypes.Structure):
     ]
 
 
+class tfl_objective(ctypes.Structure):
+    _fields_ = [("comp", ctypes.c_int32), ("box", ctypes.c_int64 * 6), ("f0", ctypes.c_double)]
+
+
 class TflError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
@@ -98,6 +102,12 @@ SIGNATURES = {
     "tfl_set_step": [P, ctypes.c_int64],
     "tfl_save_state": [P, P, P],
     "tfl_load_state": [P, P, P],
+    "tfl_adjoint_sizes": [P, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t),
+                          ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+    "tfl_forward_checkpointed": [P, ctypes.POINTER(tfl_objective), ctypes.c_int64, ctypes.c_int64, P,
+                                 ctypes.POINTER(ctypes.c_double), P],
+    "tfl_adjoint": [P, ctypes.POINTER(tfl_objective), ctypes.c_int64, ctypes.c_int64, P,
+                    ctypes.POINTER(ctypes.c_double), P, P, P, P, P],
 }
 OPTIONAL_SIGNATURES = {}
 

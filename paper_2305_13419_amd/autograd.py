@@ -1,0 +1,70 @@
+"""torch.autograd binding of the adjoint: J(inv_lambda2, sigma_n) = |F|^2.
+
+``TwoFluidObjective.apply(inv_lambda2, sigma_n, problem)`` runs the forward
+FDTD (checkpointed every ``seg`` steps) through the C ABI and returns the
+scalar objective; its backward runs the reverse-time sweep on the GPU and
+returns the per-cell gradients (FP64 accumulation, cast to the input dtype).
+"""
+import math
+
+import torch
+
+from .sim import Simulation
+
+
+class AdjointProblem:
+    """Everything of a run except the two differentiated maps.
+
+    shape, spacing, dt, theta, dtype, pml : as for Simulation
+    eps_r : per-cell relative permittivity (fixed)
+    fields : initial integer-time (E, H, J) or None for zero fields
+    sources : list of dicts for Simulation.add_source
+    objective : (comp, box, f0)
+    nsteps, seg : run length and checkpoint segment (default about sqrt(nsteps))
+    """
+
+    def __init__(self, shape, spacing, dt, eps_r, objective, nsteps, seg=None, theta=1.0, dtype=torch.float64,
+                 pml=(None, None, None), fields=None, sources=(), device="cuda"):
+        self.sim = Simulation(shape, spacing, dt, theta, dtype, pml, device=device)
+        self.eps_r = self.sim._dev(eps_r)
+        self.fields = fields
+        self.sources = list(sources)
+        for s in self.sources:
+            self.sim.add_source(**s)
+        self.objective = tuple(objective)
+        self.nsteps = int(nsteps)
+        self.seg = int(seg) if seg else max(1, int(round(math.sqrt(self.nsteps))))
+        self.ckpt, self.snap, self.work = self.sim.adjoint_buffers(self.nsteps, self.seg)
+        self.F = None
+
+    def _reset(self, inv_lambda2, sigma):
+        sim = self.sim
+        sim.set_materials(self.eps_r, sigma, inv_lambda2)
+        if self.fields is None:
+            z = [torch.zeros(sim.shape3, dtype=sim.dtype, device=sim.device) for _ in range(3)]
+            sim.set_fields(z, z, z)
+        else:
+            sim.set_fields(*self.fields)
+
+    def forward(self, inv_lambda2, sigma):
+        self._reset(inv_lambda2, sigma)
+        self.F = self.sim.forward_checkpointed(self.objective, self.nsteps, self.seg, self.ckpt)
+        return abs(self.F) ** 2
+
+    def gradient(self):
+        return self.sim.adjoint(self.objective, self.nsteps, self.seg, self.ckpt, self.F, self.snap, self.work)
+
+
+class TwoFluidObjective(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, inv_lambda2, sigma, problem):
+        J = problem.forward(inv_lambda2.detach(), sigma.detach())
+        ctx.problem = problem
+        ctx.dtypes = (inv_lambda2.dtype, sigma.dtype)
+        return torch.tensor(J, dtype=torch.float64, device=inv_lambda2.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        gl, gs = ctx.problem.gradient()
+        g = grad_out.to(torch.float64)
+        return (g * gl).to(ctx.dtypes[0]), (g * gs).to(ctx.dtypes[1]), None

@@ -10,35 +10,13 @@
 #include <string>
 #include <vector>
 
-#include "tfl_internal.h"
+#include "sim_internal.h"
 
 using namespace tfl;
 
-struct tfl_sim {
-    tfl_config cfg;
-    long long N = 0;
-    int esz = 8;
-    void *E[3] = {nullptr, nullptr, nullptr};
-    void *H[3] = {nullptr, nullptr, nullptr};
-    void *J[3] = {nullptr, nullptr, nullptr};
-    const void *eps = nullptr, *sig = nullptr, *ell = nullptr;
-    void *work = nullptr;
-    double *scratch = nullptr;
-    bool state_bound = false, work_bound = false, maps_bound = false;
-    size_t work_bytes = 0;
-    // workspace layout (element offsets in units of the field type)
-    size_t table_off[3] = {0, 0, 0};   // 6 tables of n[a] entries per CPML axis
-    size_t psi_off[3] = {0, 0, 0};     // 4 arrays of slab size per CPML axis
-    size_t psi_count[3] = {0, 0, 0};   // elements per auxiliary array
-    int64_t step = 0;
-    bool sampled0 = false;
-    std::vector<SourceDesc> src;
-    std::vector<ProbeDesc> probe;
-    double max_ell = 0.0;
-    std::string err;
-};
 
-namespace {
+namespace tfl {
+namespace detail {
 
 thread_local std::string g_create_err;
 
@@ -61,8 +39,6 @@ int hip_fail(tfl_sim *s, hipError_t e, const char *where)
 
 bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
-constexpr size_t kScratchBytes = 1 << 16;  // 8192 doubles: up to 1024 blocks x 5 partials
-constexpr int kRedBlocks = 1024;
 
 int64_t axis_n(const tfl_config &c, int a) { return a == 0 ? c.nx : (a == 1 ? c.ny : c.nz); }
 double axis_d(const tfl_config &c, int a) { return a == 0 ? c.dx : (a == 1 ? c.dy : c.dz); }
@@ -170,7 +146,7 @@ StepArgs<T> make_args(const tfl_sim *s)
 }
 
 template <typename T>
-int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev = nullptr)
+int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool probes)
 {
     const StepArgs<T> a = make_args<T>(s);
     SrcArgs<T> sa{};
@@ -182,8 +158,13 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev = nullptr
     pa.g = a.g;
     for (int q = 0; q < 3; ++q) pa.E[q] = a.E[q];
     pa.dt = s->cfg.dt;
-    const int np = (int)s->probe.size();
-    for (int q = 0; q < np; ++q) pa.p[q] = s->probe[q];
+    const int np = probes ? (int)s->probe.size() : 0;
+    if (np > 0) {
+        const int rc = upload_probes(s, st);
+        if (rc != TFL_OK) return rc;
+    }
+    pa.p = (const ProbeDesc *)((const char *)s->scratch + kProbeDescOffset);
+    pa.first = 0;
     hipError_t e;
     if (np > 0 && s->step == 0 && !s->sampled0) {
         pa.n = 0;
@@ -206,6 +187,17 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev = nullptr
         }
     }
     if (ev && nsteps > 0 && (e = hipEventRecord(ev[2 * nsteps], st)) != hipSuccess) return hip_fail(s, e, "event");
+    return TFL_OK;
+}
+
+int upload_probes(tfl_sim *s, hipStream_t st)
+{
+    if (!s->probes_dirty || s->probe.empty()) return TFL_OK;
+    void *dst = (char *)s->scratch + kProbeDescOffset;
+    hipError_t e = hipMemcpyAsync(dst, s->probe.data(), s->probe.size() * sizeof(ProbeDesc), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host vector may change after return
+    if (e != hipSuccess) return hip_fail(s, e, "probe descriptor upload");
+    s->probes_dirty = false;
     return TFL_OK;
 }
 
@@ -268,7 +260,7 @@ static int clear_psi(tfl_sim *s, hipStream_t st)
     return TFL_OK;
 }
 
-static int copy_state(tfl_sim *s, void *dst, const void *src, bool save, hipStream_t st)
+int copy_state(tfl_sim *s, void *dst, const void *src, bool save, hipStream_t st)
 {
     const size_t fb = (size_t)s->N * s->esz, stride = round256(fb);
     char *buf = save ? (char *)dst : (char *)const_cast<void *>(src);
@@ -286,7 +278,15 @@ static int copy_state(tfl_sim *s, void *dst, const void *src, bool save, hipStre
     return TFL_OK;
 }
 
-}  // namespace
+template StepArgs<double> make_args<double>(const tfl_sim *);
+template StepArgs<float> make_args<float>(const tfl_sim *);
+template int do_step<double>(tfl_sim *, int64_t, hipStream_t, hipEvent_t *, bool);
+template int do_step<float>(tfl_sim *, int64_t, hipStream_t, hipEvent_t *, bool);
+
+}  // namespace detail
+}  // namespace tfl
+
+using namespace tfl::detail;
 
 extern "C" {
 
@@ -484,6 +484,7 @@ int tfl_add_probe(tfl_sim *s, const tfl_probe *p, int *id)
     for (int f = 0; f < p->nfreq; ++f) d.freq[f] = p->freqs[f];
     d.dft = p->dft;
     s->probe.push_back(d);
+    s->probes_dirty = true;
     if (id) *id = (int)s->probe.size() - 1;
     return TFL_OK;
 }
@@ -493,6 +494,7 @@ int tfl_clear_sources_probes(tfl_sim *s)
     if (!s) return fail(nullptr, TFL_E_INVAL, "null handle");
     s->src.clear();
     s->probe.clear();
+    s->probes_dirty = true;
     return TFL_OK;
 }
 
@@ -532,7 +534,7 @@ int tfl_profile_step(tfl_sim *s, int64_t nsteps, void *stream, double *h_ms, dou
         }
     }
     for (auto &x : ev)
-        if (x) hipEventDestroy(x);
+        if (x) (void)hipEventDestroy(x);
     if (rc != TFL_OK) return rc;
     if (e != hipSuccess) return hip_fail(s, e, "profile events");
     return TFL_OK;

@@ -1,0 +1,250 @@
+// C ABI of the adjoint: checkpointed forward run and the reverse sweep.
+// All device work runs in kernels_fwd.hip and kernels_adj.hip.
+#include <cmath>
+#include <cstring>
+
+#include "sim_internal.h"
+
+using namespace tfl;
+using namespace tfl::detail;
+
+namespace {
+
+struct AdjLayout {
+    size_t field = 0;   // bytes of one field component, 256-aligned
+    size_t grad = 0;    // bytes of one FP64 per-edge accumulator, 256-aligned
+    size_t psi = 0;     // bytes of the PML adjoint variables
+    size_t total = 0;
+};
+
+AdjLayout adj_layout(const tfl_sim *s)
+{
+    AdjLayout L;
+    L.field = round256((size_t)s->N * s->esz);
+    L.grad = round256((size_t)s->N * 8);
+    for (int a = 0; a < 3; ++a) L.psi += round256(4 * s->psi_count[a] * s->esz);
+    L.total = 12 * L.field + L.psi + 6 * L.grad;
+    return L;
+}
+
+size_t state_bytes(const tfl_sim *s) { return 9 * round256((size_t)s->N * s->esz) + round256(s->work_bytes); }
+
+int check_obj(tfl_sim *s, const tfl_objective *o)
+{
+    if (!o) return fail(s, TFL_E_INVAL, "null objective");
+    if (o->comp < 0 || o->comp > 2) return fail(s, TFL_E_INVAL, "objective component must be 0..2");
+    if (!box_ok(s->cfg, o->box)) return fail(s, TFL_E_INVAL, "objective box outside the grid or empty");
+    if (!std::isfinite(o->f0)) return fail(s, TFL_E_INVAL, "objective frequency must be finite");
+    return TFL_OK;
+}
+
+ProbeDesc objective_probe(const tfl_objective *o, double *dft)
+{
+    ProbeDesc d{};
+    d.comp = o->comp;
+    d.i0 = (int)o->box[0]; d.i1 = (int)o->box[1];
+    d.j0 = (int)o->box[2]; d.j1 = (int)o->box[3];
+    d.k0 = (int)o->box[4]; d.k1 = (int)o->box[5];
+    d.series = nullptr;
+    d.cap = 0;
+    d.nfreq = 1;
+    d.freq[0] = o->f0;
+    d.dft = dft;
+    return d;
+}
+
+template <typename T>
+int forward_ckpt(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg, void *ckpt, double F[2],
+                 hipStream_t st)
+{
+    double *dft = s->scratch + kObjectiveSlot;
+    hipError_t e = launch_fill_zero(dft, 2 * sizeof(double), st);
+    if (e != hipSuccess) return hip_fail(s, e, "objective clear");
+    const int64_t n0 = s->step;
+    const bool first = (n0 == 0 && !s->sampled0);
+    s->probe.push_back(objective_probe(o, dft));
+    s->probes_dirty = true;
+    // sample at n0: every probe if this is the first sample of the run, else the objective only
+    {
+        int rc0 = upload_probes(s, st);
+        ProbeArgs<T> pa{};
+        const StepArgs<T> a = make_args<T>(s);
+        pa.g = a.g;
+        for (int q = 0; q < 3; ++q) pa.E[q] = a.E[q];
+        pa.dt = s->cfg.dt;
+        pa.n = n0;
+        pa.p = (const ProbeDesc *)((const char *)s->scratch + kProbeDescOffset);
+        const int np = (int)s->probe.size();
+        pa.first = first ? 0 : np - 1;
+        if (rc0 == TFL_OK && (e = launch_probes<T>(pa, first ? np : 1, st)) != hipSuccess)
+            rc0 = hip_fail(s, e, "objective sample");
+        if (rc0 != TFL_OK) {
+            s->probe.pop_back();
+            s->probes_dirty = true;
+            return rc0;
+        }
+        s->sampled0 = true;
+    }
+    const size_t sb = state_bytes(s);
+    int rc = TFL_OK;
+    const int64_t nseg = (nsteps + seg - 1) / seg;
+    for (int64_t g = 0; g < nseg && rc == TFL_OK; ++g) {
+        rc = copy_state(s, (char *)ckpt + (size_t)g * sb, nullptr, true, st);
+        if (rc != TFL_OK) break;
+        const int64_t len = std::min(seg, nsteps - g * seg);
+        rc = do_step<T>(s, len, st);
+    }
+    s->probe.pop_back();
+    s->probes_dirty = true;
+    if (rc != TFL_OK) return rc;
+    e = hipMemcpyAsync(F, dft, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(s, e, "objective readback");
+    s->ckpt_valid = true;
+    s->ckpt_n0 = n0;
+    s->ckpt_nsteps = nsteps;
+    s->ckpt_seg = seg;
+    return TFL_OK;
+}
+
+template <typename T>
+int adjoint(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg, const void *ckpt, const double F[2],
+            void *snap, void *adj, double *grad_ell, double *grad_sig, hipStream_t st)
+{
+    const AdjLayout L = adj_layout(s);
+    hipError_t e = launch_fill_zero(adj, L.total, st);
+    if (e != hipSuccess) return hip_fail(s, e, "adjoint clear");
+    AdjArgs<T> A{};
+    A.f = make_args<T>(s);
+    char *p = (char *)adj;
+    for (int q = 0; q < 3; ++q) { A.lE[q] = (T *)p; p += L.field; }
+    for (int q = 0; q < 3; ++q) { A.lH[q] = (T *)p; p += L.field; }
+    for (int q = 0; q < 3; ++q) { A.lJ[q] = (T *)p; p += L.field; }
+    for (int q = 0; q < 3; ++q) { A.mu[q] = (T *)p; p += L.field; }
+    for (int a = 0; a < 3; ++a) {
+        const size_t m = s->psi_count[a] * s->esz;
+        if (s->cfg.bc[a] == TFL_CPML) {
+            A.lpsiH[a][0] = (T *)p; A.lpsiH[a][1] = (T *)(p + m);
+            A.lpsiE[a][0] = (T *)(p + 2 * m); A.lpsiE[a][1] = (T *)(p + 3 * m);
+        }
+        p += round256(4 * m);
+    }
+    for (int q = 0; q < 3; ++q) { A.gL[q] = (double *)p; p += L.grad; }
+    for (int q = 0; q < 3; ++q) { A.gS[q] = (double *)p; p += L.grad; }
+    A.ocomp = o->comp;
+    for (int q = 0; q < 6; ++q) A.ob[q] = (int)o->box[q];
+
+    const size_t fb = round256((size_t)s->N * s->esz);
+    auto snapE = [&](int64_t t, int q) { return (T *)((char *)snap + ((size_t)t * 3 + q) * fb); };
+    const size_t sb = state_bytes(s);
+    const int64_t n0 = s->ckpt_n0, nend = n0 + nsteps;
+    const double dt = s->cfg.dt;
+    auto objective_coef = [&](int64_t n) {
+        const double ph = kTwoPi * o->f0 * (double)n * dt;
+        return 2.0 * dt * (F[0] * std::cos(ph) - F[1] * std::sin(ph));
+    };
+    SrcArgs<T> sa{};
+    sa.g = A.f.g;
+    sa.nsrc = (int)s->src.size();
+    for (int q = 0; q < sa.nsrc; ++q) {
+        sa.src[q] = s->src[q];
+        sa.src[q].amp = -sa.src[q].amp;  // removes the source from a snapshot
+    }
+    const int64_t nseg = (nsteps + seg - 1) / seg;
+    int rc;
+    for (int64_t g = nseg - 1; g >= 0; --g) {
+        const int64_t s0 = n0 + g * seg;
+        const int64_t len = std::min(seg, nend - s0);
+        // recompute the segment, storing E^{s0} ... E^{s0+len}
+        if ((rc = copy_state(s, nullptr, (const char *)ckpt + (size_t)g * sb, false, st)) != TFL_OK) return rc;
+        s->step = s0;
+        for (int64_t t = 0; t <= len; ++t) {
+            if (t > 0 && (rc = do_step<T>(s, 1, st, nullptr, false)) != TFL_OK) return rc;
+            for (int q = 0; q < 3; ++q) {
+                e = hipMemcpyAsync(snapE(t, q), s->E[q], (size_t)s->N * s->esz, hipMemcpyDeviceToDevice, st);
+                if (e != hipSuccess) return hip_fail(s, e, "snapshot");
+            }
+        }
+        const int64_t end = s0 + len;
+        for (int64_t n = end; n >= s0 + 1; --n) {
+            if (n != end && (e = launch_adj_faces<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint faces");
+            if (sa.nsrc > 0) {
+                for (int q = 0; q < 3; ++q) sa.E[q] = snapE(n - s0, q);
+                sa.t = (double)n * dt;
+                if ((e = launch_sources<T>(sa, st)) != hipSuccess) return hip_fail(s, e, "snapshot sources");
+            }
+            A.doC = (n != nend);
+            A.doA = 1;
+            A.obj = 1;
+            A.og = objective_coef(n);
+            for (int q = 0; q < 3; ++q) {
+                A.En[q] = snapE(n - 1 - s0, q);
+                A.Ep[q] = snapE(n - s0, q);
+            }
+            if ((e = launch_adj_edges<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint edges");
+        }
+        if ((e = launch_adj_faces<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint faces");
+        if (g == 0) {
+            A.doC = 1;
+            A.doA = 0;
+            A.obj = 1;
+            A.og = objective_coef(n0);
+            if ((e = launch_adj_edges<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint edges");
+            for (int q = 0; q < 3; ++q) A.En[q] = snapE(0, q);
+            if ((e = launch_adj_initial_kick<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint kick");
+        }
+    }
+    if ((e = launch_adj_edge_to_cell<T>(A, grad_ell, grad_sig, st)) != hipSuccess)
+        return hip_fail(s, e, "gradient to cells");
+    return TFL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tfl_adjoint_sizes(const tfl_sim *s, int64_t nsteps, int64_t seg, size_t *ckpt_bytes, size_t *snap_bytes,
+                      size_t *adj_bytes)
+{
+    if (!s) return fail(nullptr, TFL_E_INVAL, "null handle");
+    if (nsteps < 1 || seg < 1) return fail(const_cast<tfl_sim *>(s), TFL_E_INVAL, "nsteps and seg must be >= 1");
+    const int64_t nseg = (nsteps + seg - 1) / seg;
+    const int64_t sl = std::min(seg, nsteps);
+    if (ckpt_bytes) *ckpt_bytes = (size_t)nseg * state_bytes(s);
+    if (snap_bytes) *snap_bytes = (size_t)(sl + 1) * 3 * round256((size_t)s->N * s->esz);
+    if (adj_bytes) *adj_bytes = adj_layout(s).total;
+    return TFL_OK;
+}
+
+int tfl_forward_checkpointed(tfl_sim *s, const tfl_objective *obj, int64_t nsteps, int64_t seg, void *ckpt,
+                             double F[2], void *stream)
+{
+    int rc = check_bound(s, true);
+    if (rc != TFL_OK) return rc;
+    if ((rc = check_obj(s, obj)) != TFL_OK) return rc;
+    if (nsteps < 1 || seg < 1) return fail(s, TFL_E_INVAL, "nsteps and seg must be >= 1");
+    if (!ckpt || !aligned(ckpt) || !F) return fail(s, TFL_E_INVAL, "checkpoint buffer must be aligned, F non-null");
+    s->ckpt_valid = false;
+    hipStream_t st = (hipStream_t)stream;
+    return s->esz == 8 ? forward_ckpt<double>(s, obj, nsteps, seg, ckpt, F, st)
+                       : forward_ckpt<float>(s, obj, nsteps, seg, ckpt, F, st);
+}
+
+int tfl_adjoint(tfl_sim *s, const tfl_objective *obj, int64_t nsteps, int64_t seg, const void *ckpt,
+                const double F[2], void *snap, void *adj, double *grad_ell, double *grad_sigma, void *stream)
+{
+    int rc = check_bound(s, true);
+    if (rc != TFL_OK) return rc;
+    if ((rc = check_obj(s, obj)) != TFL_OK) return rc;
+    if (!s->ckpt_valid || s->ckpt_nsteps != nsteps || s->ckpt_seg != seg)
+        return fail(s, TFL_E_STATE, "no checkpointed forward run with these nsteps and seg");
+    if (!ckpt || !snap || !adj || !grad_ell || !grad_sigma || !F)
+        return fail(s, TFL_E_INVAL, "null buffer");
+    if (!aligned(ckpt) || !aligned(snap) || !aligned(adj) || !aligned(grad_ell) || !aligned(grad_sigma))
+        return fail(s, TFL_E_INVAL, "device buffers must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    return s->esz == 8 ? adjoint<double>(s, obj, nsteps, seg, ckpt, F, snap, adj, grad_ell, grad_sigma, st)
+                       : adjoint<float>(s, obj, nsteps, seg, ckpt, F, snap, adj, grad_ell, grad_sigma, st);
+}
+
+}  // extern "C"

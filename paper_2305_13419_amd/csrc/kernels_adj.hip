@@ -1,0 +1,353 @@
+// Reverse-mode (adjoint) sweeps of the two-fluid FDTD step for gfx950.
+//
+// One forward step is F2 o F1 with
+//   F1 (H pass): psiH' = bh psiH + ch D E;  H' = H - dt/mu0 (kh D E + psiH')
+//   F2 (E pass): Js' = Js + j E;  psiE' = bn psiE + cn D* H';
+//                E' = a E + b (curl_psi H' - Js')            (0 on PEC-wall edges)
+// (Algorithm 1 with the half steps fused, Sec. 3).  The adjoint step is
+// F1^T o F2^T, evaluated as two sweeps that mirror the forward passes:
+//   face sweep: lH += curl(W) with W = b lE (+ the E-side PML transposes)
+//               and the H-side PML adjoint variables;
+//   edge sweep: lE += -dt/mu0 curl^T lH (+ H-side PML transposes), the
+//               objective source, then the edge-local part of F2^T for the
+//               preceding step (mu = b lE, lJ, gradient accumulation,
+//               lE <- a lE + j lJ).
+// Gradients with respect to the per-edge j = dt ell/mu0 and sigma follow from
+// dJs'/d ell = dt E/mu0 and dE'/d sigma = -b (theta E'_pre + (1-theta) E).
+// The multiplication of a PML adjoint variable by its decay b is applied when
+// the variable is next read, so each sweep writes its variables once.
+#include "fdtd_common.h"
+
+namespace tfl {
+namespace {
+
+// curl term signs: component c differentiated along axis a enters with +1 when
+// a = c+1 (mod 3) and -1 when a = c+2 (mod 3), for both curls.
+__device__ __forceinline__ int curl_sign(int c, int a) { return ((c + 1) % 3 == a) ? 1 : -1; }
+// compact PML array of axis a that holds component c
+__device__ __forceinline__ int psi_slot(int c, int a) { return ((c - a + 3) % 3) - 1; }
+
+template <typename T>
+__device__ __forceinline__ long long psi_index(const PmlAxis<T> &P, int a, int nx, int ny, int i, int j, int k, int s)
+{
+    if (a == 0) return ((long long)k * ny + j) * P.P + s;
+    if (a == 1) return ((long long)k * P.P + s) * nx + i;
+    return ((long long)s * ny + j) * nx + i;
+}
+
+// W of an E-side term (edge component c, axis a) at edge (i,j,k): the adjoint of
+// the stretched backward difference, sg kn mu + cn tot.
+template <typename T>
+__device__ __forceinline__ T w_edge(const AdjArgs<T> &A, int c, int a, int i, int j, int k, T muv)
+{
+    const PmlAxis<T> &P = A.f.pml[a];
+    const T sg = T(curl_sign(c, a));
+    if (!P.on) return sg * muv;
+    const int pos = a == 0 ? i : (a == 1 ? j : k);
+    const int s = slab_slot(pos, P.lo, P.hi, P.n);
+    if (s < 0) return sg * muv;
+    const T tot = A.lpsiE[a][psi_slot(c, a)][psi_index(P, a, A.f.g.nx, A.f.g.ny, i, j, k, s)];
+    return sg * P.kn[pos] * muv + P.cn[pos] * tot;
+}
+
+// WH of an H-side term (face component h, axis a) at face (i,j,k): the adjoint
+// of the stretched forward difference, -dt/mu0 sg kh lH + ch tot.
+template <typename T>
+__device__ __forceinline__ T w_face(const AdjArgs<T> &A, int h, int a, int i, int j, int k, T lh)
+{
+    const PmlAxis<T> &P = A.f.pml[a];
+    const T sg = T(curl_sign(h, a));
+    const T hdt = A.f.hdt;
+    if (!P.on) return -hdt * sg * lh;
+    const int pos = a == 0 ? i : (a == 1 ? j : k);
+    const int s = slab_slot(pos, P.lo, P.hi, P.n);
+    if (s < 0) return -hdt * sg * lh;
+    const T tot = A.lpsiH[a][psi_slot(h, a)][psi_index(P, a, A.f.g.nx, A.f.g.ny, i, j, k, s)];
+    return -hdt * sg * P.kh[pos] * lh + P.ch[pos] * tot;
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_coords(const StepArgs<T> &f, int &i, int &j, int &k0, int &k1)
+{
+    const int nb = f.ntiles_x * f.ntiles_y * f.ntiles_z;
+    const int t = logical_block(blockIdx.x, nb);
+    const int tx = t % f.ntiles_x;
+    const int tr = t / f.ntiles_x;
+    const int ty = tr % f.ntiles_y;
+    const int tz = tr / f.ntiles_y;
+    i = tx * kTileX + threadIdx.x;
+    j = ty * kTileY + threadIdx.y;
+    k0 = tz * kTileZ;
+    k1 = min(k0 + kTileZ, f.g.nz);
+}
+
+// ---------------------------------------------------------------------------
+// Face sweep: lH'' = lH + curl W (F2^T), then the H-side PML variables (F1^T)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kTileX *kTileY) void adj_face_kernel(const AdjArgs<T> A)
+{
+    int i, j, k0, k1;
+    tile_coords(A.f, i, j, k0, k1);
+    const int nx = A.f.g.nx, ny = A.f.g.ny, nz = A.f.g.nz;
+    if (i >= nx || j >= ny) return;
+    const long long sxy = A.f.g.sxy;
+    const int ip = (i + 1 == nx) ? 0 : i + 1;
+    const int jp = (j + 1 == ny) ? 0 : j + 1;
+    const long long r0 = (long long)j * nx, r1 = (long long)jp * nx;
+    const T rdx = A.f.rd[0], rdy = A.f.rd[1], rdz = A.f.rd[2];
+    const T *mx = A.mu[0], *my = A.mu[1], *mz = A.mu[2];
+    for (int k = k0; k < k1; ++k) {
+        const int kp = (k + 1 == nz) ? 0 : k + 1;
+        const long long b0 = (long long)k * sxy, b1 = (long long)kp * sxy;
+        const long long c = b0 + r0 + i;
+        const T mx0 = mx[c], my0 = my[c], mz0 = mz[c];
+        // lHx: terms (Ey, z) and (Ez, y)
+        const T wyz0 = w_edge(A, 1, 2, i, j, k, my0), wyz1 = w_edge(A, 1, 2, i, j, kp, my[b1 + r0 + i]);
+        const T wzy0 = w_edge(A, 2, 1, i, j, k, mz0), wzy1 = w_edge(A, 2, 1, i, jp, k, mz[b0 + r1 + i]);
+        // lHy: terms (Ex, z) and (Ez, x)
+        const T wxz0 = w_edge(A, 0, 2, i, j, k, mx0), wxz1 = w_edge(A, 0, 2, i, j, kp, mx[b1 + r0 + i]);
+        const T wzx0 = w_edge(A, 2, 0, i, j, k, mz0), wzx1 = w_edge(A, 2, 0, ip, j, k, mz[b0 + r0 + ip]);
+        // lHz: terms (Ex, y) and (Ey, x)
+        const T wxy0 = w_edge(A, 0, 1, i, j, k, mx0), wxy1 = w_edge(A, 0, 1, i, jp, k, mx[b0 + r1 + i]);
+        const T wyx0 = w_edge(A, 1, 0, i, j, k, my0), wyx1 = w_edge(A, 1, 0, ip, j, k, my[b0 + r0 + ip]);
+        const T lh[3] = {A.lH[0][c] + (wyz0 - wyz1) * rdz + (wzy0 - wzy1) * rdy,
+                         A.lH[1][c] + (wxz0 - wxz1) * rdz + (wzx0 - wzx1) * rdx,
+                         A.lH[2][c] + (wxy0 - wxy1) * rdy + (wyx0 - wyx1) * rdx};
+        for (int h = 0; h < 3; ++h) A.lH[h][c] = lh[h];
+        // H-side PML adjoint variables: tot = bh * stored + (-dt/mu0) sg lH''
+        const int pos[3] = {i, j, k};
+        for (int a = 0; a < 3; ++a) {
+            const PmlAxis<T> &P = A.f.pml[a];
+            if (!P.on) continue;
+            const int s = slab_slot(pos[a], P.lo, P.hi, P.n);
+            if (s < 0) continue;
+            const long long pi = psi_index(P, a, nx, ny, i, j, k, s);
+            for (int q = 0; q < 2; ++q) {
+                const int h = (a + 1 + q) % 3;
+                T *ps = A.lpsiH[a][q];
+                ps[pi] = P.bh[pos[a]] * ps[pi] - A.f.hdt * T(curl_sign(h, a)) * lh[h];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Edge sweep: lE += curl^T WH (F1^T), objective source, then the edge-local
+// part of F2^T of the preceding step with the gradient accumulation.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void edge_cells(const StepArgs<T> &f, int comp, int i, int j, int k, T e[4], T s[4],
+                                           T l[4])
+{
+    const int nx = f.g.nx, ny = f.g.ny, nz = f.g.nz;
+    const int im = (i == 0) ? nx - 1 : i - 1;
+    const int jm = (j == 0) ? ny - 1 : j - 1;
+    const int km = (k == 0) ? nz - 1 : k - 1;
+    auto id = [&](int ii, int jj, int kk) { return ((long long)kk * ny + jj) * nx + ii; };
+    long long q[4];
+    if (comp == 0) { q[0] = id(i, j, k); q[1] = id(i, j, km); q[2] = id(i, jm, k); q[3] = id(i, jm, km); }
+    else if (comp == 1) { q[0] = id(i, j, k); q[1] = id(im, j, k); q[2] = id(i, j, km); q[3] = id(im, j, km); }
+    else { q[0] = id(i, j, k); q[1] = id(i, jm, k); q[2] = id(im, j, k); q[3] = id(im, jm, k); }
+    for (int t = 0; t < 4; ++t) {
+        e[t] = f.eps[q[t]];
+        s[t] = f.sig[q[t]];
+        l[t] = f.ell[q[t]];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTileX *kTileY) void adj_edge_kernel(const AdjArgs<T> A)
+{
+    int i, j, k0, k1;
+    tile_coords(A.f, i, j, k0, k1);
+    const int nx = A.f.g.nx, ny = A.f.g.ny, nz = A.f.g.nz;
+    if (i >= nx || j >= ny) return;
+    const long long sxy = A.f.g.sxy;
+    const int im = (i == 0) ? nx - 1 : i - 1;
+    const int jm = (j == 0) ? ny - 1 : j - 1;
+    const long long r0 = (long long)j * nx, rm = (long long)jm * nx;
+    const T rdx = A.f.rd[0], rdy = A.f.rd[1], rdz = A.f.rd[2];
+    const T dt = A.f.dt, theta = A.f.theta, hdt = A.f.hdt;
+    for (int k = k0; k < k1; ++k) {
+        const int km = (k == 0) ? nz - 1 : k - 1;
+        const long long b0 = (long long)k * sxy, bm = (long long)km * sxy;
+        const long long c = b0 + r0 + i;
+        T le[3] = {A.lE[0][c], A.lE[1][c], A.lE[2][c]};
+        if (A.doC) {
+            const T *hx = A.lH[0], *hy = A.lH[1], *hz = A.lH[2];
+            const T hx0 = hx[c], hy0 = hy[c], hz0 = hz[c];
+            // Ex: terms (Hy, z) and (Hz, y)
+            le[0] += (w_face(A, 1, 2, i, j, km, hy[bm + r0 + i]) - w_face(A, 1, 2, i, j, k, hy0)) * rdz +
+                     (w_face(A, 2, 1, i, jm, k, hz[b0 + rm + i]) - w_face(A, 2, 1, i, j, k, hz0)) * rdy;
+            // Ey: terms (Hx, z) and (Hz, x)
+            le[1] += (w_face(A, 0, 2, i, j, km, hx[bm + r0 + i]) - w_face(A, 0, 2, i, j, k, hx0)) * rdz +
+                     (w_face(A, 2, 0, im, j, k, hz[b0 + r0 + im]) - w_face(A, 2, 0, i, j, k, hz0)) * rdx;
+            // Ez: terms (Hx, y) and (Hy, x)
+            le[2] += (w_face(A, 0, 1, i, jm, k, hx[b0 + rm + i]) - w_face(A, 0, 1, i, j, k, hx0)) * rdy +
+                     (w_face(A, 1, 0, im, j, k, hy[b0 + r0 + im]) - w_face(A, 1, 0, i, j, k, hy0)) * rdx;
+        }
+        if (A.obj && i >= A.ob[0] && i < A.ob[1] && j >= A.ob[2] && j < A.ob[3] && k >= A.ob[4] && k < A.ob[5])
+            le[A.ocomp] += (T)A.og;
+        if (!A.doA) {
+            for (int q = 0; q < 3; ++q) A.lE[q][c] = le[q];
+            continue;
+        }
+        const int pos[3] = {i, j, k};
+        for (int q = 0; q < 3; ++q) {
+            // PEC wall: E' = 0 there, so its adjoint does not propagate
+            bool wall = false;
+            for (int a = 0; a < 3; ++a)
+                if (a != q && A.f.pml[a].on && pos[a] == 0) wall = true;
+            const T lEp = wall ? T(0) : le[q];
+            T e4[4], s4[4], l4[4];
+            edge_cells(A.f, q, i, j, k, e4, s4, l4);
+            T eps, sig, ell;
+            edge_material(e4, s4, l4, eps, sig, ell);
+            const T sdt = sig * dt;
+            const T inv = T(1) / (eps + theta * sdt);
+            const T ca = (eps - (T(1) - theta) * sdt) * inv;
+            const T cb = dt * inv;
+            const T mu = cb * lEp;
+            const T En = A.En[q][c];
+            T ljt = T(0);
+            if (ell > T(0)) {
+                ljt = A.lJ[q][c] - mu;
+                A.lJ[q][c] = ljt;
+                A.gL[q][c] += (double)hdt * (double)ljt * (double)En;
+            }
+            A.gS[q][c] += -(double)lEp * (double)cb * ((double)theta * (double)A.Ep[q][c] + (1.0 - (double)theta) * (double)En);
+            A.mu[q][c] = mu;
+            A.lE[q][c] = ca * lEp + hdt * ell * ljt;
+            // E-side PML adjoint variables: tot = bn * stored + sg mu
+            for (int a = 0; a < 3; ++a) {
+                if (a == q) continue;
+                const PmlAxis<T> &P = A.f.pml[a];
+                if (!P.on) continue;
+                const int s = slab_slot(pos[a], P.lo, P.hi, P.n);
+                if (s < 0) continue;
+                T *ps = A.lpsiE[a][psi_slot(q, a)];
+                const long long pi = psi_index(P, a, nx, ny, i, j, k, s);
+                ps[pi] = P.bn[pos[a]] * ps[pi] + T(curl_sign(q, a)) * mu;
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void adj_initial_kick_kernel(const AdjArgs<T> A)
+{
+    const int nx = A.f.g.nx, ny = A.f.g.ny;
+    const long long N = A.f.g.sxy * A.f.g.nz;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx);
+        const long long r = c / nx;
+        const int j = (int)(r % ny);
+        const int k = (int)(r / ny);
+        for (int q = 0; q < 3; ++q) {
+            T e4[4], s4[4], l4[4];
+            edge_cells(A.f, q, i, j, k, e4, s4, l4);
+            T eps, sig, ell;
+            edge_material(e4, s4, l4, eps, sig, ell);
+            if (ell > T(0))
+                A.gL[q][c] += -0.5 * (double)A.f.hdt * (double)A.lJ[q][c] * (double)A.En[q][c];
+        }
+    }
+}
+
+// Cell (i,j,k) owns 12 edges: Ex at (i, j+u, k+v), Ey at (i+u, j, k+v), Ez at
+// (i+u, j+v, k).  The derivative of the edge rule gives weight 1/|S| to each
+// superconducting cell of a superconducting edge (S its superconducting cells)
+// and 1/4 to every cell of a normal edge (sigma only).
+template <typename T>
+__global__ void adj_edge_to_cell_kernel(const AdjArgs<T> A, double *gl_cell, double *gs_cell)
+{
+    const int nx = A.f.g.nx, ny = A.f.g.ny, nz = A.f.g.nz;
+    const long long N = A.f.g.sxy * nz;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx);
+        const long long r = c / nx;
+        const int j = (int)(r % ny);
+        const int k = (int)(r / ny);
+        const bool self_sc = A.f.ell[c] > T(0);
+        double gl = 0.0, gs = 0.0;
+        for (int q = 0; q < 3; ++q)
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 2; ++v) {
+                    int ei = i, ej = j, ek = k;
+                    if (q == 0) { ej += u; ek += v; }
+                    else if (q == 1) { ei += u; ek += v; }
+                    else { ei += u; ej += v; }
+                    if (ei == nx) ei = 0;
+                    if (ej == ny) ej = 0;
+                    if (ek == nz) ek = 0;
+                    T e4[4], s4[4], l4[4];
+                    edge_cells(A.f, q, ei, ej, ek, e4, s4, l4);
+                    int nsc = 0;
+                    for (int t = 0; t < 4; ++t) nsc += (l4[t] > T(0)) ? 1 : 0;
+                    const long long e = ((long long)ek * ny + ej) * nx + ei;
+                    if (nsc > 0) {
+                        if (self_sc) {
+                            gl += A.gL[q][e] / (double)nsc;
+                            gs += A.gS[q][e] / (double)nsc;
+                        }
+                    } else {
+                        gs += 0.25 * A.gS[q][e];
+                    }
+                }
+        gl_cell[c] = gl;
+        gs_cell[c] = gs;
+    }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_adj_faces(const AdjArgs<T> &a, hipStream_t s)
+{
+    const int nb = a.f.ntiles_x * a.f.ntiles_y * a.f.ntiles_z;
+    hipLaunchKernelGGL(adj_face_kernel<T>, dim3(nb), dim3(kTileX, kTileY), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_edges(const AdjArgs<T> &a, hipStream_t s)
+{
+    const int nb = a.f.ntiles_x * a.f.ntiles_y * a.f.ntiles_z;
+    hipLaunchKernelGGL(adj_edge_kernel<T>, dim3(nb), dim3(kTileX, kTileY), 0, s, a);
+    return hipGetLastError();
+}
+
+static int grid_blocks(long long N)
+{
+    const long long nb = (N + 255) / 256;
+    return (int)(nb < 65536 ? nb : 65536);
+}
+
+template <typename T>
+hipError_t launch_adj_initial_kick(const AdjArgs<T> &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(adj_initial_kick_kernel<T>, dim3(grid_blocks(a.f.g.sxy * a.f.g.nz)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_edge_to_cell(const AdjArgs<T> &a, double *grad_ell, double *grad_sig, hipStream_t s)
+{
+    hipLaunchKernelGGL(adj_edge_to_cell_kernel<T>, dim3(grid_blocks(a.f.g.sxy * a.f.g.nz)), dim3(256), 0, s, a,
+                       grad_ell, grad_sig);
+    return hipGetLastError();
+}
+
+#define TFL_ADJ_INSTANTIATE(T)                                                        \
+    template hipError_t launch_adj_faces<T>(const AdjArgs<T> &, hipStream_t);         \
+    template hipError_t launch_adj_edges<T>(const AdjArgs<T> &, hipStream_t);         \
+    template hipError_t launch_adj_initial_kick<T>(const AdjArgs<T> &, hipStream_t);  \
+    template hipError_t launch_adj_edge_to_cell<T>(const AdjArgs<T> &, double *, double *, hipStream_t);
+
+TFL_ADJ_INSTANTIATE(double)
+TFL_ADJ_INSTANTIATE(float)
+
+}  // namespace tfl

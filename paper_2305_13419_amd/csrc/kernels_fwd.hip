@@ -15,75 +15,16 @@
 // L1/L2.  Blocks are renumbered so that each XCD (blocks are dealt to the 8
 // XCDs round robin) receives a contiguous range of tiles, keeping the halo
 // rows of neighbouring tiles in the same L2.
-#include "tfl_internal.h"
+#include "fdtd_common.h"
 
 namespace tfl {
 namespace {
-
-__device__ __forceinline__ int logical_block(int b, int nblocks)
-{
-    const int q = nblocks >> 3, r = nblocks & 7;
-    const int x = b & 7, m = b >> 3;
-    return x * q + min(x, r) + m;
-}
-
-__device__ __forceinline__ int slab_slot(int i, int lo, int hi, int n)
-{
-    if (i < lo) return i;
-    if (i >= n - hi) return lo + i - (n - hi);
-    return -1;
-}
-
-template <typename T>
-__device__ __forceinline__ T inv_count(int c)
-{
-    return c == 1 ? T(1) : (c == 2 ? T(0.5) : (c == 3 ? T(1) / T(3) : T(0.25)));
-}
-
-// Per-edge material of the four cells q0..q3 sharing an edge (Sec. 3): if any
-// cell is superconducting (ell > 0) the edge takes the mean over those cells,
-// otherwise the mean over all four.  Summed in q order.
-template <typename T>
-__device__ __forceinline__ void edge_material(const T e[4], const T s[4], const T l[4], T &eps, T &sig, T &ell)
-{
-    const bool anysc = (l[0] > T(0)) | (l[1] > T(0)) | (l[2] > T(0)) | (l[3] > T(0));
-    T se = T(0), ss = T(0), sl = T(0);
-    int cnt = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const bool use = !anysc || (l[q] > T(0));
-        se += use ? e[q] : T(0);
-        ss += use ? s[q] : T(0);
-        sl += use ? l[q] : T(0);
-        cnt += use ? 1 : 0;
-    }
-    const T ic = inv_count<T>(cnt);
-    eps = T(kEps0) * (se * ic);
-    sig = ss * ic;
-    ell = sl * ic;
-}
-
-// Stretched derivative: d <- kappa^-1 d + psi, psi <- b psi + c d.
-template <typename T>
-__device__ __forceinline__ T stretch(T d, T *psi, long long pidx, T b, T c, T kinv)
-{
-    const T p = b * psi[pidx] + c * d;
-    psi[pidx] = p;
-    return kinv * d + p;
-}
-
-template <typename T>
-__device__ __forceinline__ T stretch_virtual(T d, const T *psi, long long pidx, T b, T c, T kinv)
-{
-    const T p = b * psi[pidx] + c * d;
-    return kinv * d + p;
-}
 
 // ---------------------------------------------------------------------------
 // H pass (Faraday's law)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kTileX *kTileY) void h_pass_kernel(const StepArgs<T> a)
+__global__ __launch_bounds__(kTileX *kTileY, TFL_MIN_WAVES) void h_pass_kernel(const StepArgs<T> a)
 {
     const int nb = a.ntiles_x * a.ntiles_y * a.ntiles_z;
     const int t = logical_block(blockIdx.x, nb);
@@ -179,7 +120,7 @@ __device__ __forceinline__ void update_edge(T *__restrict__ E, T *__restrict__ J
 }
 
 template <typename T>
-__global__ __launch_bounds__(kTileX *kTileY) void e_pass_kernel(const StepArgs<T> a)
+__global__ __launch_bounds__(kTileX *kTileY, TFL_MIN_WAVES) void e_pass_kernel(const StepArgs<T> a)
 {
     const int nb = a.ntiles_x * a.ntiles_y * a.ntiles_z;
     const int t = logical_block(blockIdx.x, nb);
@@ -310,7 +251,7 @@ constexpr int kProbeThreads = 256;
 template <typename T>
 __global__ __launch_bounds__(kProbeThreads) void probe_kernel(const ProbeArgs<T> a)
 {
-    const ProbeDesc &p = a.p[blockIdx.x];
+    const ProbeDesc &p = a.p[a.first + blockIdx.x];
     const T *E = a.E[p.comp];
     const int wx = p.i1 - p.i0, wy = p.j1 - p.j0, wz = p.k1 - p.k0;
     const long long cnt = (long long)wx * wy * wz;

@@ -1,0 +1,67 @@
+// Host-side state of a simulation handle and the helpers shared by the
+// forward (api.cpp) and adjoint (api_adj.cpp) drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "tfl_internal.h"
+
+struct tfl_sim {
+    tfl_config cfg;
+    long long N = 0;
+    int esz = 8;
+    void *E[3] = {nullptr, nullptr, nullptr};
+    void *H[3] = {nullptr, nullptr, nullptr};
+    void *J[3] = {nullptr, nullptr, nullptr};
+    const void *eps = nullptr, *sig = nullptr, *ell = nullptr;
+    void *work = nullptr;
+    double *scratch = nullptr;
+    bool state_bound = false, work_bound = false, maps_bound = false;
+    size_t work_bytes = 0;
+    // workspace layout (element offsets in units of the field type)
+    size_t table_off[3] = {0, 0, 0};   // 6 tables of n[a] entries per CPML axis
+    size_t psi_off[3] = {0, 0, 0};     // 4 arrays of slab size per CPML axis
+    size_t psi_count[3] = {0, 0, 0};   // elements per auxiliary array
+    int64_t step = 0;
+    bool sampled0 = false;
+    bool probes_dirty = true;  // descriptors not yet uploaded to scratch
+    std::vector<tfl::SourceDesc> src;
+    std::vector<tfl::ProbeDesc> probe;
+    double max_ell = 0.0;
+    // last tfl_forward_checkpointed run
+    bool ckpt_valid = false;
+    int64_t ckpt_n0 = 0, ckpt_nsteps = 0, ckpt_seg = 0;
+    std::string err;
+};
+
+
+namespace tfl {
+namespace detail {
+
+int fail(tfl_sim *s, int code, const char *fmt, ...);
+int hip_fail(tfl_sim *s, hipError_t e, const char *where);
+bool aligned(const void *p);
+size_t round256(size_t bytes);
+int check_bound(tfl_sim *s, bool need_maps);
+bool box_ok(const tfl_config &c, const int64_t *b);
+template <typename T> StepArgs<T> make_args(const tfl_sim *s);
+// nsteps forward steps; ev (optional) receives 2 nsteps + 1 events; with
+// probes = false the probe kernels are skipped (recomputation in the adjoint).
+template <typename T> int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev = nullptr,
+                                  bool probes = true);
+int copy_state(tfl_sim *s, void *dst, const void *src, bool save, hipStream_t st);
+
+// scratch buffer layout: reduction partials, the objective DFT, probe descriptors
+constexpr size_t kScratchBytes = 1 << 17;
+constexpr int kRedBlocks = 1024;            // reductions use doubles [0, 5 * kRedBlocks)
+constexpr size_t kObjectiveSlot = 6144;     // doubles [6144, 6146): objective DFT
+constexpr size_t kProbeDescOffset = 65536;  // bytes: TFL_MAX_PROBES + 1 ProbeDesc
+static_assert(kProbeDescOffset + (TFL_MAX_PROBES + 1) * sizeof(ProbeDesc) <= kScratchBytes, "scratch too small");
+// Upload the probe descriptors to scratch when they changed (synchronises).
+int upload_probes(tfl_sim *s, hipStream_t st);
+
+}  // namespace detail
+}  // namespace tfl

@@ -15,9 +15,18 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 // Tile of the 2.5-D sweeps: a block covers kTileX x kTileY columns of the
 // x-y plane and marches kTileZ planes along z, keeping the z neighbour in
 // registers.  kTileX is one 64-wide wavefront.
+#ifndef TFL_TILE_Y
+#define TFL_TILE_Y 4
+#endif
+#ifndef TFL_TILE_Z
+#define TFL_TILE_Z 32
+#endif
+#ifndef TFL_MIN_WAVES
+#define TFL_MIN_WAVES 1
+#endif
 constexpr int kTileX = 64;
-constexpr int kTileY = 4;
-constexpr int kTileZ = 32;
+constexpr int kTileY = TFL_TILE_Y;
+constexpr int kTileZ = TFL_TILE_Z;
 
 struct GridDims {
     int nx, ny, nz;
@@ -86,13 +95,33 @@ struct SrcArgs {
     SourceDesc src[TFL_MAX_SOURCES];
 };
 
+// Probe descriptors live in device memory (the bound scratch buffer); a
+// launch samples probes [first, first + gridDim.x).
 template <typename T>
 struct ProbeArgs {
     GridDims g;
     const T *E[3];
     long long n;
     double dt;
-    ProbeDesc p[TFL_MAX_PROBES];
+    const ProbeDesc *p;
+    int first;
+};
+
+// Reverse-mode (adjoint) sweep arguments.  Adjoint fields are stored in the
+// field precision; gradient accumulators are FP64.  lpsiH/lpsiE follow the
+// compact slab layout of the forward auxiliary variables.
+template <typename T>
+struct AdjArgs {
+    StepArgs<T> f;
+    T *lE[3], *lH[3], *lJ[3], *mu[3];
+    T *lpsiH[3][2], *lpsiE[3][2];
+    double *gL[3], *gS[3];
+    const T *En[3];  // E^m: input E of the forward step m -> m+1 (A part)
+    const T *Ep[3];  // E^{m+1} before the sources (A part)
+    int doC, doA;
+    int obj;         // add og to lE[ocomp] on the objective box
+    int ocomp, ob[6];
+    double og;
 };
 
 // Host-side launchers (kernels_fwd.hip).
@@ -113,5 +142,14 @@ template <typename T>
 hipError_t launch_map_stats(const T *eps, const T *sig, const T *ell, long long n, double *scratch, int nblocks,
                             hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+// Adjoint launchers (kernels_adj.hip).
+template <typename T> hipError_t launch_adj_faces(const AdjArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_adj_edges(const AdjArgs<T> &a, hipStream_t s);
+// gL += -dt/(2 mu0) lJ E^0 on superconducting edges (dependence of Js^{-1/2} on ell).
+template <typename T> hipError_t launch_adj_initial_kick(const AdjArgs<T> &a, hipStream_t s);
+// Per-edge FP64 accumulators -> per-cell gradients (derivative of the edge rule).
+template <typename T>
+hipError_t launch_adj_edge_to_cell(const AdjArgs<T> &a, double *grad_ell, double *grad_sig, hipStream_t s);
 
 }  // namespace tfl

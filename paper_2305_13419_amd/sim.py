@@ -193,3 +193,42 @@ class Simulation:
 
     def load_state(self, src):
         self._call("tfl_load_state", ctypes.c_void_p(src.data_ptr()), _stream())
+
+    # -- adjoint ------------------------------------------------------------
+    @staticmethod
+    def _objective(comp, box, f0):
+        o = L.tfl_objective()
+        o.comp = int(comp)
+        for q in range(6):
+            o.box[q] = int(box[q])
+        o.f0 = float(f0)
+        return o
+
+    def adjoint_buffers(self, nsteps, seg):
+        """Caller-owned device buffers for a checkpointed run: (checkpoints, snapshots, workspace)."""
+        c, s, a = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        self._call("tfl_adjoint_sizes", ctypes.c_int64(int(nsteps)), ctypes.c_int64(int(seg)), ctypes.byref(c),
+                   ctypes.byref(s), ctypes.byref(a))
+        mk = lambda n: torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)  # noqa: E731
+        return mk(c.value), mk(s.value), mk(a.value)
+
+    def forward_checkpointed(self, objective, nsteps, seg, ckpt):
+        """Run nsteps with checkpoints every seg steps; returns F (complex) of the objective
+        (comp, box, f0): J = |F|^2, F = sum_n dt exp(-i 2 pi f0 n dt) sum_box E_comp^n."""
+        o = self._objective(*objective)
+        F = (ctypes.c_double * 2)()
+        self._call("tfl_forward_checkpointed", ctypes.byref(o), ctypes.c_int64(int(nsteps)), ctypes.c_int64(int(seg)),
+                   ctypes.c_void_p(ckpt.data_ptr()), F, _stream())
+        return complex(F[0], F[1])
+
+    def adjoint(self, objective, nsteps, seg, ckpt, F, snap, work):
+        """Per-cell FP64 gradients (dJ/d inv_lambda2, dJ/d sigma_n) of the last checkpointed run."""
+        o = self._objective(*objective)
+        Fa = (ctypes.c_double * 2)(F.real, F.imag)
+        gl = torch.empty(self.shape3, dtype=torch.float64, device=self.device)
+        gs = torch.empty(self.shape3, dtype=torch.float64, device=self.device)
+        self._call("tfl_adjoint", ctypes.byref(o), ctypes.c_int64(int(nsteps)), ctypes.c_int64(int(seg)),
+                   ctypes.c_void_p(ckpt.data_ptr()), Fa, ctypes.c_void_p(snap.data_ptr()),
+                   ctypes.c_void_p(work.data_ptr()), ctypes.c_void_p(gl.data_ptr()), ctypes.c_void_p(gs.data_ptr()),
+                   _stream())
+        return gl, gs

@@ -1,0 +1,134 @@
+"""Adjoint (reverse-time) gradients of the HIP path against the oracle's adjoint
+and against central finite differences of the HIP FP64 forward."""
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleSim
+from paper_2305_13419_amd import workloads
+from tests.helpers import MU0, WAVE_KIND, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def gpu_adjoint(wl, objective, N, seg, dtype, maps=None):
+    from paper_2305_13419_amd import Simulation
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"])
+    sim.set_materials(*[np.asarray(m, dtype=npdt) for m in (maps or wl["maps"])])
+    if wl["fields"] is None:
+        z = [np.zeros(sim.shape3, dtype=npdt)] * 3
+        sim.set_fields(z, z, z)
+    else:
+        sim.set_fields(*[[np.asarray(a, dtype=npdt) for a in grp] for grp in wl["fields"]])
+    for s in wl["sources"]:
+        sim.add_source(**s)
+    ckpt, snap, work = sim.adjoint_buffers(N, seg)
+    F = sim.forward_checkpointed(objective, N, seg, ckpt)
+    gl, gs = sim.adjoint(objective, N, seg, ckpt, F, snap, work)
+    torch.cuda.synchronize()
+    out = F, gl.cpu().numpy(), gs.cpu().numpy()
+    sim.close()
+    return out
+
+
+def oracle_adjoint(wl, objective, N, npdt=np.float64):
+    pml = wl["pml"]
+    o = OracleSim(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], pml=[0 if p is None else 1 for p in pml],
+                  npml=[(0, 0) if p is None else p for p in pml])
+    o.set_materials(*[np.asarray(m, dtype=npdt).astype(np.float64) for m in wl["maps"]])
+    sh = o.shape3
+    if wl["fields"] is None:
+        z = [np.zeros(sh)] * 3
+        o.set_fields(z, z, z)
+    else:
+        E, H, J = [[np.asarray(a, dtype=npdt).astype(np.float64) for a in grp] for grp in wl["fields"]]
+        o.set_fields(E, [h * MU0 for h in H], J)
+    for s in wl["sources"]:
+        o.add_source(s["comp"], s["box"], s["amplitude"], WAVE_KIND[s["waveform"]], s.get("freq", 0.0),
+                     s.get("t0", 0.0), s.get("tw", 1.0))
+    comp, box, f0 = objective
+    pid = o.add_probe(comp, box, 1, [f0])
+    return o.adjoint(N, pid, f0)
+
+
+CASES = [
+    dict(shape=(40, 9, 36), pml=(None, None, None), theta=1.0, fields=True, N=37, seg=8),
+    dict(shape=(34, 12, 40), pml=((5, 5), None, (4, 4)), theta=0.5, fields=False, N=40, seg=40),
+    dict(shape=(30, 14, 33), pml=((4, 3), (3, 4), (5, 2)), theta=0.7, fields=True, N=25, seg=1),
+    dict(shape=(70, 6, 35), pml=((6, 6), None, None), theta=1.0, fields=True, N=30, seg=7),
+]
+
+
+def make_case(c, seed=41):
+    wl = workloads.random_medium(c["shape"], seed=seed, pml=c["pml"], theta=c["theta"])
+    if not c["fields"]:
+        wl["fields"] = None
+    nx, ny, nz = c["shape"]
+    wl["sources"] = [dict(comp=1, box=(nx // 3, nx // 3 + 1, 0, ny, nz // 4, nz // 2), amplitude=2.0,
+                          waveform="mod_gauss", freq=3e14, t0=1.5e-15, tw=6e-16)]
+    objective = (1, (2 * nx // 3, 2 * nx // 3 + 1, 0, ny, 0, nz), 2.5e14)
+    return wl, objective
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_adjoint_fp64_matches_oracle_adjoint(case):
+    c = CASES[case]
+    wl, obj = make_case(c)
+    print(f"case {case}: {c}", flush=True)
+    F, gl, gs = gpu_adjoint(wl, obj, c["N"], c["seg"], torch.float64)
+    Jo, Fo, glo, gso = oracle_adjoint(wl, obj, c["N"])
+    print(f"  F rel {abs(F - Fo) / abs(Fo):.2e}  grad ell {rel_l2(gl, glo):.2e}  grad sigma {rel_l2(gs, gso):.2e}",
+          flush=True)
+    assert abs(F - Fo) <= 1e-12 * abs(Fo)
+    assert rel_l2(gl, glo) <= 1e-10
+    assert rel_l2(gs, gso) <= 1e-10
+    assert np.all(gl[wl["maps"][2] == 0] == 0.0)
+
+
+def test_adjoint_fp32_close_to_oracle():
+    c = CASES[0]
+    wl, obj = make_case(c)
+    F, gl, gs = gpu_adjoint(wl, obj, c["N"], c["seg"], torch.float32)
+    Jo, Fo, glo, gso = oracle_adjoint(wl, obj, c["N"], np.float32)
+    print(f"FP32: F rel {abs(F - Fo) / abs(Fo):.2e} grad ell {rel_l2(gl, glo):.2e} grad sigma {rel_l2(gs, gso):.2e}",
+          flush=True)
+    assert abs(F - Fo) <= 1e-5 * abs(Fo)
+    assert rel_l2(gl, glo) <= 1e-4
+    assert rel_l2(gs, gso) <= 1e-4
+
+
+def test_autograd_function_and_finite_differences():
+    """TwoFluidObjective returns J and, in backward, the adjoint gradients; they match central
+    differences of the HIP FP64 forward on superconducting cells (ell) and on any cell (sigma)."""
+    from paper_2305_13419_amd import AdjointProblem, TwoFluidObjective
+    c = CASES[1]
+    wl, obj = make_case(c)
+    eps, sig, ell = wl["maps"]
+    prob = AdjointProblem(wl["shape"], wl["spacing"], wl["dt"], eps, obj, c["N"], seg=10, theta=c["theta"],
+                          pml=c["pml"], sources=wl["sources"])
+    L = torch.tensor(ell, device="cuda", requires_grad=True)
+    S = torch.tensor(sig, device="cuda", requires_grad=True)
+    J = TwoFluidObjective.apply(L, S, prob)
+    J.backward()
+    gl, gs = L.grad.cpu().numpy(), S.grad.cpu().numpy()
+    Jo, Fo, glo, gso = oracle_adjoint(wl, obj, c["N"])
+    assert abs(J.item() / Jo - 1) < 1e-12
+    assert rel_l2(gl, glo) <= 1e-10 and rel_l2(gs, gso) <= 1e-10
+    rng = np.random.default_rng(4)
+    worst = 0.0
+    for g, m, ref, mi in ((gl, ell, 1e14, 0), (gs, sig, 1e4, 1)):
+        # cells whose map value stays non-negative under -h (sigma = 0 cells are excluded)
+        big = np.argwhere((np.abs(g) >= 1e-2 * np.abs(g).max()) & (m > 2e-6 * np.maximum(m, ref)))
+        for cell in big[rng.choice(len(big), 6, replace=False)]:
+            cell = tuple(cell)
+            h = 1e-6 * max(abs(m[cell]), ref)
+            vals = []
+            for sgn in (1, -1):
+                mm = [ell.copy(), sig.copy()]
+                mm[mi][cell] += sgn * h
+                vals.append(prob.forward(torch.tensor(mm[0], device="cuda"), torch.tensor(mm[1], device="cuda")))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            worst = max(worst, abs(g[cell] - fd) / abs(fd))
+    print(f"max relative FD error {worst:.2e}", flush=True)
+    assert worst <= 1e-4
