@@ -241,11 +241,51 @@ int tfl_forward_checkpointed(tfl_sim *sim, const tfl_objective *obj, int64_t nst
  * seg and ckpt; F as returned by it).  Writes dJ/d inv_lambda2 and
  * dJ/d sigma_n per cell to grad_ell and grad_sigma (device FP64, N each).
  * snap and adj are device buffers of snap_bytes and adj_bytes.  Probes are
- * not sampled during the recomputation.  On return the state and step index
- * are those after the first segment of the run; restore a saved state to
- * continue from elsewhere.  TFL_E_STATE if no matching forward run exists. */
+ * not sampled during the recomputation.  On return the state arrays hold
+ * intermediate values of the recomputation: load a saved state (and set the
+ * step index) before stepping again.  TFL_E_STATE if no matching forward run
+ * exists. */
 int tfl_adjoint(tfl_sim *sim, const tfl_objective *obj, int64_t nsteps, int64_t seg, const void *ckpt,
                 const double F[2], void *snap, void *adj, double *grad_ell, double *grad_sigma, void *stream);
+
+/* ----------------------------------------------------------------------
+ * Resonance frequency and quality factor from a ringdown (Sec. 5, Table 7)
+ *
+ * The paper extracts f and Q from probe time series with ESPRIT; this
+ * library fits a linear predictor instead (Prony's method): the series
+ * x_m = series[start + m*decim], m = 0 .. count-1, is modelled as
+ * x_m = sum_{k=1}^{P} a_k x_{m-k}; the GPU forms the FP64 normal equations
+ * (Gram matrix of the lagged samples) and the host solves the P x P system
+ * (refined twice with the residual correction formed on the device) and finds
+ * the roots z of z^P - a_1 z^{P-1} - ... - a_P.  Each root gives a mode
+ * z = exp((-alpha + i 2 pi f) decim dt); the modes' complex amplitudes follow
+ * from a least-squares fit of the window; Q = pi f / alpha.
+ * ---------------------------------------------------------------------- */
+#define TFL_FIT_MAX_ORDER 16
+
+typedef struct {
+    int64_t start, count, decim;  /* window of the probe series and decimation  */
+    int32_t order;                /* P <= TFL_FIT_MAX_ORDER; 0: the numerical rank of
+                                     the order-16 normal matrix (eigenvalues above
+                                     1e-8 of the largest), at least 2             */
+    double f_hint;                /* report the largest-amplitude mode with f in
+                                     [0.5, 1.5] f_hint (Hz); <= 0 or none there:
+                                     the largest-amplitude mode with f > 0        */
+} tfl_fit_req;
+
+typedef struct {
+    double f0, alpha, Q;          /* Hz, 1/s, pi f0 / alpha                         */
+    double residual;              /* prediction residual energy / signal energy     */
+    int32_t order;                /* order used                                      */
+    int32_t nmodes;               /* roots found                                     */
+    double modes[2 * TFL_FIT_MAX_ORDER]; /* (f_m, alpha_m) of every root              */
+} tfl_fit_result;
+
+/* Fit the series of probe `probe_id` (its FP64 device buffer).  Requires
+ * count > order and start + (count-1)*decim < capacity.  Synchronises
+ * `stream`.  TFL_E_INVAL on bad windows, TFL_E_NONFINITE if the normal
+ * equations are singular or the root iteration does not converge. */
+int tfl_ringdown_fit(tfl_sim *sim, int probe_id, const tfl_fit_req *req, tfl_fit_result *out, void *stream);
 
 #ifdef __cplusplus
 }

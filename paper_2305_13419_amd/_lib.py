@@ -69,6 +69,20 @@ class tfl_objective(ctypes.Structure):
     _fields_ = [("comp", ctypes.c_int32), ("box", ctypes.c_int64 * 6), ("f0", ctypes.c_double)]
 
 
+TFL_FIT_MAX_ORDER = 16
+
+
+class tfl_fit_req(ctypes.Structure):
+    _fields_ = [("start", ctypes.c_int64), ("count", ctypes.c_int64), ("decim", ctypes.c_int64),
+                ("order", ctypes.c_int32), ("f_hint", ctypes.c_double)]
+
+
+class tfl_fit_result(ctypes.Structure):
+    _fields_ = [("f0", ctypes.c_double), ("alpha", ctypes.c_double), ("Q", ctypes.c_double),
+                ("residual", ctypes.c_double), ("order", ctypes.c_int32), ("nmodes", ctypes.c_int32),
+                ("modes", ctypes.c_double * (2 * TFL_FIT_MAX_ORDER))]
+
+
 class TflError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
@@ -108,6 +122,7 @@ SIGNATURES = {
                                  ctypes.POINTER(ctypes.c_double), P],
     "tfl_adjoint": [P, ctypes.POINTER(tfl_objective), ctypes.c_int64, ctypes.c_int64, P,
                     ctypes.POINTER(ctypes.c_double), P, P, P, P, P],
+    "tfl_ringdown_fit": [P, ctypes.c_int, ctypes.POINTER(tfl_fit_req), ctypes.POINTER(tfl_fit_result), P],
 }
 OPTIONAL_SIGNATURES = {}
 

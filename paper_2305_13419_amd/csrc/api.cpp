@@ -110,6 +110,7 @@ StepArgs<T> make_args(const tfl_sim *s)
     a.g.sxy = (long long)c.nx * c.ny;
     for (int q = 0; q < 3; ++q) {
         a.E[q] = (T *)s->E[q];
+        a.Eout[q] = (T *)s->E[q];
         a.H[q] = (T *)s->H[q];
         a.J[q] = (T *)s->J[q];
     }

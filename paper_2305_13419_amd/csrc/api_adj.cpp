@@ -155,16 +155,33 @@ int adjoint(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg, con
     for (int64_t g = nseg - 1; g >= 0; --g) {
         const int64_t s0 = n0 + g * seg;
         const int64_t len = std::min(seg, nend - s0);
-        // recompute the segment, storing E^{s0} ... E^{s0+len}
+        // recompute the segment, writing E^{s0+t+1} straight into snapshot t+1
         if ((rc = copy_state(s, nullptr, (const char *)ckpt + (size_t)g * sb, false, st)) != TFL_OK) return rc;
-        s->step = s0;
-        for (int64_t t = 0; t <= len; ++t) {
-            if (t > 0 && (rc = do_step<T>(s, 1, st, nullptr, false)) != TFL_OK) return rc;
-            for (int q = 0; q < 3; ++q) {
-                e = hipMemcpyAsync(snapE(t, q), s->E[q], (size_t)s->N * s->esz, hipMemcpyDeviceToDevice, st);
-                if (e != hipSuccess) return hip_fail(s, e, "snapshot");
+        for (int q = 0; q < 3; ++q) {
+            e = hipMemcpyAsync(snapE(0, q), s->E[q], (size_t)s->N * s->esz, hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return hip_fail(s, e, "snapshot");
+        }
+        {
+            StepArgs<T> f = make_args<T>(s);
+            SrcArgs<T> fs{};
+            fs.g = f.g;
+            fs.nsrc = (int)s->src.size();
+            for (int q = 0; q < fs.nsrc; ++q) fs.src[q] = s->src[q];
+            for (int64_t t = 0; t < len; ++t) {
+                for (int q = 0; q < 3; ++q) {
+                    f.E[q] = snapE(t, q);
+                    f.Eout[q] = snapE(t + 1, q);
+                    fs.E[q] = snapE(t + 1, q);
+                }
+                if ((e = launch_h_pass<T>(f, st)) != hipSuccess) return hip_fail(s, e, "recompute h_pass");
+                if ((e = launch_e_pass<T>(f, st)) != hipSuccess) return hip_fail(s, e, "recompute e_pass");
+                if (fs.nsrc > 0) {
+                    fs.t = (double)(s0 + t + 1) * dt;
+                    if ((e = launch_sources<T>(fs, st)) != hipSuccess) return hip_fail(s, e, "recompute sources");
+                }
             }
         }
+        s->step = s0 + len;
         const int64_t end = s0 + len;
         for (int64_t n = end; n >= s0 + 1; --n) {
             if (n != end && (e = launch_adj_faces<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint faces");

@@ -157,6 +157,49 @@ __device__ __forceinline__ void edge_cells(const StepArgs<T> &f, int comp, int i
 }
 
 template <typename T>
+__device__ __forceinline__ void adj_edge_local(const AdjArgs<T> &A, int q, long long c, const int pos[3], T lEq,
+                                               const T e4[4], const T s4[4], const T l4[4])
+{
+    const int nx = A.f.g.nx, ny = A.f.g.ny;
+    const T dt = A.f.dt, theta = A.f.theta, hdt = A.f.hdt;
+    // PEC wall: E' = 0 there, so its adjoint does not propagate
+    bool wall = false;
+    for (int a = 0; a < 3; ++a)
+        if (a != q && A.f.pml[a].on && pos[a] == 0) wall = true;
+    const T lEp = wall ? T(0) : lEq;
+    T eps, sig, ell;
+    edge_material(e4, s4, l4, eps, sig, ell);
+    const T sdt = sig * dt;
+    const T inv = T(1) / (eps + theta * sdt);
+    const T ca = (eps - (T(1) - theta) * sdt) * inv;
+    const T cb = dt * inv;
+    const T mu = cb * lEp;
+    const T En = A.En[q][c];
+    T ljt = T(0);
+    if (ell > T(0)) {
+        ljt = A.lJ[q][c] - mu;
+        A.lJ[q][c] = ljt;
+        A.gL[q][c] += (double)hdt * (double)ljt * (double)En;
+    }
+    A.gS[q][c] += -(double)lEp * (double)cb * ((double)theta * (double)A.Ep[q][c] + (1.0 - (double)theta) * (double)En);
+    A.mu[q][c] = mu;
+    A.lE[q][c] = ca * lEp + hdt * ell * ljt;
+    // E-side PML adjoint variables: tot = bn * stored + sg mu
+    for (int a = 0; a < 3; ++a) {
+        if (a == q) continue;
+        const PmlAxis<T> &P = A.f.pml[a];
+        if (!P.on) continue;
+        const int sl = slab_slot(pos[a], P.lo, P.hi, P.n);
+        if (sl < 0) continue;
+        T *ps = A.lpsiE[a][psi_slot(q, a)];
+        const long long pi = psi_index(P, a, nx, ny, pos[0], pos[1], pos[2], sl);
+        ps[pi] = P.bn[pos[a]] * ps[pi] + T(curl_sign(q, a)) * mu;
+    }
+}
+
+// z-marching like the forward E pass: the maps of plane k-1 and the z terms
+// of the curl^T at k-1 are carried in registers.
+template <typename T>
 __global__ __launch_bounds__(kTileX *kTileY) void adj_edge_kernel(const AdjArgs<T> A)
 {
     int i, j, k0, k1;
@@ -168,24 +211,38 @@ __global__ __launch_bounds__(kTileX *kTileY) void adj_edge_kernel(const AdjArgs<
     const int jm = (j == 0) ? ny - 1 : j - 1;
     const long long r0 = (long long)j * nx, rm = (long long)jm * nx;
     const T rdx = A.f.rd[0], rdy = A.f.rd[1], rdz = A.f.rd[2];
-    const T dt = A.f.dt, theta = A.f.theta, hdt = A.f.hdt;
+    const T *__restrict__ meps = A.f.eps;
+    const T *__restrict__ msig = A.f.sig;
+    const T *__restrict__ mell = A.f.ell;
+    const int km0 = (k0 == 0) ? nz - 1 : k0 - 1;
+    const long long bm = (long long)km0 * sxy;
+    T whyz_m = T(0), whxz_m = T(0);
+    if (A.doC) {
+        whyz_m = w_face(A, 1, 2, i, j, km0, A.lH[1][bm + r0 + i]);
+        whxz_m = w_face(A, 0, 2, i, j, km0, A.lH[0][bm + r0 + i]);
+    }
+    T pe00 = T(0), pe10 = T(0), pe01 = T(0), ps00 = T(0), ps10 = T(0), ps01 = T(0), pl00 = T(0), pl10 = T(0),
+      pl01 = T(0);
+    if (A.doA) {
+        pe00 = meps[bm + r0 + i]; pe10 = meps[bm + r0 + im]; pe01 = meps[bm + rm + i];
+        ps00 = msig[bm + r0 + i]; ps10 = msig[bm + r0 + im]; ps01 = msig[bm + rm + i];
+        pl00 = mell[bm + r0 + i]; pl10 = mell[bm + r0 + im]; pl01 = mell[bm + rm + i];
+    }
     for (int k = k0; k < k1; ++k) {
-        const int km = (k == 0) ? nz - 1 : k - 1;
-        const long long b0 = (long long)k * sxy, bm = (long long)km * sxy;
+        const long long b0 = (long long)k * sxy;
         const long long c = b0 + r0 + i;
+        const long long cxm = b0 + r0 + im, cym = b0 + rm + i, cxym = b0 + rm + im;
         T le[3] = {A.lE[0][c], A.lE[1][c], A.lE[2][c]};
         if (A.doC) {
-            const T *hx = A.lH[0], *hy = A.lH[1], *hz = A.lH[2];
-            const T hx0 = hx[c], hy0 = hy[c], hz0 = hz[c];
-            // Ex: terms (Hy, z) and (Hz, y)
-            le[0] += (w_face(A, 1, 2, i, j, km, hy[bm + r0 + i]) - w_face(A, 1, 2, i, j, k, hy0)) * rdz +
-                     (w_face(A, 2, 1, i, jm, k, hz[b0 + rm + i]) - w_face(A, 2, 1, i, j, k, hz0)) * rdy;
-            // Ey: terms (Hx, z) and (Hz, x)
-            le[1] += (w_face(A, 0, 2, i, j, km, hx[bm + r0 + i]) - w_face(A, 0, 2, i, j, k, hx0)) * rdz +
-                     (w_face(A, 2, 0, im, j, k, hz[b0 + r0 + im]) - w_face(A, 2, 0, i, j, k, hz0)) * rdx;
-            // Ez: terms (Hx, y) and (Hy, x)
-            le[2] += (w_face(A, 0, 1, i, jm, k, hx[b0 + rm + i]) - w_face(A, 0, 1, i, j, k, hx0)) * rdy +
-                     (w_face(A, 1, 0, im, j, k, hy[b0 + r0 + im]) - w_face(A, 1, 0, i, j, k, hy0)) * rdx;
+            const T hx0 = A.lH[0][c], hy0 = A.lH[1][c], hz0 = A.lH[2][c];
+            const T whyz = w_face(A, 1, 2, i, j, k, hy0), whxz = w_face(A, 0, 2, i, j, k, hx0);
+            // Ex: terms (Hy, z) and (Hz, y); Ey: (Hx, z) and (Hz, x); Ez: (Hx, y) and (Hy, x)
+            le[0] += (whyz_m - whyz) * rdz + (w_face(A, 2, 1, i, jm, k, A.lH[2][cym]) - w_face(A, 2, 1, i, j, k, hz0)) * rdy;
+            le[1] += (whxz_m - whxz) * rdz + (w_face(A, 2, 0, im, j, k, A.lH[2][cxm]) - w_face(A, 2, 0, i, j, k, hz0)) * rdx;
+            le[2] += (w_face(A, 0, 1, i, jm, k, A.lH[0][cym]) - w_face(A, 0, 1, i, j, k, hx0)) * rdy +
+                     (w_face(A, 1, 0, im, j, k, A.lH[1][cxm]) - w_face(A, 1, 0, i, j, k, hy0)) * rdx;
+            whyz_m = whyz;
+            whxz_m = whxz;
         }
         if (A.obj && i >= A.ob[0] && i < A.ob[1] && j >= A.ob[2] && j < A.ob[3] && k >= A.ob[4] && k < A.ob[5])
             le[A.ocomp] += (T)A.og;
@@ -193,44 +250,25 @@ __global__ __launch_bounds__(kTileX *kTileY) void adj_edge_kernel(const AdjArgs<
             for (int q = 0; q < 3; ++q) A.lE[q][c] = le[q];
             continue;
         }
+        const T e00 = meps[c], e10 = meps[cxm], e01 = meps[cym], e11 = meps[cxym];
+        const T s00 = msig[c], s10 = msig[cxm], s01 = msig[cym], s11 = msig[cxym];
+        const T l00 = mell[c], l10 = mell[cxm], l01 = mell[cym], l11 = mell[cxym];
         const int pos[3] = {i, j, k};
-        for (int q = 0; q < 3; ++q) {
-            // PEC wall: E' = 0 there, so its adjoint does not propagate
-            bool wall = false;
-            for (int a = 0; a < 3; ++a)
-                if (a != q && A.f.pml[a].on && pos[a] == 0) wall = true;
-            const T lEp = wall ? T(0) : le[q];
-            T e4[4], s4[4], l4[4];
-            edge_cells(A.f, q, i, j, k, e4, s4, l4);
-            T eps, sig, ell;
-            edge_material(e4, s4, l4, eps, sig, ell);
-            const T sdt = sig * dt;
-            const T inv = T(1) / (eps + theta * sdt);
-            const T ca = (eps - (T(1) - theta) * sdt) * inv;
-            const T cb = dt * inv;
-            const T mu = cb * lEp;
-            const T En = A.En[q][c];
-            T ljt = T(0);
-            if (ell > T(0)) {
-                ljt = A.lJ[q][c] - mu;
-                A.lJ[q][c] = ljt;
-                A.gL[q][c] += (double)hdt * (double)ljt * (double)En;
-            }
-            A.gS[q][c] += -(double)lEp * (double)cb * ((double)theta * (double)A.Ep[q][c] + (1.0 - (double)theta) * (double)En);
-            A.mu[q][c] = mu;
-            A.lE[q][c] = ca * lEp + hdt * ell * ljt;
-            // E-side PML adjoint variables: tot = bn * stored + sg mu
-            for (int a = 0; a < 3; ++a) {
-                if (a == q) continue;
-                const PmlAxis<T> &P = A.f.pml[a];
-                if (!P.on) continue;
-                const int s = slab_slot(pos[a], P.lo, P.hi, P.n);
-                if (s < 0) continue;
-                T *ps = A.lpsiE[a][psi_slot(q, a)];
-                const long long pi = psi_index(P, a, nx, ny, i, j, k, s);
-                ps[pi] = P.bn[pos[a]] * ps[pi] + T(curl_sign(q, a)) * mu;
-            }
+        {
+            const T e[4] = {e00, pe00, e01, pe01}, s[4] = {s00, ps00, s01, ps01}, l[4] = {l00, pl00, l01, pl01};
+            adj_edge_local(A, 0, c, pos, le[0], e, s, l);
         }
+        {
+            const T e[4] = {e00, e10, pe00, pe10}, s[4] = {s00, s10, ps00, ps10}, l[4] = {l00, l10, pl00, pl10};
+            adj_edge_local(A, 1, c, pos, le[1], e, s, l);
+        }
+        {
+            const T e[4] = {e00, e01, e10, e11}, s[4] = {s00, s01, s10, s11}, l[4] = {l00, l01, l10, l11};
+            adj_edge_local(A, 2, c, pos, le[2], e, s, l);
+        }
+        pe00 = e00; pe10 = e10; pe01 = e01;
+        ps00 = s00; ps10 = s10; ps01 = s01;
+        pl00 = l00; pl10 = l10; pl01 = l01;
     }
 }
 

@@ -99,9 +99,9 @@ __global__ __launch_bounds__(kTileX *kTileY, TFL_MIN_WAVES) void h_pass_kernel(c
 // E pass (London supercurrent + Ampere's law with the theta-weighted Ohmic term)
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void update_edge(T *__restrict__ E, T *__restrict__ J, long long c, T curl,
-                                            const T e[4], const T s[4], const T l[4], T dt, T theta, T hdt,
-                                            bool wall)
+__device__ __forceinline__ void update_edge(const T *__restrict__ E, T *__restrict__ Eo, T *__restrict__ J,
+                                            long long c, T curl, const T e[4], const T s[4], const T l[4], T dt,
+                                            T theta, T hdt, bool wall)
 {
     T eps, sig, ell;
     edge_material(e, s, l, eps, sig, ell);
@@ -116,7 +116,7 @@ __device__ __forceinline__ void update_edge(T *__restrict__ E, T *__restrict__ J
         J[c] = Jn;
     }
     const T En = ca * E0 + cb * (curl - Jn);
-    E[c] = wall ? T(0) : En;
+    Eo[c] = wall ? T(0) : En;
 }
 
 template <typename T>
@@ -138,9 +138,12 @@ __global__ __launch_bounds__(kTileX *kTileY, TFL_MIN_WAVES) void e_pass_kernel(c
     const int im = (i == 0) ? nx - 1 : i - 1;
     const int jm = (j == 0) ? ny - 1 : j - 1;
     const long long r0 = (long long)j * nx, rm = (long long)jm * nx;
-    T *__restrict__ Ex = a.E[0];
-    T *__restrict__ Ey = a.E[1];
-    T *__restrict__ Ez = a.E[2];
+    const T *Ex = a.E[0];
+    const T *Ey = a.E[1];
+    const T *Ez = a.E[2];
+    T *Exo = a.Eout[0];
+    T *Eyo = a.Eout[1];
+    T *Ezo = a.Eout[2];
     T *__restrict__ Jx = a.J[0];
     T *__restrict__ Jy = a.J[1];
     T *__restrict__ Jz = a.J[2];
@@ -201,15 +204,15 @@ __global__ __launch_bounds__(kTileX *kTileY, TFL_MIN_WAVES) void e_pass_kernel(c
         const T l00 = mell[c], l10 = mell[cxm], l01 = mell[cym], l11 = mell[cxym];
         {   // Ex: cells (j,k), (j,k-1), (j-1,k), (j-1,k-1)
             const T e[4] = {e00, pe00, e01, pe01}, s[4] = {s00, ps00, s01, ps01}, l[4] = {l00, pl00, l01, pl01};
-            update_edge(Ex, Jx, c, dyHz - dzHy, e, s, l, dt, theta, hdt, wall_y || wall_z);
+            update_edge(Ex, Exo, Jx, c, dyHz - dzHy, e, s, l, dt, theta, hdt, wall_y || wall_z);
         }
         {   // Ey: cells (k,i), (k,i-1), (k-1,i), (k-1,i-1)
             const T e[4] = {e00, e10, pe00, pe10}, s[4] = {s00, s10, ps00, ps10}, l[4] = {l00, l10, pl00, pl10};
-            update_edge(Ey, Jy, c, dzHx - dxHz, e, s, l, dt, theta, hdt, wall_z || wall_x);
+            update_edge(Ey, Eyo, Jy, c, dzHx - dxHz, e, s, l, dt, theta, hdt, wall_z || wall_x);
         }
         {   // Ez: cells (i,j), (i,j-1), (i-1,j), (i-1,j-1)
             const T e[4] = {e00, e01, e10, e11}, s[4] = {s00, s01, s10, s11}, l[4] = {l00, l01, l10, l11};
-            update_edge(Ez, Jz, c, dxHy - dyHx, e, s, l, dt, theta, hdt, wall_x || wall_y);
+            update_edge(Ez, Ezo, Jz, c, dxHy - dyHx, e, s, l, dt, theta, hdt, wall_x || wall_y);
         }
         hx_km = hx;
         hy_km = hy;

@@ -53,6 +53,7 @@ template <typename T>
 struct StepArgs {
     GridDims g;
     T *E[3];
+    T *Eout[3];  // where the E pass writes E^{n+1} (E itself except in recomputation)
     T *H[3];
     T *J[3];
     const T *eps, *sig, *ell;  // per-cell maps
@@ -142,6 +143,17 @@ template <typename T>
 hipError_t launch_map_stats(const T *eps, const T *sig, const T *ell, long long n, double *scratch, int nblocks,
                             hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+// Gram matrix of the lagged decimated series (fit.hip): for every pair
+// j <= k <= P, G[j][k] = sum_{m=P}^{M-1} x_{m-j} x_{m-k}, x_m = series[start + m*decim];
+// the (P+1)(P+2)/2 sums are written to out in row-major upper-triangle order.
+hipError_t launch_gram(const double *series, long long start, long long count, long long decim, int order,
+                       double *out, hipStream_t s);
+
+// Residual correction of the linear predictor a (device, order P):
+// out[j-1] = sum_{m=P}^{M-1} x_{m-j} (x_m - sum_k a_k x_{m-k}), j = 1..P.
+hipError_t launch_lp_residual(const double *series, long long start, long long count, long long decim, int order,
+                              const double *a, double *out, hipStream_t s);
 
 // Adjoint launchers (kernels_adj.hip).
 template <typename T> hipError_t launch_adj_faces(const AdjArgs<T> &a, hipStream_t s);

@@ -194,6 +194,16 @@ class Simulation:
     def load_state(self, src):
         self._call("tfl_load_state", ctypes.c_void_p(src.data_ptr()), _stream())
 
+    def ringdown_fit(self, pid, start, count, decim=1, order=0, f_hint=0.0):
+        """Linear-prediction fit of probe pid's series window; returns dict(f0, alpha, Q, residual,
+        order, modes=[(f, alpha), ...])."""
+        rq = L.tfl_fit_req()
+        rq.start, rq.count, rq.decim, rq.order, rq.f_hint = int(start), int(count), int(decim), int(order), f_hint
+        r = L.tfl_fit_result()
+        self._call("tfl_ringdown_fit", ctypes.c_int(int(pid)), ctypes.byref(rq), ctypes.byref(r), _stream())
+        modes = [(r.modes[2 * q], r.modes[2 * q + 1]) for q in range(r.nmodes)]
+        return dict(f0=r.f0, alpha=r.alpha, Q=r.Q, residual=r.residual, order=r.order, modes=modes)
+
     # -- adjoint ------------------------------------------------------------
     @staticmethod
     def _objective(comp, box, f0):

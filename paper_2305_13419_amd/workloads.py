@@ -104,3 +104,78 @@ def random_medium(shape, seed, pml=(None, None, None), d=(20e-9, 17e-9, 23e-9), 
     return dict(name=f"random medium {nx}x{ny}x{nz}", shape=shape, spacing=tuple(d),
                 dt=courant_dt(d, 1.0 / (50e-9) ** 2, 0.95), theta=theta, pml=pml,
                 maps=(eps, sig, ell), fields=(E, H, J), sources=[], probes=[], steps=20)
+
+
+def cpw_grid(scale=1, steps=None, dtype_note="FP32 fields + FP64 probes"):
+    """Coplanar-waveguide resonator shaped like the paper's device (Sec. 5), at reduced size.
+
+    scale=1: 512 x 256 x 128 cells of 0.5 um; scale=2 halves every length (256 x 128 x 64).
+    eps_r = 11.7 substrate below the film; a 4-cell (2 at scale 2) superconducting film
+    (lambda_L = 100 nm, sigma_n = 1e4 S/m) patterned as a centre strip with two gaps and ground
+    planes reaching the periodic y edges; the strip is cut by two coupling gaps into input port,
+    half-wave resonator and output port; the pattern stops one PML width short of the x-PML.
+    CPML on the x and z faces.  Excitation: opposite soft Ey Gaussian-modulated pulses in the two
+    gaps near the input end (f = 0.96 THz at scale 1, doubled at scale 2; tw = 1/(2f), t0 = 4 tw).
+    dt = 0.95 x the stable limit with the London term."""
+    s = scale
+    nx, ny, nz = 512 // s, 256 // s, 128 // s
+    d = 0.5e-6
+    npml = 16 // s
+    k_film0, k_film1 = 48 // s, 52 // s
+    strip = (118 // s, 138 // s) if s == 1 else (59, 69)
+    gap_lo = (106 // s, strip[0]) if s == 1 else (53, 59)
+    gap_hi = (strip[1], 150 // s) if s == 1 else (69, 75)
+    x0, x1 = 32 // s, 480 // s
+    cg1 = (190 // s, 194 // s) if s == 1 else (95, 97)
+    cg2 = (318 // s, 322 // s) if s == 1 else (159, 161)
+    shp = (nz, ny, nx)
+    eps = np.ones(shp)
+    eps[:k_film0] = 11.7
+    film = np.zeros((ny, nx), bool)
+    film[:, x0:x1] = True                       # ground planes and strip region
+    film[gap_lo[0]:gap_lo[1], x0:x1] = False    # the two gaps
+    film[gap_hi[0]:gap_hi[1], x0:x1] = False
+    film[strip[0]:strip[1], cg1[0]:cg1[1]] = False  # coupling gaps cut the strip
+    film[strip[0]:strip[1], cg2[0]:cg2[1]] = False
+    ell = np.zeros(shp)
+    sig = np.zeros(shp)
+    ell[k_film0:k_film1][:, film] = 1e14
+    sig[k_film0:k_film1][:, film] = 1e4
+    f = 0.96e12 * s
+    tw = 1.0 / (2 * f)
+    xs = 40 // s
+    kk = (k_film0, k_film1 + 1)
+    src = [dict(comp=1, box=(xs, xs + 1, gap_lo[0], gap_lo[1], kk[0], kk[1]), amplitude=1.0, waveform="mod_gauss",
+                freq=f, t0=4 * tw, tw=tw),
+           dict(comp=1, box=(xs, xs + 1, gap_hi[0], gap_hi[1], kk[0], kk[1]), amplitude=-1.0, waveform="mod_gauss",
+                freq=f, t0=4 * tw, tw=tw)]
+    xp = cg1[1] + 4 // s
+    kmid = (k_film0 + k_film1) // 2
+    probes = [dict(comp=1, box=(xp, xp + 1, gap_lo[0] + 6 // s, gap_lo[0] + 6 // s + 1, kmid, kmid + 1)),
+              dict(comp=1, box=(xp, xp + 1, gap_lo[0], gap_lo[1], kmid, kmid + 1))]
+    return dict(name=f"cpw {nx}x{ny}x{nz}", shape=(nx, ny, nz), spacing=(d, d, d),
+                dt=courant_dt((d, d, d), 1e14, 0.95), theta=1.0, pml=((npml, npml), None, (npml, npml)),
+                maps=(eps, sig, ell), fields=None, sources=src, probes=probes, freq=f,
+                steps=steps if steps is not None else (20000 if s == 1 else 4096),
+                objective=(1, probes[1]["box"], None), note=dtype_note)
+
+
+def large_mixed_grid(seed=5, steps=8192):
+    """Large mixed-precision workload: 1024 x 512 x 256 cells of 20 nm, periodic, eps_r = 11.7 in the
+    bottom quarter, random superconducting boxes as in the roofline grid (seed 5), zero fields driven by
+    a soft Ey sheet source; objective: Ey summed along y at x = 512, z = 128."""
+    rng = np.random.default_rng(seed)
+    shape = (1024, 512, 256)
+    eps0 = np.ones((256, 512, 1024))
+    eps0[:64] = 11.7
+    maps = random_boxes(shape, rng, eps_r=eps0)
+    d = 20e-9
+    f = 2e14
+    tw = 1.0 / (2 * f)
+    return dict(name="large 1024x512x256", shape=shape, spacing=(d, d, d),
+                dt=courant_dt((d, d, d), 1.0 / (50e-9) ** 2, 0.95), theta=1.0, pml=(None, None, None),
+                maps=maps, fields=None,
+                sources=[dict(comp=1, box=(256, 257, 0, 512, 96, 160), amplitude=1.0, waveform="mod_gauss", freq=f,
+                              t0=4 * tw, tw=tw)],
+                probes=[dict(comp=1, box=(512, 513, 0, 512, 128, 129))], freq=f, steps=steps,
+                objective=(1, (512, 513, 0, 512, 128, 129), None))
