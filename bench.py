@@ -3,13 +3,17 @@
 Workload: the 256^3 roofline grid (dx = 20 nm, periodic, random
 superconducting boxes on ~30 % of the cells, E and H ~ N(0, 1)), stepped in
 FP64 and in FP32.  A step is one full time step of Algorithm 1 (the H pass
-and the E + Js pass).  Prints one JSON line.
+and the E + Js pass).  Also timed: the adjoint gradient on the half-size CPW
+workload (256 x 128 x 64 cells, 4096 steps, 64-step checkpoint segments)
+against its checkpointed forward run.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--n 256] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--n 256] [--no-cpu] [--no-adjoint]
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -61,6 +65,54 @@ def run_gpu(wl, dtype, steps, warmup):
                 nonfinite=int(bad), energy=W)
 
 
+def measured_traffic(dtype_name):
+    """HBM bytes per E-pass launch from the committed rocprofv3 counter summary, or None when the
+    kernel source changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "e_pass_kernel_roofline_256cube.md")
+    src = os.path.join(ROOT, "paper_2305_13419_amd", "csrc", "kernels_fwd.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        m = re.match(r"TRAFFIC (\w+) e_pass_kernel bytes_per_launch=(\S+) kernels_fwd_sha=(\w+)", line.strip())
+        if m and m.group(1) == dtype_name and m.group(3) == sha:
+            return float(m.group(2))
+    return None
+
+
+def adjoint_ratio(dtype, seg=64):
+    """Wall time of the reverse sweep over that of the checkpointed forward run (half-size CPW)."""
+    import numpy as np
+    import torch
+
+    from paper_2305_13419_amd import Simulation, workloads
+
+    wl = workloads.cpw_grid(2)
+    N = wl["steps"]
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"])
+    sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
+    z = [np.zeros(sim.shape3, dtype=npdt)] * 3
+    for s in wl["sources"]:
+        sim.add_source(**s)
+    obj = wl["objective"]
+    ckpt, snap, work = sim.adjoint_buffers(N, seg)
+    best = None
+    for _ in range(2):  # the first pass warms up allocations and code objects
+        sim.set_fields(z, z, z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = sim.forward_checkpointed(obj, N, seg, ckpt)
+        t1 = time.perf_counter()
+        sim.adjoint(obj, N, seg, ckpt, F, snap, work)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        best = (t1 - t0, t2 - t1)
+    sim.close()
+    return dict(forward_s=best[0], adjoint_s=best[1], ratio=best[1] / best[0], steps=N, seg=seg,
+                workload=wl["name"])
+
+
 def cpu_baseline(wl, steps):
     """The FP64 CPU oracle on the same grid, a bounded number of steps."""
     import numpy as np
@@ -86,8 +138,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1).", file=sys.stderr)
@@ -119,8 +172,8 @@ def main():
             h_pass_GBs=h_bytes / (r["h_ms"] * 1e-3) / 1e9, e_pass_GBs=e_gbs,
             nonfinite=r["nonfinite"],
             roofline=dict(bound="hbm", kernel="e_pass_kernel", achieved=e_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                          frac=e_gbs / HBM_PEAK_GBS, traffic=None,
-                          bytes_per_cell=w * (12 + 6 * fJ)),
+                          frac=e_gbs / HBM_PEAK_GBS, traffic=measured_traffic(name),
+                          bytes_per_cell=w * (12 + 6 * fJ), algorithmic_bytes_per_launch=e_bytes),
         )
     f64 = out["f64"]
     line = {
@@ -142,6 +195,13 @@ def main():
         "f64": {k: v for k, v in f64.items() if k != "roofline"},
         "f32": out["f32"],
     }
+    if not args.no_adjoint:
+        ratios = {}
+        for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+            print(f"# adjoint/forward ratio, {name}", file=sys.stderr, flush=True)
+            ratios[name] = adjoint_ratio(dt)
+        line["adjoint_forward_ratio"] = {k: v["ratio"] for k, v in ratios.items()}
+        line["adjoint"] = ratios
     if not args.no_cpu:
         print(f"# cpu_baseline: oracle, {args.cpu_steps} steps", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
