@@ -8,6 +8,9 @@ workload (256 x 128 x 64 cells, 4096 steps, 64-step checkpoint segments)
 against its checkpointed forward run.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--n 256] [--no-cpu] [--no-adjoint]
+    python bench.py --large      # the 1024 x 512 x 256 workload: FP32 forward 8192 steps and the
+                                 # three-level adjoint, plus a finite-difference check of the FP64
+                                 # gradient over 512 steps (several minutes)
 """
 import argparse
 import hashlib
@@ -113,6 +116,92 @@ def adjoint_ratio(dtype, seg=64):
                 workload=wl["name"])
 
 
+def large_run(steps=8192, seg=512, seg2=32, fd_steps=512, fd_cells=4):
+    """FP32 forward + three-level adjoint on the large grid, then central differences of the FP64
+    forward (three-level adjoint over fd_steps) at fd_cells cells per map."""
+    import numpy as np
+    import torch
+
+    from paper_2305_13419_amd import Simulation, workloads
+
+    wl = workloads.large_mixed_grid(steps=steps)
+    n = int(np.prod(wl["shape"]))
+    obj = (wl["objective"][0], wl["objective"][1], wl["freq"])
+    out = {"workload": wl["name"], "steps": steps, "seg": seg, "seg2": seg2, "objective_f0": wl["freq"]}
+
+    def make(dtype, npdt):
+        sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"])
+        sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
+        for s in wl["sources"]:
+            sim.add_source(**s)
+        z = [torch.zeros(sim.shape3, dtype=dtype, device="cuda")] * 3
+        sim.set_fields(z, z, z)
+        return sim
+
+    print("# large: FP32 forward and three-level adjoint", file=sys.stderr, flush=True)
+    torch.cuda.reset_peak_memory_stats()
+    sim = make(torch.float32, np.float32)
+    ckpt, ckpt2, snap, work = sim.adjoint_nested_buffers(steps, seg, seg2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = sim.forward_checkpointed(obj, steps, seg, ckpt)
+    t1 = time.perf_counter()
+    gl, gs = sim.adjoint_nested(obj, steps, seg, seg2, ckpt, F, ckpt2, snap, work)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["f32"] = dict(forward_s=t1 - t0, forward_Gcells=n * steps / (t1 - t0) / 1e9, adjoint_s=t2 - t1,
+                      ratio=(t2 - t1) / (t1 - t0), J=abs(F) ** 2,
+                      peak_GB=torch.cuda.max_memory_allocated() / 1e9,
+                      grad_finite=bool(torch.isfinite(gl).all() and torch.isfinite(gs).all()))
+    print(f"# large FP32: {out['f32']}", file=sys.stderr, flush=True)
+    sim.close()
+    del sim, ckpt, ckpt2, snap, work, gl, gs
+    torch.cuda.empty_cache()
+
+    print(f"# large: FP64 gradient over {fd_steps} steps and central differences", file=sys.stderr, flush=True)
+    sim = make(torch.float64, np.float64)
+    s1, s2 = 128, 16
+    ckpt, ckpt2, snap, work = sim.adjoint_nested_buffers(fd_steps, s1, s2)
+    F = sim.forward_checkpointed(obj, fd_steps, s1, ckpt)
+    gl, gs = sim.adjoint_nested(obj, fd_steps, s1, s2, ckpt, F, ckpt2, snap, work)
+    gl, gs = gl.cpu().numpy(), gs.cpu().numpy()
+    del ckpt, ckpt2, snap, work
+    torch.cuda.empty_cache()
+    J0 = abs(F) ** 2
+    fpid = sim.add_probe(obj[0], obj[1], 0, [obj[2]])
+    eps, sig, ell = wl["maps"]
+    dev = [torch.tensor(m, device="cuda") for m in (eps, sig, ell)]
+
+    def J_of(mi, cell, delta):
+        d = dev[mi].clone()
+        d[cell] += delta
+        maps = [dev[0], d if mi == 1 else dev[1], d if mi == 2 else dev[2]]
+        sim.set_materials(*maps)
+        z = [torch.zeros(sim.shape3, dtype=torch.float64, device="cuda")] * 3
+        sim.set_fields(z, z, z)
+        sim._probes[fpid][1].zero_()
+        sim.step(fd_steps)
+        return abs(sim.probe(fpid)[1][0]) ** 2
+
+    rng = np.random.default_rng(5)
+    errs = {}
+    hrel = 1e-4
+    for name, g, m, ref, mi in (("ell", gl, ell, 1e14, 2), ("sigma", gs, sig, 1e4, 1)):
+        dJ = np.abs(g) * hrel * np.maximum(np.abs(m), ref) / J0
+        ok = (m > 0) & (dJ >= 1e-2 * dJ[m > 0].max())
+        cells = np.argwhere(ok)
+        e = []
+        for c in cells[rng.choice(len(cells), fd_cells, replace=False)]:
+            c = tuple(int(v) for v in c)
+            h = hrel * max(abs(m[c]), ref)
+            fd = (J_of(mi, c, h) - J_of(mi, c, -h)) / (2 * h)
+            e.append(abs(g[c] - fd) / abs(fd))
+        errs[name] = max(e)
+    out["fd_fp64"] = dict(steps=fd_steps, seg=s1, seg2=s2, cells_per_map=fd_cells, max_rel_err=errs)
+    sim.close()
+    return out
+
+
 def cpu_baseline(wl, steps):
     """The FP64 CPU oracle on the same grid, a bounded number of steps."""
     import numpy as np
@@ -141,6 +230,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--large", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1).", file=sys.stderr)
@@ -149,6 +239,10 @@ def main():
     import torch
 
     from paper_2305_13419_amd import workloads
+
+    if args.large:
+        print(json.dumps({"metric": METRIC, "large": large_run()}), flush=True)
+        return
 
     wl = workloads.roofline_grid(args.n, steps=args.steps)
     ncell = args.n**3

@@ -287,6 +287,19 @@ typedef struct {
  * equations are singular or the root iteration does not converge. */
 int tfl_ringdown_fit(tfl_sim *sim, int probe_id, const tfl_fit_req *req, tfl_fit_result *out, void *stream);
 
+/* Three-level variant for runs whose two-level schedule does not fit in
+ * memory: after the same tfl_forward_checkpointed run (checkpoints every seg
+ * steps), each outer segment is recomputed saving inner checkpoints every
+ * seg2 steps (1 <= seg2 <= seg) into ckpt2, and each inner segment is
+ * recomputed into the snapshots and swept backwards.  Sizes from
+ * tfl_adjoint_nested_sizes (ckpt2 holds ceil(seg/seg2) states, snap seg2 + 1
+ * E fields).  Same results, outputs and errors as tfl_adjoint. */
+int tfl_adjoint_nested_sizes(const tfl_sim *sim, int64_t nsteps, int64_t seg, int64_t seg2, size_t *ckpt_bytes,
+                             size_t *ckpt2_bytes, size_t *snap_bytes, size_t *adj_bytes);
+int tfl_adjoint_nested(tfl_sim *sim, const tfl_objective *obj, int64_t nsteps, int64_t seg, const void *ckpt,
+                       const double F[2], int64_t seg2, void *ckpt2, void *snap, void *adj, double *grad_ell,
+                       double *grad_sigma, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,10 +21,11 @@ class AdjointProblem:
     sources : list of dicts for Simulation.add_source
     objective : (comp, box, f0)
     nsteps, seg : run length and checkpoint segment (default about sqrt(nsteps))
+    seg2 : inner segment of a three-level schedule (None: two levels)
     """
 
     def __init__(self, shape, spacing, dt, eps_r, objective, nsteps, seg=None, theta=1.0, dtype=torch.float64,
-                 pml=(None, None, None), fields=None, sources=(), device="cuda"):
+                 pml=(None, None, None), fields=None, sources=(), device="cuda", seg2=None):
         self.sim = Simulation(shape, spacing, dt, theta, dtype, pml, device=device)
         self.eps_r = self.sim._dev(eps_r)
         self.fields = fields
@@ -34,7 +35,12 @@ class AdjointProblem:
         self.objective = tuple(objective)
         self.nsteps = int(nsteps)
         self.seg = int(seg) if seg else max(1, int(round(math.sqrt(self.nsteps))))
-        self.ckpt, self.snap, self.work = self.sim.adjoint_buffers(self.nsteps, self.seg)
+        self.seg2 = int(seg2) if seg2 else None
+        if self.seg2:
+            self.ckpt, self.ckpt2, self.snap, self.work = self.sim.adjoint_nested_buffers(self.nsteps, self.seg,
+                                                                                         self.seg2)
+        else:
+            self.ckpt, self.snap, self.work = self.sim.adjoint_buffers(self.nsteps, self.seg)
         self.F = None
 
     def _reset(self, inv_lambda2, sigma):
@@ -52,6 +58,9 @@ class AdjointProblem:
         return abs(self.F) ** 2
 
     def gradient(self):
+        if self.seg2:
+            return self.sim.adjoint_nested(self.objective, self.nsteps, self.seg, self.seg2, self.ckpt, self.F,
+                                           self.ckpt2, self.snap, self.work)
         return self.sim.adjoint(self.objective, self.nsteps, self.seg, self.ckpt, self.F, self.snap, self.work)
 
 

@@ -108,77 +108,56 @@ int forward_ckpt(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg
 }
 
 template <typename T>
-int adjoint(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg, const void *ckpt, const double F[2],
-            void *snap, void *adj, double *grad_ell, double *grad_sig, hipStream_t st)
-{
-    const AdjLayout L = adj_layout(s);
-    hipError_t e = launch_fill_zero(adj, L.total, st);
-    if (e != hipSuccess) return hip_fail(s, e, "adjoint clear");
-    AdjArgs<T> A{};
-    A.f = make_args<T>(s);
-    char *p = (char *)adj;
-    for (int q = 0; q < 3; ++q) { A.lE[q] = (T *)p; p += L.field; }
-    for (int q = 0; q < 3; ++q) { A.lH[q] = (T *)p; p += L.field; }
-    for (int q = 0; q < 3; ++q) { A.lJ[q] = (T *)p; p += L.field; }
-    for (int q = 0; q < 3; ++q) { A.mu[q] = (T *)p; p += L.field; }
-    for (int a = 0; a < 3; ++a) {
-        const size_t m = s->psi_count[a] * s->esz;
-        if (s->cfg.bc[a] == TFL_CPML) {
-            A.lpsiH[a][0] = (T *)p; A.lpsiH[a][1] = (T *)(p + m);
-            A.lpsiE[a][0] = (T *)(p + 2 * m); A.lpsiE[a][1] = (T *)(p + 3 * m);
-        }
-        p += round256(4 * m);
-    }
-    for (int q = 0; q < 3; ++q) { A.gL[q] = (double *)p; p += L.grad; }
-    for (int q = 0; q < 3; ++q) { A.gS[q] = (double *)p; p += L.grad; }
-    A.ocomp = o->comp;
-    for (int q = 0; q < 6; ++q) A.ob[q] = (int)o->box[q];
+struct Reverse {
+    tfl_sim *s;
+    const tfl_objective *o;
+    const double *F;
+    AdjArgs<T> A;
+    SrcArgs<T> sa;   // the sources with negated amplitudes (removes them from a snapshot)
+    void *snap;
+    size_t fb;
+    int64_t n0, nend;
+    hipStream_t st;
 
-    const size_t fb = round256((size_t)s->N * s->esz);
-    auto snapE = [&](int64_t t, int q) { return (T *)((char *)snap + ((size_t)t * 3 + q) * fb); };
-    const size_t sb = state_bytes(s);
-    const int64_t n0 = s->ckpt_n0, nend = n0 + nsteps;
-    const double dt = s->cfg.dt;
-    auto objective_coef = [&](int64_t n) {
-        const double ph = kTwoPi * o->f0 * (double)n * dt;
-        return 2.0 * dt * (F[0] * std::cos(ph) - F[1] * std::sin(ph));
-    };
-    SrcArgs<T> sa{};
-    sa.g = A.f.g;
-    sa.nsrc = (int)s->src.size();
-    for (int q = 0; q < sa.nsrc; ++q) {
-        sa.src[q] = s->src[q];
-        sa.src[q].amp = -sa.src[q].amp;  // removes the source from a snapshot
+    T *snapE(int64_t t, int q) const { return (T *)((char *)snap + ((size_t)t * 3 + q) * fb); }
+
+    double objective_coef(int64_t n) const
+    {
+        const double ph = kTwoPi * o->f0 * (double)n * s->cfg.dt;
+        return 2.0 * s->cfg.dt * (F[0] * std::cos(ph) - F[1] * std::sin(ph));
     }
-    const int64_t nseg = (nsteps + seg - 1) / seg;
-    int rc;
-    for (int64_t g = nseg - 1; g >= 0; --g) {
-        const int64_t s0 = n0 + g * seg;
-        const int64_t len = std::min(seg, nend - s0);
-        // recompute the segment, writing E^{s0+t+1} straight into snapshot t+1
-        if ((rc = copy_state(s, nullptr, (const char *)ckpt + (size_t)g * sb, false, st)) != TFL_OK) return rc;
+
+    // Reverse sweep over the forward steps [s0, s0 + len) from the saved state at s0: recompute the
+    // range writing E^{s0+t} into snapshot t, then the adjoint sweeps CA(s0+len) [with doC unless the
+    // range ends the run], (B(n), CA(n)) for n = s0+len-1 .. s0+1, and B(s0); the range starting the
+    // run also does CA(n0) (no edge-local part) and the initial half-kick gradient.  CA(s0) of a later
+    // range is the first kernel of the range before it.
+    int range(int64_t s0, int64_t len, const void *state_s0)
+    {
+        hipError_t e;
+        int rc = copy_state(s, nullptr, state_s0, false, st);
+        if (rc != TFL_OK) return rc;
         for (int q = 0; q < 3; ++q) {
             e = hipMemcpyAsync(snapE(0, q), s->E[q], (size_t)s->N * s->esz, hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) return hip_fail(s, e, "snapshot");
         }
-        {
-            StepArgs<T> f = make_args<T>(s);
-            SrcArgs<T> fs{};
-            fs.g = f.g;
-            fs.nsrc = (int)s->src.size();
-            for (int q = 0; q < fs.nsrc; ++q) fs.src[q] = s->src[q];
-            for (int64_t t = 0; t < len; ++t) {
-                for (int q = 0; q < 3; ++q) {
-                    f.E[q] = snapE(t, q);
-                    f.Eout[q] = snapE(t + 1, q);
-                    fs.E[q] = snapE(t + 1, q);
-                }
-                if ((e = launch_h_pass<T>(f, st)) != hipSuccess) return hip_fail(s, e, "recompute h_pass");
-                if ((e = launch_e_pass<T>(f, st)) != hipSuccess) return hip_fail(s, e, "recompute e_pass");
-                if (fs.nsrc > 0) {
-                    fs.t = (double)(s0 + t + 1) * dt;
-                    if ((e = launch_sources<T>(fs, st)) != hipSuccess) return hip_fail(s, e, "recompute sources");
-                }
+        StepArgs<T> f = make_args<T>(s);
+        SrcArgs<T> fs{};
+        fs.g = f.g;
+        fs.nsrc = (int)s->src.size();
+        for (int q = 0; q < fs.nsrc; ++q) fs.src[q] = s->src[q];
+        const double dt = s->cfg.dt;
+        for (int64_t t = 0; t < len; ++t) {
+            for (int q = 0; q < 3; ++q) {
+                f.E[q] = snapE(t, q);
+                f.Eout[q] = snapE(t + 1, q);
+                fs.E[q] = snapE(t + 1, q);
+            }
+            if ((e = launch_h_pass<T>(f, st)) != hipSuccess) return hip_fail(s, e, "recompute h_pass");
+            if ((e = launch_e_pass<T>(f, st)) != hipSuccess) return hip_fail(s, e, "recompute e_pass");
+            if (fs.nsrc > 0) {
+                fs.t = (double)(s0 + t + 1) * dt;
+                if ((e = launch_sources<T>(fs, st)) != hipSuccess) return hip_fail(s, e, "recompute sources");
             }
         }
         s->step = s0 + len;
@@ -201,7 +180,7 @@ int adjoint(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg, con
             if ((e = launch_adj_edges<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint edges");
         }
         if ((e = launch_adj_faces<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint faces");
-        if (g == 0) {
+        if (s0 == n0) {
             A.doC = 1;
             A.doA = 0;
             A.obj = 1;
@@ -210,9 +189,106 @@ int adjoint(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg, con
             for (int q = 0; q < 3; ++q) A.En[q] = snapE(0, q);
             if ((e = launch_adj_initial_kick<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint kick");
         }
+        return TFL_OK;
     }
-    if ((e = launch_adj_edge_to_cell<T>(A, grad_ell, grad_sig, st)) != hipSuccess)
-        return hip_fail(s, e, "gradient to cells");
+};
+
+template <typename T>
+int make_reverse(tfl_sim *s, const tfl_objective *o, const double F[2], void *snap, void *adj, hipStream_t st,
+                 Reverse<T> &R)
+{
+    const AdjLayout L = adj_layout(s);
+    hipError_t e = launch_fill_zero(adj, L.total, st);
+    if (e != hipSuccess) return hip_fail(s, e, "adjoint clear");
+    R.s = s;
+    R.o = o;
+    R.F = F;
+    R.snap = snap;
+    R.st = st;
+    R.fb = round256((size_t)s->N * s->esz);
+    R.n0 = s->ckpt_n0;
+    R.nend = s->ckpt_n0 + s->ckpt_nsteps;
+    AdjArgs<T> &A = R.A;
+    A = AdjArgs<T>{};
+    A.f = make_args<T>(s);
+    char *p = (char *)adj;
+    for (int q = 0; q < 3; ++q) { A.lE[q] = (T *)p; p += L.field; }
+    for (int q = 0; q < 3; ++q) { A.lH[q] = (T *)p; p += L.field; }
+    for (int q = 0; q < 3; ++q) { A.lJ[q] = (T *)p; p += L.field; }
+    for (int q = 0; q < 3; ++q) { A.mu[q] = (T *)p; p += L.field; }
+    for (int a = 0; a < 3; ++a) {
+        const size_t m = s->psi_count[a] * s->esz;
+        if (s->cfg.bc[a] == TFL_CPML) {
+            A.lpsiH[a][0] = (T *)p; A.lpsiH[a][1] = (T *)(p + m);
+            A.lpsiE[a][0] = (T *)(p + 2 * m); A.lpsiE[a][1] = (T *)(p + 3 * m);
+        }
+        p += round256(4 * m);
+    }
+    for (int q = 0; q < 3; ++q) { A.gL[q] = (double *)p; p += L.grad; }
+    for (int q = 0; q < 3; ++q) { A.gS[q] = (double *)p; p += L.grad; }
+    A.ocomp = o->comp;
+    for (int q = 0; q < 6; ++q) A.ob[q] = (int)o->box[q];
+    R.sa = SrcArgs<T>{};
+    R.sa.g = A.f.g;
+    R.sa.nsrc = (int)s->src.size();
+    for (int q = 0; q < R.sa.nsrc; ++q) {
+        R.sa.src[q] = s->src[q];
+        R.sa.src[q].amp = -R.sa.src[q].amp;
+    }
+    return TFL_OK;
+}
+
+template <typename T>
+int adjoint(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg, const void *ckpt, const double F[2],
+            void *snap, void *adj, double *grad_ell, double *grad_sig, hipStream_t st)
+{
+    Reverse<T> R;
+    int rc = make_reverse<T>(s, o, F, snap, adj, st, R);
+    if (rc != TFL_OK) return rc;
+    const size_t sb = state_bytes(s);
+    const int64_t nseg = (nsteps + seg - 1) / seg;
+    for (int64_t g = nseg - 1; g >= 0; --g) {
+        const int64_t s0 = R.n0 + g * seg;
+        const int64_t len = std::min(seg, R.nend - s0);
+        if ((rc = R.range(s0, len, (const char *)ckpt + (size_t)g * sb)) != TFL_OK) return rc;
+    }
+    hipError_t e = launch_adj_edge_to_cell<T>(R.A, grad_ell, grad_sig, st);
+    if (e != hipSuccess) return hip_fail(s, e, "gradient to cells");
+    return TFL_OK;
+}
+
+// Three levels: the outer checkpoints of the forward run every seg steps; each outer segment is
+// recomputed saving inner checkpoints every seg2 steps into ckpt2; each inner segment is recomputed
+// into the snapshots and swept backwards.
+template <typename T>
+int adjoint_nested(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg, const void *ckpt,
+                   const double F[2], int64_t seg2, void *ckpt2, void *snap, void *adj, double *grad_ell,
+                   double *grad_sig, hipStream_t st)
+{
+    Reverse<T> R;
+    int rc = make_reverse<T>(s, o, F, snap, adj, st, R);
+    if (rc != TFL_OK) return rc;
+    const size_t sb = state_bytes(s);
+    const int64_t nseg = (nsteps + seg - 1) / seg;
+    for (int64_t g = nseg - 1; g >= 0; --g) {
+        const int64_t s0 = R.n0 + g * seg;
+        const int64_t len = std::min(seg, R.nend - s0);
+        const int64_t nin = (len + seg2 - 1) / seg2;
+        if ((rc = copy_state(s, nullptr, (const char *)ckpt + (size_t)g * sb, false, st)) != TFL_OK) return rc;
+        s->step = s0;
+        for (int64_t h = 0; h < nin; ++h) {
+            if ((rc = copy_state(s, (char *)ckpt2 + (size_t)h * sb, nullptr, true, st)) != TFL_OK) return rc;
+            const int64_t l2 = std::min(seg2, len - h * seg2);
+            if (h + 1 < nin && (rc = do_step<T>(s, l2, st, nullptr, false)) != TFL_OK) return rc;
+        }
+        for (int64_t h = nin - 1; h >= 0; --h) {
+            const int64_t m0 = s0 + h * seg2;
+            const int64_t l2 = std::min(seg2, len - h * seg2);
+            if ((rc = R.range(m0, l2, (const char *)ckpt2 + (size_t)h * sb)) != TFL_OK) return rc;
+        }
+    }
+    hipError_t e = launch_adj_edge_to_cell<T>(R.A, grad_ell, grad_sig, st);
+    if (e != hipSuccess) return hip_fail(s, e, "gradient to cells");
     return TFL_OK;
 }
 
@@ -245,6 +321,41 @@ int tfl_forward_checkpointed(tfl_sim *s, const tfl_objective *obj, int64_t nstep
     hipStream_t st = (hipStream_t)stream;
     return s->esz == 8 ? forward_ckpt<double>(s, obj, nsteps, seg, ckpt, F, st)
                        : forward_ckpt<float>(s, obj, nsteps, seg, ckpt, F, st);
+}
+
+int tfl_adjoint_nested_sizes(const tfl_sim *s, int64_t nsteps, int64_t seg, int64_t seg2, size_t *ckpt_bytes,
+                             size_t *ckpt2_bytes, size_t *snap_bytes, size_t *adj_bytes)
+{
+    if (!s) return fail(nullptr, TFL_E_INVAL, "null handle");
+    if (nsteps < 1 || seg < 1 || seg2 < 1 || seg2 > seg)
+        return fail(const_cast<tfl_sim *>(s), TFL_E_INVAL, "need nsteps, seg >= 1 and 1 <= seg2 <= seg");
+    const int64_t sl = std::min(seg, nsteps), s2 = std::min(seg2, sl);
+    if (ckpt_bytes) *ckpt_bytes = (size_t)((nsteps + seg - 1) / seg) * state_bytes(s);
+    if (ckpt2_bytes) *ckpt2_bytes = (size_t)((sl + seg2 - 1) / seg2) * state_bytes(s);
+    if (snap_bytes) *snap_bytes = (size_t)(s2 + 1) * 3 * round256((size_t)s->N * s->esz);
+    if (adj_bytes) *adj_bytes = adj_layout(s).total;
+    return TFL_OK;
+}
+
+int tfl_adjoint_nested(tfl_sim *s, const tfl_objective *obj, int64_t nsteps, int64_t seg, const void *ckpt,
+                       const double F[2], int64_t seg2, void *ckpt2, void *snap, void *adj, double *grad_ell,
+                       double *grad_sigma, void *stream)
+{
+    int rc = check_bound(s, true);
+    if (rc != TFL_OK) return rc;
+    if ((rc = check_obj(s, obj)) != TFL_OK) return rc;
+    if (!s->ckpt_valid || s->ckpt_nsteps != nsteps || s->ckpt_seg != seg)
+        return fail(s, TFL_E_STATE, "no checkpointed forward run with these nsteps and seg");
+    if (seg2 < 1 || seg2 > seg) return fail(s, TFL_E_INVAL, "seg2 must lie in [1, seg]");
+    if (!ckpt || !ckpt2 || !snap || !adj || !grad_ell || !grad_sigma || !F)
+        return fail(s, TFL_E_INVAL, "null buffer");
+    if (!aligned(ckpt) || !aligned(ckpt2) || !aligned(snap) || !aligned(adj) || !aligned(grad_ell) ||
+        !aligned(grad_sigma))
+        return fail(s, TFL_E_INVAL, "device buffers must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    return s->esz == 8
+               ? adjoint_nested<double>(s, obj, nsteps, seg, ckpt, F, seg2, ckpt2, snap, adj, grad_ell, grad_sigma, st)
+               : adjoint_nested<float>(s, obj, nsteps, seg, ckpt, F, seg2, ckpt2, snap, adj, grad_ell, grad_sigma, st);
 }
 
 int tfl_adjoint(tfl_sim *s, const tfl_objective *obj, int64_t nsteps, int64_t seg, const void *ckpt,

@@ -138,12 +138,15 @@ __global__ __launch_bounds__(kTileX *kTileY, TFL_MIN_WAVES) void e_pass_kernel(c
     const int im = (i == 0) ? nx - 1 : i - 1;
     const int jm = (j == 0) ? ny - 1 : j - 1;
     const long long r0 = (long long)j * nx, rm = (long long)jm * nx;
-    const T *Ex = a.E[0];
-    const T *Ey = a.E[1];
-    const T *Ez = a.E[2];
-    T *Exo = a.Eout[0];
-    T *Eyo = a.Eout[1];
-    T *Ezo = a.Eout[2];
+    // E and Eout are the same arrays except in the adjoint's recomputation; either way each thread
+    // reads E[c] before writing Eout[c] at the same c and no other thread touches c, so the restrict
+    // qualifiers only let the compiler move other planes' accesses.
+    const T *__restrict__ Ex = a.E[0];
+    const T *__restrict__ Ey = a.E[1];
+    const T *__restrict__ Ez = a.E[2];
+    T *__restrict__ Exo = a.Eout[0];
+    T *__restrict__ Eyo = a.Eout[1];
+    T *__restrict__ Ezo = a.Eout[2];
     T *__restrict__ Jx = a.J[0];
     T *__restrict__ Jy = a.J[1];
     T *__restrict__ Jz = a.J[2];

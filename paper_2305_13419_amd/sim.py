@@ -231,6 +231,25 @@ class Simulation:
                    ctypes.c_void_p(ckpt.data_ptr()), F, _stream())
         return complex(F[0], F[1])
 
+    def adjoint_nested_buffers(self, nsteps, seg, seg2):
+        """Buffers of the three-level schedule: (outer checkpoints, inner checkpoints, snapshots, workspace)."""
+        v = [ctypes.c_size_t() for _ in range(4)]
+        self._call("tfl_adjoint_nested_sizes", ctypes.c_int64(int(nsteps)), ctypes.c_int64(int(seg)),
+                   ctypes.c_int64(int(seg2)), *[ctypes.byref(x) for x in v])
+        return tuple(torch.empty(max(x.value, 1), dtype=torch.uint8, device=self.device) for x in v)
+
+    def adjoint_nested(self, objective, nsteps, seg, seg2, ckpt, F, ckpt2, snap, work):
+        """Per-cell FP64 gradients of the last checkpointed run, three-level schedule."""
+        o = self._objective(*objective)
+        Fa = (ctypes.c_double * 2)(F.real, F.imag)
+        gl = torch.empty(self.shape3, dtype=torch.float64, device=self.device)
+        gs = torch.empty(self.shape3, dtype=torch.float64, device=self.device)
+        self._call("tfl_adjoint_nested", ctypes.byref(o), ctypes.c_int64(int(nsteps)), ctypes.c_int64(int(seg)),
+                   ctypes.c_void_p(ckpt.data_ptr()), Fa, ctypes.c_int64(int(seg2)), ctypes.c_void_p(ckpt2.data_ptr()),
+                   ctypes.c_void_p(snap.data_ptr()), ctypes.c_void_p(work.data_ptr()), ctypes.c_void_p(gl.data_ptr()),
+                   ctypes.c_void_p(gs.data_ptr()), _stream())
+        return gl, gs
+
     def adjoint(self, objective, nsteps, seg, ckpt, F, snap, work):
         """Per-cell FP64 gradients (dJ/d inv_lambda2, dJ/d sigma_n) of the last checkpointed run."""
         o = self._objective(*objective)
