@@ -125,8 +125,9 @@ typedef struct {
     double *dft;         /* device, FP64 [2*nfreq]                            */
 } tfl_probe;
 
-/* Create a handle; validates sizes (>= 1), spacings and dt (> 0), theta in
- * [0.5, 1], dtype, bc and PML cell counts (lo + hi <= n on a CPML axis).
+/* Create a handle; validates sizes (>= 1, nx * ny <= 2^29 so that one x-y
+ * plane is addressed with 32-bit byte offsets), spacings and dt (> 0), theta
+ * in [0.5, 1], dtype, bc and PML cell counts (lo + hi <= n on a CPML axis).
  * TFL_E_INVAL on bad values. */
 int tfl_create(const tfl_config *cfg, tfl_sim **out);
 int tfl_destroy(tfl_sim *sim);

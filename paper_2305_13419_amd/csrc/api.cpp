@@ -140,9 +140,6 @@ StepArgs<T> make_args(const tfl_sim *s)
         const size_t m = s->psi_count[ax];
         p.psiH[0] = ps; p.psiH[1] = ps + m; p.psiE[0] = ps + 2 * m; p.psiE[1] = ps + 3 * m;
     }
-    a.ntiles_x = (int)((c.nx + kTileX - 1) / kTileX);
-    a.ntiles_y = (int)((c.ny + kTileY - 1) / kTileY);
-    a.ntiles_z = (int)((c.nz + kTileZ - 1) / kTileZ);
     return a;
 }
 
@@ -301,6 +298,8 @@ int tfl_create(const tfl_config *cfg, tfl_sim **out)
     if (c.nx < 1 || c.ny < 1 || c.nz < 1) return fail(nullptr, TFL_E_INVAL, "grid sizes must be >= 1");
     if (c.nx > (1LL << 30) || c.ny > (1LL << 30) || c.nz > (1LL << 30) || c.nx * c.ny * c.nz > (1LL << 40))
         return fail(nullptr, TFL_E_INVAL, "grid too large");
+    // the sweeps address one x-y plane with 32-bit byte offsets
+    if (c.nx * c.ny > (1LL << 29)) return fail(nullptr, TFL_E_INVAL, "nx * ny must not exceed 2^29");
     if (!(c.dx > 0) || !(c.dy > 0) || !(c.dz > 0) || !std::isfinite(c.dx) || !std::isfinite(c.dy) ||
         !std::isfinite(c.dz))
         return fail(nullptr, TFL_E_INVAL, "spacings must be finite and > 0");

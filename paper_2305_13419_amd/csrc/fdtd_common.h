@@ -14,6 +14,42 @@ static __device__ __forceinline__ int logical_block(int b, int nblocks)
     return x * q + min(x, r) + m;
 }
 
+// Column tile of a z-marching sweep: kTileX x TY columns of the x-y plane and
+// TZ planes along z.  Tiles are numbered x fastest, then y, then z, and blocks
+// are renumbered so that each XCD takes a contiguous range: the blocks of one
+// XCD sweep neighbouring columns of the same planes at the same time.
+// Returns false for lanes outside the grid.
+template <int TY, int TZ>
+static __device__ __forceinline__ bool tile_of(int nx, int ny, int nz, int &i, int &j, int &k0, int &k1)
+{
+    const int ntx = (nx + kTileX - 1) / kTileX, nty = (ny + TY - 1) / TY, ntz = (nz + TZ - 1) / TZ;
+    const int t = logical_block(blockIdx.x, ntx * nty * ntz);
+    const int tx = t % ntx;
+    const int tr = t / ntx;
+    const int ty = tr % nty;
+    const int tz = tr / nty;
+    i = tx * kTileX + threadIdx.x;
+    j = ty * TY + threadIdx.y;
+    k0 = tz * TZ;
+    k1 = min(k0 + TZ, nz);
+    return i < nx && j < ny;
+}
+
+// Access at a wave-uniform base plus a 32-bit per-lane byte offset, through a
+// global (address space 1) pointer: the base stays in scalar registers and the
+// access takes the "SGPR base + VGPR offset" form.
+template <typename T>
+static __device__ __forceinline__ T ldp(const T *base, uint32_t off)
+{
+    return *(const __attribute__((address_space(1))) T *)(reinterpret_cast<const char *>(base) + off);
+}
+
+template <typename T>
+static __device__ __forceinline__ void stp(T *base, uint32_t off, T v)
+{
+    *(__attribute__((address_space(1))) T *)(reinterpret_cast<char *>(base) + off) = v;
+}
+
 static __device__ __forceinline__ int slab_slot(int i, int lo, int hi, int n)
 {
     if (i < lo) return i;
@@ -21,10 +57,21 @@ static __device__ __forceinline__ int slab_slot(int i, int lo, int hi, int n)
     return -1;
 }
 
+// 1/c for c = 1..4 without branches: 2^-(c>>1) is exact for 1, 2 and 4.
 template <typename T>
 static __device__ __forceinline__ T inv_count(int c)
 {
-    return c == 1 ? T(1) : (c == 2 ? T(0.5) : (c == 3 ? T(1) / T(3) : T(0.25)));
+    const T p2 = ldexp(T(1), -(c >> 1));
+    return c == 3 ? T(1) / T(3) : p2;
+}
+
+// A wave-uniform element offset kept opaque to loop strength reduction, so that
+// accesses inside z-marching loops stay "scalar base + 32-bit lane offset"
+// instead of becoming per-lane 64-bit pointer induction variables.
+static __device__ __forceinline__ long long opaque_offset(long long off)
+{
+    asm volatile("" : "+s"(off));
+    return off;
 }
 
 // Per-edge material of the four cells q0..q3 sharing an edge (Sec. 3): if any

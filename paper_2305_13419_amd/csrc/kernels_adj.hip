@@ -66,31 +66,15 @@ __device__ __forceinline__ T w_face(const AdjArgs<T> &A, int h, int a, int i, in
     return -hdt * sg * P.kh[pos] * lh + P.ch[pos] * tot;
 }
 
-template <typename T>
-__device__ __forceinline__ void tile_coords(const StepArgs<T> &f, int &i, int &j, int &k0, int &k1)
-{
-    const int nb = f.ntiles_x * f.ntiles_y * f.ntiles_z;
-    const int t = logical_block(blockIdx.x, nb);
-    const int tx = t % f.ntiles_x;
-    const int tr = t / f.ntiles_x;
-    const int ty = tr % f.ntiles_y;
-    const int tz = tr / f.ntiles_y;
-    i = tx * kTileX + threadIdx.x;
-    j = ty * kTileY + threadIdx.y;
-    k0 = tz * kTileZ;
-    k1 = min(k0 + kTileZ, f.g.nz);
-}
-
 // ---------------------------------------------------------------------------
 // Face sweep: lH'' = lH + curl W (F2^T), then the H-side PML variables (F1^T)
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kTileX *kTileY) void adj_face_kernel(const AdjArgs<T> A)
+template <typename T, int TY, int TZ>
+__global__ __launch_bounds__(kTileX *TY) void adj_face_kernel(const AdjArgs<T> A)
 {
-    int i, j, k0, k1;
-    tile_coords(A.f, i, j, k0, k1);
     const int nx = A.f.g.nx, ny = A.f.g.ny, nz = A.f.g.nz;
-    if (i >= nx || j >= ny) return;
+    int i, j, k0, k1;
+    if (!tile_of<TY, TZ>(nx, ny, nz, i, j, k0, k1)) return;
     const long long sxy = A.f.g.sxy;
     const int ip = (i + 1 == nx) ? 0 : i + 1;
     const int jp = (j + 1 == ny) ? 0 : j + 1;
@@ -156,34 +140,47 @@ __device__ __forceinline__ void edge_cells(const StepArgs<T> &f, int comp, int i
     }
 }
 
+// Coefficients of one edge (as in the forward E pass): a, b and j = dt ell/mu0.
 template <typename T>
-__device__ __forceinline__ void adj_edge_local(const AdjArgs<T> &A, int q, long long c, const int pos[3], T lEq,
-                                               const T e4[4], const T s4[4], const T l4[4])
+struct AdjCoef {
+    T ca, cb, cj;
+};
+
+template <typename T>
+__device__ __forceinline__ AdjCoef<T> adj_coef(const T e4[4], const T s4[4], const T l4[4], T dt, T theta, T hdt)
+{
+    T eps, sig, ell;
+    edge_material(e4, s4, l4, eps, sig, ell);
+    const T sdt = sig * dt;
+    const T inv = T(1) / (eps + theta * sdt);
+    return {(eps - (T(1) - theta) * sdt) * inv, dt * inv, hdt * ell};
+}
+
+// Edge-local part of F2^T for component q of the edge at plane offset b, lane
+// byte offsets ow (arrays of T) and od (FP64 gradient arrays), from values
+// loaded by the caller: lJ and gL (superconducting edges only), gS, E^n, E'_pre.
+template <typename T>
+__device__ __forceinline__ void adj_edge_local(const AdjArgs<T> &A, int q, long long b, uint32_t ow, uint32_t od,
+                                               const int pos[3], T lEq, const AdjCoef<T> &k, T En, T Ep, T lJ,
+                                               double gL, double gS)
 {
     const int nx = A.f.g.nx, ny = A.f.g.ny;
-    const T dt = A.f.dt, theta = A.f.theta, hdt = A.f.hdt;
+    const T theta = A.f.theta, hdt = A.f.hdt;
     // PEC wall: E' = 0 there, so its adjoint does not propagate
     bool wall = false;
     for (int a = 0; a < 3; ++a)
         if (a != q && A.f.pml[a].on && pos[a] == 0) wall = true;
     const T lEp = wall ? T(0) : lEq;
-    T eps, sig, ell;
-    edge_material(e4, s4, l4, eps, sig, ell);
-    const T sdt = sig * dt;
-    const T inv = T(1) / (eps + theta * sdt);
-    const T ca = (eps - (T(1) - theta) * sdt) * inv;
-    const T cb = dt * inv;
-    const T mu = cb * lEp;
-    const T En = A.En[q][c];
+    const T mu = k.cb * lEp;
     T ljt = T(0);
-    if (ell > T(0)) {
-        ljt = A.lJ[q][c] - mu;
-        A.lJ[q][c] = ljt;
-        A.gL[q][c] += (double)hdt * (double)ljt * (double)En;
+    if (k.cj > T(0)) {
+        ljt = lJ - mu;
+        stp(A.lJ[q] + b, ow, ljt);
+        stp(A.gL[q] + b, od, gL + (double)hdt * (double)ljt * (double)En);
     }
-    A.gS[q][c] += -(double)lEp * (double)cb * ((double)theta * (double)A.Ep[q][c] + (1.0 - (double)theta) * (double)En);
-    A.mu[q][c] = mu;
-    A.lE[q][c] = ca * lEp + hdt * ell * ljt;
+    stp(A.gS[q] + b, od, gS - (double)lEp * (double)k.cb * ((double)theta * (double)Ep + (1.0 - (double)theta) * (double)En));
+    stp(A.mu[q] + b, ow, mu);
+    stp(A.lE[q] + b, ow, k.ca * lEp + k.cj * ljt);
     // E-side PML adjoint variables: tot = bn * stored + sg mu
     for (int a = 0; a < 3; ++a) {
         if (a == q) continue;
@@ -197,78 +194,121 @@ __device__ __forceinline__ void adj_edge_local(const AdjArgs<T> &A, int q, long 
     }
 }
 
-// z-marching like the forward E pass: the maps of plane k-1 and the z terms
-// of the curl^T at k-1 are carried in registers.
-template <typename T>
-__global__ __launch_bounds__(kTileX *kTileY) void adj_edge_kernel(const AdjArgs<T> A)
+// z-marching like the forward E pass: the maps of plane k-1 and the z terms of
+// the curl^T at k-1 are carried in registers, and the edge coefficients of a
+// plane are formed one iteration ahead so that all loads of an iteration
+// (including lJ and gL on superconducting edges) are issued before the first wait.
+template <typename T, int TY, int TZ>
+__global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A)
 {
-    int i, j, k0, k1;
-    tile_coords(A.f, i, j, k0, k1);
     const int nx = A.f.g.nx, ny = A.f.g.ny, nz = A.f.g.nz;
-    if (i >= nx || j >= ny) return;
+    int i, j, k0, k1;
+    if (!tile_of<TY, TZ>(nx, ny, nz, i, j, k0, k1)) return;
     const long long sxy = A.f.g.sxy;
     const int im = (i == 0) ? nx - 1 : i - 1;
     const int jm = (j == 0) ? ny - 1 : j - 1;
-    const long long r0 = (long long)j * nx, rm = (long long)jm * nx;
+    // byte offsets inside one plane: each access is a plane base (scalar registers) plus a lane offset
+    const uint32_t cell = uint32_t(j * nx + i);
+    const uint32_t o00 = cell * sizeof(T), o10 = uint32_t(j * nx + im) * sizeof(T);
+    const uint32_t o01 = uint32_t(jm * nx + i) * sizeof(T), o11 = uint32_t(jm * nx + im) * sizeof(T);
+    const uint32_t od = cell * sizeof(double);
     const T rdx = A.f.rd[0], rdy = A.f.rd[1], rdz = A.f.rd[2];
-    const T *__restrict__ meps = A.f.eps;
-    const T *__restrict__ msig = A.f.sig;
-    const T *__restrict__ mell = A.f.ell;
+    const T dt = A.f.dt, theta = A.f.theta, hdt = A.f.hdt;
     const int km0 = (k0 == 0) ? nz - 1 : k0 - 1;
-    const long long bm = (long long)km0 * sxy;
     T whyz_m = T(0), whxz_m = T(0);
     if (A.doC) {
-        whyz_m = w_face(A, 1, 2, i, j, km0, A.lH[1][bm + r0 + i]);
-        whxz_m = w_face(A, 0, 2, i, j, km0, A.lH[0][bm + r0 + i]);
+        const long long bm = (long long)km0 * sxy;
+        whyz_m = w_face(A, 1, 2, i, j, km0, ldp(A.lH[1] + bm, o00));
+        whxz_m = w_face(A, 0, 2, i, j, km0, ldp(A.lH[0] + bm, o00));
     }
     T pe00 = T(0), pe10 = T(0), pe01 = T(0), ps00 = T(0), ps10 = T(0), ps01 = T(0), pl00 = T(0), pl10 = T(0),
       pl01 = T(0);
+    AdjCoef<T> cq[3] = {};
+    struct Maps {
+        T e00, e10, e01, e11, s00, s10, s01, s11, l00, l10, l01, l11;
+    };
+    auto load_maps = [&](int kk) {
+        const long long b = opaque_offset((long long)kk * sxy);
+        const T *me = A.f.eps + b, *ms = A.f.sig + b, *ml = A.f.ell + b;
+        return Maps{ldp(me, o00), ldp(me, o10), ldp(me, o01), ldp(me, o11),
+                    ldp(ms, o00), ldp(ms, o10), ldp(ms, o01), ldp(ms, o11),
+                    ldp(ml, o00), ldp(ml, o10), ldp(ml, o01), ldp(ml, o11)};
+    };
+    auto coefs = [&](const Maps &m) {
+        {   // Ex: cells (j,k), (j,k-1), (j-1,k), (j-1,k-1)
+            const T e[4] = {m.e00, pe00, m.e01, pe01}, s[4] = {m.s00, ps00, m.s01, ps01},
+                    l[4] = {m.l00, pl00, m.l01, pl01};
+            cq[0] = adj_coef(e, s, l, dt, theta, hdt);
+        }
+        {   // Ey: cells (k,i), (k,i-1), (k-1,i), (k-1,i-1)
+            const T e[4] = {m.e00, m.e10, pe00, pe10}, s[4] = {m.s00, m.s10, ps00, ps10},
+                    l[4] = {m.l00, m.l10, pl00, pl10};
+            cq[1] = adj_coef(e, s, l, dt, theta, hdt);
+        }
+        {   // Ez: cells (i,j), (i,j-1), (i-1,j), (i-1,j-1)
+            const T e[4] = {m.e00, m.e01, m.e10, m.e11}, s[4] = {m.s00, m.s01, m.s10, m.s11},
+                    l[4] = {m.l00, m.l01, m.l10, m.l11};
+            cq[2] = adj_coef(e, s, l, dt, theta, hdt);
+        }
+        pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
+        ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
+        pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
+    };
     if (A.doA) {
-        pe00 = meps[bm + r0 + i]; pe10 = meps[bm + r0 + im]; pe01 = meps[bm + rm + i];
-        ps00 = msig[bm + r0 + i]; ps10 = msig[bm + r0 + im]; ps01 = msig[bm + rm + i];
-        pl00 = mell[bm + r0 + i]; pl10 = mell[bm + r0 + im]; pl01 = mell[bm + rm + i];
+        const Maps m = load_maps(km0);
+        pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
+        ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
+        pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
+        coefs(load_maps(k0));
     }
     for (int k = k0; k < k1; ++k) {
-        const long long b0 = (long long)k * sxy;
-        const long long c = b0 + r0 + i;
-        const long long cxm = b0 + r0 + im, cym = b0 + rm + i, cxym = b0 + rm + im;
-        T le[3] = {A.lE[0][c], A.lE[1][c], A.lE[2][c]};
+        const long long b = opaque_offset((long long)k * sxy);
+        T le[3] = {ldp(A.lE[0] + b, o00), ldp(A.lE[1] + b, o00), ldp(A.lE[2] + b, o00)};
+        T hx0 = T(0), hy0 = T(0), hz0 = T(0), hz_ym = T(0), hz_xm = T(0), hx_ym = T(0), hy_xm = T(0);
         if (A.doC) {
-            const T hx0 = A.lH[0][c], hy0 = A.lH[1][c], hz0 = A.lH[2][c];
+            const T *Hx = A.lH[0] + b, *Hy = A.lH[1] + b, *Hz = A.lH[2] + b;
+            hx0 = ldp(Hx, o00); hy0 = ldp(Hy, o00); hz0 = ldp(Hz, o00);
+            hz_ym = ldp(Hz, o01); hz_xm = ldp(Hz, o10); hx_ym = ldp(Hx, o01); hy_xm = ldp(Hy, o10);
+        }
+        const AdjCoef<T> kq[3] = {cq[0], cq[1], cq[2]};
+        T En[3] = {}, Ep[3] = {}, lJ[3] = {};
+        double gL[3] = {}, gS[3] = {};
+        Maps mn{};
+        if (A.doA) {
+            for (int q = 0; q < 3; ++q) {
+                if (kq[q].cj > T(0)) {
+                    lJ[q] = ldp(A.lJ[q] + b, o00);
+                    gL[q] = ldp(A.gL[q] + b, od);
+                }
+            }
+            for (int q = 0; q < 3; ++q) {
+                En[q] = ldp(A.En[q] + b, o00);
+                Ep[q] = ldp(A.Ep[q] + b, o00);
+                gS[q] = ldp(A.gS[q] + b, od);
+            }
+            // maps of the next plane (the last iteration re-reads its own plane and discards them)
+            mn = load_maps(k + 1 < nz ? k + 1 : k);
+        }
+        if (A.doC) {
             const T whyz = w_face(A, 1, 2, i, j, k, hy0), whxz = w_face(A, 0, 2, i, j, k, hx0);
             // Ex: terms (Hy, z) and (Hz, y); Ey: (Hx, z) and (Hz, x); Ez: (Hx, y) and (Hy, x)
-            le[0] += (whyz_m - whyz) * rdz + (w_face(A, 2, 1, i, jm, k, A.lH[2][cym]) - w_face(A, 2, 1, i, j, k, hz0)) * rdy;
-            le[1] += (whxz_m - whxz) * rdz + (w_face(A, 2, 0, im, j, k, A.lH[2][cxm]) - w_face(A, 2, 0, i, j, k, hz0)) * rdx;
-            le[2] += (w_face(A, 0, 1, i, jm, k, A.lH[0][cym]) - w_face(A, 0, 1, i, j, k, hx0)) * rdy +
-                     (w_face(A, 1, 0, im, j, k, A.lH[1][cxm]) - w_face(A, 1, 0, i, j, k, hy0)) * rdx;
+            le[0] += (whyz_m - whyz) * rdz + (w_face(A, 2, 1, i, jm, k, hz_ym) - w_face(A, 2, 1, i, j, k, hz0)) * rdy;
+            le[1] += (whxz_m - whxz) * rdz + (w_face(A, 2, 0, im, j, k, hz_xm) - w_face(A, 2, 0, i, j, k, hz0)) * rdx;
+            le[2] += (w_face(A, 0, 1, i, jm, k, hx_ym) - w_face(A, 0, 1, i, j, k, hx0)) * rdy +
+                     (w_face(A, 1, 0, im, j, k, hy_xm) - w_face(A, 1, 0, i, j, k, hy0)) * rdx;
             whyz_m = whyz;
             whxz_m = whxz;
         }
         if (A.obj && i >= A.ob[0] && i < A.ob[1] && j >= A.ob[2] && j < A.ob[3] && k >= A.ob[4] && k < A.ob[5])
             le[A.ocomp] += (T)A.og;
         if (!A.doA) {
-            for (int q = 0; q < 3; ++q) A.lE[q][c] = le[q];
+            for (int q = 0; q < 3; ++q) stp(A.lE[q] + b, o00, le[q]);
             continue;
         }
-        const T e00 = meps[c], e10 = meps[cxm], e01 = meps[cym], e11 = meps[cxym];
-        const T s00 = msig[c], s10 = msig[cxm], s01 = msig[cym], s11 = msig[cxym];
-        const T l00 = mell[c], l10 = mell[cxm], l01 = mell[cym], l11 = mell[cxym];
         const int pos[3] = {i, j, k};
-        {
-            const T e[4] = {e00, pe00, e01, pe01}, s[4] = {s00, ps00, s01, ps01}, l[4] = {l00, pl00, l01, pl01};
-            adj_edge_local(A, 0, c, pos, le[0], e, s, l);
-        }
-        {
-            const T e[4] = {e00, e10, pe00, pe10}, s[4] = {s00, s10, ps00, ps10}, l[4] = {l00, l10, pl00, pl10};
-            adj_edge_local(A, 1, c, pos, le[1], e, s, l);
-        }
-        {
-            const T e[4] = {e00, e01, e10, e11}, s[4] = {s00, s01, s10, s11}, l[4] = {l00, l01, l10, l11};
-            adj_edge_local(A, 2, c, pos, le[2], e, s, l);
-        }
-        pe00 = e00; pe10 = e10; pe01 = e01;
-        ps00 = s00; ps10 = s10; ps01 = s01;
-        pl00 = l00; pl10 = l10; pl01 = l01;
+        for (int q = 0; q < 3; ++q)
+            adj_edge_local(A, q, b, o00, od, pos, le[q], kq[q], En[q], Ep[q], lJ[q], gL[q], gS[q]);
+        coefs(mn);
     }
 }
 
@@ -342,20 +382,42 @@ __global__ void adj_edge_to_cell_kernel(const AdjArgs<T> A, double *gl_cell, dou
 
 }  // namespace
 
+// Both adjoint sweeps: 4 rows per block, the z run chosen as in the forward
+// sweeps for at least 8192 wavefronts per launch.
+constexpr int kAdjTileY = 4;
+constexpr long long kAdjWaves = 8192;
+
+template <typename T, int TY, int TZ>
+static void launch_adj_tz(bool faces, const AdjArgs<T> &a, hipStream_t s)
+{
+    const dim3 blk(kTileX, TY), grd(tile_blocks(a.f.g, TY, TZ));
+    if (faces)
+        hipLaunchKernelGGL((adj_face_kernel<T, TY, TZ>), grd, blk, 0, s, a);
+    else
+        hipLaunchKernelGGL((adj_edge_kernel<T, TY, TZ>), grd, blk, 0, s, a);
+}
+
+template <typename T>
+static hipError_t launch_adj_sweep(bool faces, const AdjArgs<T> &a, hipStream_t s)
+{
+    switch (pick_tile_z(a.f.g, kAdjTileY, kAdjWaves, 32)) {
+    case 32: launch_adj_tz<T, kAdjTileY, 32>(faces, a, s); break;
+    case 16: launch_adj_tz<T, kAdjTileY, 16>(faces, a, s); break;
+    default: launch_adj_tz<T, kAdjTileY, 8>(faces, a, s); break;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_adj_faces(const AdjArgs<T> &a, hipStream_t s)
 {
-    const int nb = a.f.ntiles_x * a.f.ntiles_y * a.f.ntiles_z;
-    hipLaunchKernelGGL(adj_face_kernel<T>, dim3(nb), dim3(kTileX, kTileY), 0, s, a);
-    return hipGetLastError();
+    return launch_adj_sweep<T>(true, a, s);
 }
 
 template <typename T>
 hipError_t launch_adj_edges(const AdjArgs<T> &a, hipStream_t s)
 {
-    const int nb = a.f.ntiles_x * a.f.ntiles_y * a.f.ntiles_z;
-    hipLaunchKernelGGL(adj_edge_kernel<T>, dim3(nb), dim3(kTileX, kTileY), 0, s, a);
-    return hipGetLastError();
+    return launch_adj_sweep<T>(false, a, s);
 }
 
 static int grid_blocks(long long N)

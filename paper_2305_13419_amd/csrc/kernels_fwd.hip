@@ -23,21 +23,12 @@ namespace {
 // ---------------------------------------------------------------------------
 // H pass (Faraday's law)
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kTileX *kTileY, TFL_MIN_WAVES) void h_pass_kernel(const StepArgs<T> a)
+template <typename T, int TY, int TZ>
+__global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void h_pass_kernel(const StepArgs<T> a)
 {
-    const int nb = a.ntiles_x * a.ntiles_y * a.ntiles_z;
-    const int t = logical_block(blockIdx.x, nb);
-    const int tx = t % a.ntiles_x;
-    const int tr = t / a.ntiles_x;
-    const int ty = tr % a.ntiles_y;
-    const int tz = tr / a.ntiles_y;
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-    const int i = tx * kTileX + threadIdx.x;
-    const int j = ty * kTileY + threadIdx.y;
-    if (i >= nx || j >= ny) return;
-    const int k0 = tz * kTileZ;
-    const int k1 = min(k0 + kTileZ, nz);
+    int i, j, k0, k1;
+    if (!tile_of<TY, TZ>(nx, ny, nz, i, j, k0, k1)) return;
     const long long sxy = a.g.sxy;
     const int ip = (i + 1 == nx) ? 0 : i + 1;
     const int jp = (j + 1 == ny) ? 0 : j + 1;
@@ -98,64 +89,37 @@ __global__ __launch_bounds__(kTileX *kTileY, TFL_MIN_WAVES) void h_pass_kernel(c
 // ---------------------------------------------------------------------------
 // E pass (London supercurrent + Ampere's law with the theta-weighted Ohmic term)
 // ---------------------------------------------------------------------------
+// Coefficients of one edge: E^{n+1} = ca E^n + cb (curl H - Js^{n+1/2}) and
+// Js^{n+1/2} = Js^{n-1/2} + cj E^n with cj = dt ell_e / mu0 (cj = 0 off the
+// superconductor, where Js stays zero and is neither read nor written).
 template <typename T>
-__device__ __forceinline__ void update_edge(const T *__restrict__ E, T *__restrict__ Eo, T *__restrict__ J,
-                                            long long c, T curl, const T e[4], const T s[4], const T l[4], T dt,
-                                            T theta, T hdt, bool wall)
+struct EdgeCoef {
+    T ca, cb, cj;
+};
+
+template <typename T>
+__device__ __forceinline__ EdgeCoef<T> edge_coef(const T e[4], const T s[4], const T l[4], T dt, T theta, T hdt)
 {
     T eps, sig, ell;
     edge_material(e, s, l, eps, sig, ell);
     const T sdt = sig * dt;
     const T inv = T(1) / (eps + theta * sdt);
-    const T ca = (eps - (T(1) - theta) * sdt) * inv;
-    const T cb = dt * inv;
-    const T E0 = E[c];
-    T Jn = T(0);
-    if (ell > T(0)) {
-        Jn = J[c] + hdt * ell * E0;
-        J[c] = Jn;
-    }
-    const T En = ca * E0 + cb * (curl - Jn);
-    Eo[c] = wall ? T(0) : En;
+    return {(eps - (T(1) - theta) * sdt) * inv, dt * inv, hdt * ell};
 }
 
-template <typename T>
-__global__ __launch_bounds__(kTileX *kTileY, TFL_MIN_WAVES) void e_pass_kernel(const StepArgs<T> a)
+template <typename T, int TY, int TZ>
+__global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const StepArgs<T> a)
 {
-    const int nb = a.ntiles_x * a.ntiles_y * a.ntiles_z;
-    const int t = logical_block(blockIdx.x, nb);
-    const int tx = t % a.ntiles_x;
-    const int tr = t / a.ntiles_x;
-    const int ty = tr % a.ntiles_y;
-    const int tz = tr / a.ntiles_y;
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-    const int i = tx * kTileX + threadIdx.x;
-    const int j = ty * kTileY + threadIdx.y;
-    if (i >= nx || j >= ny) return;
-    const int k0 = tz * kTileZ;
-    const int k1 = min(k0 + kTileZ, nz);
+    int i, j, k0, k1;
+    if (!tile_of<TY, TZ>(nx, ny, nz, i, j, k0, k1)) return;
     const long long sxy = a.g.sxy;
     const int im = (i == 0) ? nx - 1 : i - 1;
     const int jm = (j == 0) ? ny - 1 : j - 1;
-    const long long r0 = (long long)j * nx, rm = (long long)jm * nx;
-    // E and Eout are the same arrays except in the adjoint's recomputation; either way each thread
-    // reads E[c] before writing Eout[c] at the same c and no other thread touches c, so the restrict
-    // qualifiers only let the compiler move other planes' accesses.
-    const T *__restrict__ Ex = a.E[0];
-    const T *__restrict__ Ey = a.E[1];
-    const T *__restrict__ Ez = a.E[2];
-    T *__restrict__ Exo = a.Eout[0];
-    T *__restrict__ Eyo = a.Eout[1];
-    T *__restrict__ Ezo = a.Eout[2];
-    T *__restrict__ Jx = a.J[0];
-    T *__restrict__ Jy = a.J[1];
-    T *__restrict__ Jz = a.J[2];
-    const T *__restrict__ Hx = a.H[0];
-    const T *__restrict__ Hy = a.H[1];
-    const T *__restrict__ Hz = a.H[2];
-    const T *__restrict__ meps = a.eps;
-    const T *__restrict__ msig = a.sig;
-    const T *__restrict__ mell = a.ell;
+    // byte offsets inside one plane (a plane is below 4 GiB): each access is a uniform plane base in
+    // scalar registers plus one of these four 32-bit lane offsets
+    const uint32_t o00 = uint32_t(j * nx + i) * sizeof(T), o10 = uint32_t(j * nx + im) * sizeof(T);
+    const uint32_t o01 = uint32_t(jm * nx + i) * sizeof(T), o11 = uint32_t(jm * nx + im) * sizeof(T);
     const T rdx = a.rd[0], rdy = a.rd[1], rdz = a.rd[2];
     const T dt = a.dt, theta = a.theta, hdt = a.hdt;
     const PmlAxis<T> &px = a.pml[0], &py = a.pml[1], &pz = a.pml[2];
@@ -164,21 +128,71 @@ __global__ __launch_bounds__(kTileX *kTileY, TFL_MIN_WAVES) void e_pass_kernel(c
     const bool wall_x = px.on && i == 0;
     const bool wall_y = py.on && j == 0;
 
-    // plane k-1: H and the maps of cells (i,j), (i-1,j), (i,j-1)
+    // Materials of plane k-1 at cells (i,j), (i-1,j), (i,j-1) are carried in registers and the edge
+    // coefficients of a plane are formed one iteration ahead, so all loads of an iteration (Js on
+    // superconducting edges, H, E, the maps of the next plane) are issued before the first wait.
+    T pe00, pe10, pe01, ps00, ps10, ps01, pl00, pl10, pl01;
+    EdgeCoef<T> cx, cy, cz;
+    struct Maps {
+        T e00, e10, e01, e11, s00, s10, s01, s11, l00, l10, l01, l11;
+    };
+    auto load_maps = [&](int kk) {
+        const long long b = opaque_offset((long long)kk * sxy);
+        const T *me = a.eps + b, *ms = a.sig + b, *ml = a.ell + b;
+        return Maps{ldp(me, o00), ldp(me, o10), ldp(me, o01), ldp(me, o11),
+                    ldp(ms, o00), ldp(ms, o10), ldp(ms, o01), ldp(ms, o11),
+                    ldp(ml, o00), ldp(ml, o10), ldp(ml, o01), ldp(ml, o11)};
+    };
+    auto coefs = [&](const Maps &m) {
+        {   // Ex: cells (j,k), (j,k-1), (j-1,k), (j-1,k-1)
+            const T e[4] = {m.e00, pe00, m.e01, pe01}, s[4] = {m.s00, ps00, m.s01, ps01},
+                    l[4] = {m.l00, pl00, m.l01, pl01};
+            cx = edge_coef(e, s, l, dt, theta, hdt);
+        }
+        {   // Ey: cells (k,i), (k,i-1), (k-1,i), (k-1,i-1)
+            const T e[4] = {m.e00, m.e10, pe00, pe10}, s[4] = {m.s00, m.s10, ps00, ps10},
+                    l[4] = {m.l00, m.l10, pl00, pl10};
+            cy = edge_coef(e, s, l, dt, theta, hdt);
+        }
+        {   // Ez: cells (i,j), (i,j-1), (i-1,j), (i-1,j-1)
+            const T e[4] = {m.e00, m.e01, m.e10, m.e11}, s[4] = {m.s00, m.s01, m.s10, m.s11},
+                    l[4] = {m.l00, m.l01, m.l10, m.l11};
+            cz = edge_coef(e, s, l, dt, theta, hdt);
+        }
+        pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
+        ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
+        pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
+    };
     const int km0 = (k0 == 0) ? nz - 1 : k0 - 1;
-    const long long bm = (long long)km0 * sxy;
-    T hx_km = Hx[bm + r0 + i], hy_km = Hy[bm + r0 + i];
-    T pe00 = meps[bm + r0 + i], pe10 = meps[bm + r0 + im], pe01 = meps[bm + rm + i];
-    T ps00 = msig[bm + r0 + i], ps10 = msig[bm + r0 + im], ps01 = msig[bm + rm + i];
-    T pl00 = mell[bm + r0 + i], pl10 = mell[bm + r0 + im], pl01 = mell[bm + rm + i];
+    T hx_km, hy_km;
+    {
+        const long long b = (long long)km0 * sxy;
+        const Maps m = load_maps(km0);
+        pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
+        ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
+        pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
+        hx_km = ldp(a.H[0] + b, o00);
+        hy_km = ldp(a.H[1] + b, o00);
+    }
+    coefs(load_maps(k0));
 
     for (int k = k0; k < k1; ++k) {
-        const long long b0 = (long long)k * sxy;
-        const long long c = b0 + r0 + i;
-        const long long cxm = b0 + r0 + im, cym = b0 + rm + i, cxym = b0 + rm + im;
-        const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
-        const T hz_xm = Hz[cxm], hz_ym = Hz[cym];
-        const T hy_xm = Hy[cxm], hx_ym = Hx[cym];
+        const long long b = opaque_offset((long long)k * sxy);
+        T *Jx = a.J[0] + b, *Jy = a.J[1] + b, *Jz = a.J[2] + b;
+        const EdgeCoef<T> qx = cx, qy = cy, qz = cz;
+        T jx = T(0), jy = T(0), jz = T(0);
+        if (qx.cj > T(0)) jx = ldp(Jx, o00);
+        if (qy.cj > T(0)) jy = ldp(Jy, o00);
+        if (qz.cj > T(0)) jz = ldp(Jz, o00);
+        const T *Hx = a.H[0] + b, *Hy = a.H[1] + b, *Hz = a.H[2] + b;
+        const T *Ex = a.E[0] + b, *Ey = a.E[1] + b, *Ez = a.E[2] + b;
+        const T hx = ldp(Hx, o00), hy = ldp(Hy, o00), hz = ldp(Hz, o00);
+        const T hz_xm = ldp(Hz, o10), hz_ym = ldp(Hz, o01);
+        const T hy_xm = ldp(Hy, o10), hx_ym = ldp(Hx, o01);
+        const T ex = ldp(Ex, o00), ey = ldp(Ey, o00), ez = ldp(Ez, o00);
+        // materials of the next plane (the last iteration re-reads its own plane and discards them)
+        const Maps mn = load_maps(k + 1 < nz ? k + 1 : k);
+
         T dyHz = (hz - hz_ym) * rdy, dzHy = (hy - hy_km) * rdz;  // Ex
         T dzHx = (hx - hx_km) * rdz, dxHz = (hz - hz_xm) * rdx;  // Ey
         T dxHy = (hy - hy_xm) * rdx, dyHx = (hx - hx_ym) * rdy;  // Ez
@@ -202,26 +216,21 @@ __global__ __launch_bounds__(kTileX *kTileY, TFL_MIN_WAVES) void e_pass_kernel(c
                 dzHx = stretch(dzHx, pz.psiE[1], p, pz.bn[k], pz.cn[k], pz.kn[k]);  // Ey
             }
         }
-        const T e00 = meps[c], e10 = meps[cxm], e01 = meps[cym], e11 = meps[cxym];
-        const T s00 = msig[c], s10 = msig[cxm], s01 = msig[cym], s11 = msig[cxym];
-        const T l00 = mell[c], l10 = mell[cxm], l01 = mell[cym], l11 = mell[cxym];
-        {   // Ex: cells (j,k), (j,k-1), (j-1,k), (j-1,k-1)
-            const T e[4] = {e00, pe00, e01, pe01}, s[4] = {s00, ps00, s01, ps01}, l[4] = {l00, pl00, l01, pl01};
-            update_edge(Ex, Exo, Jx, c, dyHz - dzHy, e, s, l, dt, theta, hdt, wall_y || wall_z);
-        }
-        {   // Ey: cells (k,i), (k,i-1), (k-1,i), (k-1,i-1)
-            const T e[4] = {e00, e10, pe00, pe10}, s[4] = {s00, s10, ps00, ps10}, l[4] = {l00, l10, pl00, pl10};
-            update_edge(Ey, Eyo, Jy, c, dzHx - dxHz, e, s, l, dt, theta, hdt, wall_z || wall_x);
-        }
-        {   // Ez: cells (i,j), (i,j-1), (i-1,j), (i-1,j-1)
-            const T e[4] = {e00, e01, e10, e11}, s[4] = {s00, s01, s10, s11}, l[4] = {l00, l01, l10, l11};
-            update_edge(Ez, Ezo, Jz, c, dxHy - dyHx, e, s, l, dt, theta, hdt, wall_x || wall_y);
-        }
+        if (qx.cj > T(0)) { jx = jx + qx.cj * ex; stp(Jx, o00, jx); }
+        if (qy.cj > T(0)) { jy = jy + qy.cj * ey; stp(Jy, o00, jy); }
+        if (qz.cj > T(0)) { jz = jz + qz.cj * ez; stp(Jz, o00, jz); }
+        const T nex = qx.ca * ex + qx.cb * ((dyHz - dzHy) - jx);
+        const T ney = qy.ca * ey + qy.cb * ((dzHx - dxHz) - jy);
+        const T nez = qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz);
+        // E and Eout are the same arrays except in the adjoint's recomputation; each lane reads E at
+        // its own offset before writing Eout there and no other lane touches that word
+        T *Exo = a.Eout[0] + b, *Eyo = a.Eout[1] + b, *Ezo = a.Eout[2] + b;
+        stp(Exo, o00, (wall_y || wall_z) ? T(0) : nex);
+        stp(Eyo, o00, (wall_z || wall_x) ? T(0) : ney);
+        stp(Ezo, o00, (wall_x || wall_y) ? T(0) : nez);
         hx_km = hx;
         hy_km = hy;
-        pe00 = e00; pe10 = e10; pe01 = e01;
-        ps00 = s00; ps10 = s10; ps01 = s01;
-        pl00 = l00; pl10 = l10; pl01 = l01;
+        coefs(mn);
     }
 }
 
@@ -544,19 +553,52 @@ __global__ void fill_zero_kernel(uint32_t *p, size_t nwords)
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+// Tile shapes of the two forward sweeps per storage type: rows of 64-wide
+// wavefronts per block, the longest z run, and the wavefronts a launch should
+// at least provide (from a sweep of shapes on MI355X: the FP64 H pass is
+// fastest with all its tiles resident in one round, the other sweeps with
+// about two rounds of waves).
+template <typename T>
+struct FwdTiles;
+template <>
+struct FwdTiles<double> {
+    static constexpr int hy = 4, hz_max = 64, ey = 8, ez_max = 64;
+    static constexpr long long h_waves = 4096, e_waves = 8192;
+};
+template <>
+struct FwdTiles<float> {
+    static constexpr int hy = 4, hz_max = 64, ey = 4, ez_max = 64;
+    static constexpr long long h_waves = 8192, e_waves = 8192;
+};
+
+// Launch kernel template K<T, TY, TZ> with TZ in {8, 16, 32, 64} chosen at run time.
+#define TFL_LAUNCH_TZ(K, T, TY, TZ, a, s)                                                                        \
+    do {                                                                                                       \
+        const dim3 blk(kTileX, TY);                                                                            \
+        const dim3 grd(tile_blocks((a).g, TY, TZ));                                                            \
+        switch (TZ) {                                                                                          \
+        case 64: hipLaunchKernelGGL((K<T, TY, 64>), grd, blk, 0, s, a); break;                                 \
+        case 32: hipLaunchKernelGGL((K<T, TY, 32>), grd, blk, 0, s, a); break;                                 \
+        case 16: hipLaunchKernelGGL((K<T, TY, 16>), grd, blk, 0, s, a); break;                                 \
+        default: hipLaunchKernelGGL((K<T, TY, 8>), grd, blk, 0, s, a); break;                                  \
+        }                                                                                                      \
+    } while (0)
+
 template <typename T>
 hipError_t launch_h_pass(const StepArgs<T> &a, hipStream_t s)
 {
-    const int nb = a.ntiles_x * a.ntiles_y * a.ntiles_z;
-    hipLaunchKernelGGL(h_pass_kernel<T>, dim3(nb), dim3(kTileX, kTileY), 0, s, a);
+    using C = FwdTiles<T>;
+    const int tz = pick_tile_z(a.g, C::hy, C::h_waves, C::hz_max);
+    TFL_LAUNCH_TZ(h_pass_kernel, T, C::hy, tz, a, s);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t s)
 {
-    const int nb = a.ntiles_x * a.ntiles_y * a.ntiles_z;
-    hipLaunchKernelGGL(e_pass_kernel<T>, dim3(nb), dim3(kTileX, kTileY), 0, s, a);
+    using C = FwdTiles<T>;
+    const int tz = pick_tile_z(a.g, C::ey, C::e_waves, C::ez_max);
+    TFL_LAUNCH_TZ(e_pass_kernel, T, C::ey, tz, a, s);
     return hipGetLastError();
 }
 

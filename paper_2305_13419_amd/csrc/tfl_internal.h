@@ -12,21 +12,13 @@ constexpr double kEps0 = 8.8541878128e-12;  // F/m (CODATA 2018)
 constexpr double kMu0 = 1.25663706212e-6;   // H/m (CODATA 2018)
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 
-// Tile of the 2.5-D sweeps: a block covers kTileX x kTileY columns of the
-// x-y plane and marches kTileZ planes along z, keeping the z neighbour in
-// registers.  kTileX is one 64-wide wavefront.
-#ifndef TFL_TILE_Y
-#define TFL_TILE_Y 4
-#endif
-#ifndef TFL_TILE_Z
-#define TFL_TILE_Z 32
-#endif
+// Tiles of the 2.5-D sweeps: a block covers kTileX x TY columns of the x-y
+// plane (one 64-wide wavefront per row) and marches TZ planes along z, keeping
+// the z neighbour in registers.  TY and TZ are chosen per sweep at launch.
 #ifndef TFL_MIN_WAVES
 #define TFL_MIN_WAVES 1
 #endif
 constexpr int kTileX = 64;
-constexpr int kTileY = TFL_TILE_Y;
-constexpr int kTileZ = TFL_TILE_Z;
 
 struct GridDims {
     int nx, ny, nz;
@@ -61,9 +53,7 @@ struct StepArgs {
     T hdt;                     // dt / mu0
     T dt;
     T theta;
-    T eps0dt;                  // unused slot kept for alignment
     PmlAxis<T> pml[3];
-    int ntiles_x, ntiles_y, ntiles_z;
 };
 
 struct SourceDesc {
@@ -124,6 +114,23 @@ struct AdjArgs {
     int ocomp, ob[6];
     double og;
 };
+
+// z length of the column tiles of a z-marching sweep, chosen at launch: the
+// longest of max_tz, ..., 16, 8 planes whose tiles still give at least
+// target_waves wavefronts (longer runs re-read fewer halo planes; enough waves
+// are needed to cover the HBM latency on small grids).
+inline int pick_tile_z(const GridDims &g, int ty, long long target_waves, int max_tz)
+{
+    const long long cols = (long long)((g.nx + kTileX - 1) / kTileX) * ((g.ny + ty - 1) / ty);
+    int tz = max_tz;
+    while (tz > 8 && cols * ((g.nz + tz - 1) / tz) * ty < target_waves) tz /= 2;
+    return tz;
+}
+
+inline int tile_blocks(const GridDims &g, int ty, int tz)
+{
+    return (int)(((g.nx + kTileX - 1) / kTileX) * ((g.ny + ty - 1) / ty) * ((g.nz + tz - 1) / tz));
+}
 
 // Host-side launchers (kernels_fwd.hip).
 template <typename T> hipError_t launch_h_pass(const StepArgs<T> &a, hipStream_t s);
