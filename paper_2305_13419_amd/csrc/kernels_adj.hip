@@ -214,6 +214,7 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
     const uint32_t od = cell * sizeof(double);
     const T rdx = A.f.rd[0], rdy = A.f.rd[1], rdz = A.f.rd[2];
     const T dt = A.f.dt, theta = A.f.theta, hdt = A.f.hdt;
+    const bool theta_one = (theta == T(1));
     const int km0 = (k0 == 0) ? nz - 1 : k0 - 1;
     T whyz_m = T(0), whxz_m = T(0);
     if (A.doC) {
@@ -282,7 +283,9 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
                 }
             }
             for (int q = 0; q < 3; ++q) {
-                En[q] = ldp(A.En[q] + b, o00);
+                // E^n enters the sigma gradient only through (1 - theta) E^n: with theta = 1 it is read
+                // on superconducting edges only (the ell gradient)
+                if (!theta_one || kq[q].cj > T(0)) En[q] = ldp(A.En[q] + b, o00);
                 Ep[q] = ldp(A.Ep[q] + b, o00);
                 gS[q] = ldp(A.gS[q] + b, od);
             }
