@@ -252,8 +252,9 @@ int tfl_adjoint(tfl_sim *sim, const tfl_objective *obj, int64_t nsteps, int64_t 
 /* ----------------------------------------------------------------------
  * Resonance frequency and quality factor from a ringdown (Sec. 5, Table 7)
  *
- * The paper extracts f and Q from probe time series with ESPRIT; this
- * library fits a linear predictor instead (Prony's method): the series
+ * The paper extracts f and Q from probe time series with ESPRIT, which
+ * tfl_esprit_fit below implements.  tfl_ringdown_fit is a second, independent
+ * estimator, a linear predictor (Prony's method): the series
  * x_m = series[start + m*decim], m = 0 .. count-1, is modelled as
  * x_m = sum_{k=1}^{P} a_k x_{m-k}; the GPU forms the FP64 normal equations
  * (Gram matrix of the lagged samples) and the host solves the P x P system
@@ -287,6 +288,27 @@ typedef struct {
  * `stream`.  TFL_E_INVAL on bad windows, TFL_E_NONFINITE if the normal
  * equations are singular or the root iteration does not converge. */
 int tfl_ringdown_fit(tfl_sim *sim, int probe_id, const tfl_fit_req *req, tfl_fit_result *out, void *stream);
+
+/* ESPRIT, the paper's own f / Q extraction (Sec. 5, Table 7; Roy and Kailath's
+ * estimation of signal parameters via rotational invariance, least-squares
+ * form).  The window x_m of req (start, count, decim) is taken as a sum of
+ * damped complex exponentials c_q z_q^m.  With the Hankel matrix H[r][a] =
+ * x_{r+a} of `pencil` columns, the GPU forms the FP64 Gram matrix H^T H; the
+ * host takes its eigenvectors of the req->order largest eigenvalues as the
+ * signal subspace V_s (pencil x P), solves V_s[1:] = V_s[:-1] Phi by least
+ * squares, and the eigenvalues of Phi (Hessenberg QR) are the modes
+ * z = exp((-alpha + i 2 pi f) decim dt).  Amplitudes and the reported mode
+ * (f_hint rule) as for tfl_ringdown_fit; a real damped cosine gives a
+ * conjugate pair, so P = 2 per mode.
+ *   req->order: P <= min(TFL_FIT_MAX_ORDER, pencil - 1); 0: the numerical rank
+ *               of H^T H (eigenvalues above 1e-8 of the largest), at least 2.
+ *   pencil:     3 .. TFL_ESPRIT_MAX_PENCIL, at most count / 2; 0: min(64, count / 3).
+ *   out->residual: fraction of the trace of H^T H outside the signal subspace.
+ * Synchronises `stream`.  TFL_E_INVAL on bad windows or sizes, TFL_E_NONFINITE
+ * if the Gram matrix is zero or an iteration does not converge. */
+#define TFL_ESPRIT_MAX_PENCIL 64
+int tfl_esprit_fit(tfl_sim *sim, int probe_id, const tfl_fit_req *req, int32_t pencil, tfl_fit_result *out,
+                   void *stream);
 
 /* Three-level variant for runs whose two-level schedule does not fit in
  * memory: after the same tfl_forward_checkpointed run (checkpoints every seg

@@ -204,6 +204,18 @@ class Simulation:
         modes = [(r.modes[2 * q], r.modes[2 * q + 1]) for q in range(r.nmodes)]
         return dict(f0=r.f0, alpha=r.alpha, Q=r.Q, residual=r.residual, order=r.order, modes=modes)
 
+    def esprit_fit(self, pid, start, count, decim=1, order=0, pencil=0, f_hint=0.0):
+        """ESPRIT fit of probe pid's series window (pencil 0: min(64, count // 3)); returns
+        dict(f0, alpha, Q, residual, order, pencil, modes=[(f, alpha), ...])."""
+        rq = L.tfl_fit_req()
+        rq.start, rq.count, rq.decim, rq.order, rq.f_hint = int(start), int(count), int(decim), int(order), f_hint
+        r = L.tfl_fit_result()
+        self._call("tfl_esprit_fit", ctypes.c_int(int(pid)), ctypes.byref(rq), ctypes.c_int32(int(pencil)),
+                   ctypes.byref(r), _stream())
+        modes = [(r.modes[2 * q], r.modes[2 * q + 1]) for q in range(r.nmodes)]
+        M = int(pencil) if pencil else min(64, int(count) // 3)
+        return dict(f0=r.f0, alpha=r.alpha, Q=r.Q, residual=r.residual, order=r.order, pencil=M, modes=modes)
+
     # -- adjoint ------------------------------------------------------------
     @staticmethod
     def _objective(comp, box, f0):

@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 from oracle import closed_forms as cf
+from oracle.esprit import esprit
 from oracle.ringdown import lp_fit
 from paper_2305_13419_amd import workloads
 from tests.helpers import MU0, compare, rel_l2, run_gpu, run_oracle
@@ -124,6 +125,16 @@ def test_cpw_workload_parity_and_ringdown():
         ref = lp_fit(series, start, count, decim, fit["order"], wl["dt"], f_hint=fh)
         print(f"  reference fit (NumPy): f0 {ref['f0'] / 1e12:.6f} THz, Q {ref['Q']:.4f}", flush=True)
         assert abs(fit["f0"] / ref["f0"] - 1) < 1e-6 and abs(fit["Q"] / ref["Q"] - 1) < 1e-4
+        # ESPRIT (the paper's extraction) on the same window matches its NumPy oracle at the order the
+        # library chose.  The window holds ~4 periods of a Q ~ 50 mode after the source dies, below
+        # ESPRIT's resolution for the neighbouring modes: f0 of the two methods agrees to a few %,
+        # their Q is reported (ESPRIT 25, linear prediction 47 in FP64)
+        esp = sim.esprit_fit(pids[1], start, count, decim, 0, 0, f_hint=fh)
+        eref = esprit(series, start, count, decim, esp["order"], wl["dt"], esp["pencil"], f_hint=fh)
+        print(f"  ESPRIT: f0 {esp['f0'] / 1e12:.6f} THz, Q {esp['Q']:.4f} (order {esp['order']}, pencil "
+              f"{esp['pencil']}); oracle f0 {eref['f0'] / 1e12:.6f} THz, Q {eref['Q']:.4f}", flush=True)
+        assert abs(esp["f0"] / eref["f0"] - 1) < 1e-6 and abs(esp["Q"] / eref["Q"] - 1) < 1e-3
+        assert abs(esp["f0"] / fit["f0"] - 1) < 5e-2 and esp["Q"] > 0
         out[dtype] = (series, fit, el)
         print(f"cpw {dtype}: {N} steps in {el:.2f} s ({16777216 * N / el / 1e9:.1f} Gcell/s incl. probes); "
               f"DFT peak {fh / 1e12:.4f} THz; fit f0 {fit['f0'] / 1e12:.4f} THz, Q {fit['Q']:.2f}, "
