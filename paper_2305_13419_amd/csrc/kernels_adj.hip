@@ -78,27 +78,39 @@ __global__ __launch_bounds__(kTileX *TY) void adj_face_kernel(const AdjArgs<T> A
     const long long sxy = A.f.g.sxy;
     const int ip = (i + 1 == nx) ? 0 : i + 1;
     const int jp = (j + 1 == ny) ? 0 : j + 1;
-    const long long r0 = (long long)j * nx, r1 = (long long)jp * nx;
+    const uint32_t o00 = uint32_t(j * nx + i) * sizeof(T), oxp = uint32_t(j * nx + ip) * sizeof(T);
+    const uint32_t oyp = uint32_t(jp * nx + i) * sizeof(T);
     const T rdx = A.f.rd[0], rdy = A.f.rd[1], rdz = A.f.rd[2];
     const T *mx = A.mu[0], *my = A.mu[1], *mz = A.mu[2];
+    // the z terms W(Ey, z) and W(Ex, z) of plane k are those of plane k+1 one iteration earlier
+    T wyz0, wxz0;
+    {
+        const long long b = (long long)k0 * sxy;
+        wyz0 = w_edge(A, 1, 2, i, j, k0, ldp(my + b, o00));
+        wxz0 = w_edge(A, 0, 2, i, j, k0, ldp(mx + b, o00));
+    }
     for (int k = k0; k < k1; ++k) {
         const int kp = (k + 1 == nz) ? 0 : k + 1;
-        const long long b0 = (long long)k * sxy, b1 = (long long)kp * sxy;
-        const long long c = b0 + r0 + i;
-        const T mx0 = mx[c], my0 = my[c], mz0 = mz[c];
+        const long long b = opaque_offset((long long)k * sxy), bp = opaque_offset((long long)kp * sxy);
+        const T mx0 = ldp(mx + b, o00), my0 = ldp(my + b, o00), mz0 = ldp(mz + b, o00);
+        const T my_kp = ldp(my + bp, o00), mx_kp = ldp(mx + bp, o00);
+        const T mz_yp = ldp(mz + b, oyp), mz_xp = ldp(mz + b, oxp), mx_yp = ldp(mx + b, oyp), my_xp = ldp(my + b, oxp);
+        const T lh0 = ldp(A.lH[0] + b, o00), lh1 = ldp(A.lH[1] + b, o00), lh2 = ldp(A.lH[2] + b, o00);
         // lHx: terms (Ey, z) and (Ez, y)
-        const T wyz0 = w_edge(A, 1, 2, i, j, k, my0), wyz1 = w_edge(A, 1, 2, i, j, kp, my[b1 + r0 + i]);
-        const T wzy0 = w_edge(A, 2, 1, i, j, k, mz0), wzy1 = w_edge(A, 2, 1, i, jp, k, mz[b0 + r1 + i]);
+        const T wyz1 = w_edge(A, 1, 2, i, j, kp, my_kp);
+        const T wzy0 = w_edge(A, 2, 1, i, j, k, mz0), wzy1 = w_edge(A, 2, 1, i, jp, k, mz_yp);
         // lHy: terms (Ex, z) and (Ez, x)
-        const T wxz0 = w_edge(A, 0, 2, i, j, k, mx0), wxz1 = w_edge(A, 0, 2, i, j, kp, mx[b1 + r0 + i]);
-        const T wzx0 = w_edge(A, 2, 0, i, j, k, mz0), wzx1 = w_edge(A, 2, 0, ip, j, k, mz[b0 + r0 + ip]);
+        const T wxz1 = w_edge(A, 0, 2, i, j, kp, mx_kp);
+        const T wzx0 = w_edge(A, 2, 0, i, j, k, mz0), wzx1 = w_edge(A, 2, 0, ip, j, k, mz_xp);
         // lHz: terms (Ex, y) and (Ey, x)
-        const T wxy0 = w_edge(A, 0, 1, i, j, k, mx0), wxy1 = w_edge(A, 0, 1, i, jp, k, mx[b0 + r1 + i]);
-        const T wyx0 = w_edge(A, 1, 0, i, j, k, my0), wyx1 = w_edge(A, 1, 0, ip, j, k, my[b0 + r0 + ip]);
-        const T lh[3] = {A.lH[0][c] + (wyz0 - wyz1) * rdz + (wzy0 - wzy1) * rdy,
-                         A.lH[1][c] + (wxz0 - wxz1) * rdz + (wzx0 - wzx1) * rdx,
-                         A.lH[2][c] + (wxy0 - wxy1) * rdy + (wyx0 - wyx1) * rdx};
-        for (int h = 0; h < 3; ++h) A.lH[h][c] = lh[h];
+        const T wxy0 = w_edge(A, 0, 1, i, j, k, mx0), wxy1 = w_edge(A, 0, 1, i, jp, k, mx_yp);
+        const T wyx0 = w_edge(A, 1, 0, i, j, k, my0), wyx1 = w_edge(A, 1, 0, ip, j, k, my_xp);
+        const T lh[3] = {lh0 + (wyz0 - wyz1) * rdz + (wzy0 - wzy1) * rdy,
+                         lh1 + (wxz0 - wxz1) * rdz + (wzx0 - wzx1) * rdx,
+                         lh2 + (wxy0 - wxy1) * rdy + (wyx0 - wyx1) * rdx};
+        for (int h = 0; h < 3; ++h) stp(A.lH[h] + b, o00, lh[h]);
+        wyz0 = wyz1;
+        wxz0 = wxz1;
         // H-side PML adjoint variables: tot = bh * stored + (-dt/mu0) sg lH''
         const int pos[3] = {i, j, k};
         for (int a = 0; a < 3; ++a) {

@@ -2,8 +2,9 @@
 
 Tolerances: relative L2 <= 1e-12 per field group for the FP64 path, <= 1e-5
 for the FP32 path (both started from the same FP32-rounded inputs), after the
-stated number of steps.  Grids are chosen to span several 64 x 4 x 32 tiles
-with ragged tails, degenerate axes and every boundary combination.
+stated number of steps.  Grids are chosen to span several column tiles (64
+wide, 4-8 rows, 8-64 planes: the sweeps pick the z length at launch from the
+grid size) with ragged tails, degenerate axes and every boundary combination.
 """
 import numpy as np
 import pytest
@@ -54,6 +55,14 @@ def test_cpml_sources_probes(pml, dtype):
                     dict(comp=0, box=(20, 21, 10, 11, 15, 16), freqs=(2e14,)),
                     dict(comp=2, box=(0, 66, 0, 21, 0, 40))]
     check(wl, 30, dtype)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_mid_size_grid(dtype):
+    """8.4 M cells: the launch rule picks 16-plane tiles for the FP32 sweeps and the FP64 E pass
+    and 32-plane tiles for the FP64 H pass, which the small grids (8 planes) do not reach."""
+    wl = workloads.random_medium((256, 128, 256), seed=23, pml=((4, 4), None, (6, 6)))
+    check(wl, 3, dtype)
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 96), (80, 1, 1), (1, 70, 1), (1, 1, 1), (3, 5, 2), (130, 9, 1)])
