@@ -2,8 +2,9 @@
 
 Workload: the 256^3 roofline grid (dx = 20 nm, periodic, random
 superconducting boxes on ~30 % of the cells, E and H ~ N(0, 1)), stepped in
-FP64 and in FP32.  A step is one full time step of Algorithm 1 (the H pass
-and the E + Js pass).  Also timed: the adjoint gradient on the half-size CPW
+FP64 and in FP32.  A step is one full time step of Algorithm 1: on this
+all-periodic grid one fused sweep (the product path), and for comparison the
+two passes (H pass, E + Js pass) that grids with CPML use.  Also timed: the adjoint gradient on the half-size CPW
 workload (256 x 128 x 64 cells, 4096 steps, 64-step checkpoint segments)
 against its checkpointed forward run.  Prints one JSON line.
 
@@ -44,20 +45,21 @@ def sc_edge_fraction(ell):
     return float(np.mean(fr))
 
 
-def run_gpu(wl, dtype, steps, warmup):
+def run_gpu(wl, dtype, steps, warmup, fused=True):
     import numpy as np
     import torch
 
     from paper_2305_13419_amd import Simulation
 
     npdt = np.float64 if dtype == torch.float64 else np.float32
-    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"])
+    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"], fused=fused)
     sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
     E, H, _ = wl["fields"]
     sim.set_fields([np.asarray(a, dtype=npdt) for a in E], [np.asarray(a, dtype=npdt) for a in H])
     sim.step(warmup)
     torch.cuda.synchronize()
-    # timed region: K steps, HIP events around every pass on the launch stream
+    # timed region: K steps, HIP events around every kernel on the launch stream (fused sweep: the
+    # first interval is the fused kernel, the second only the gap to the next step)
     t0 = time.perf_counter()
     h_ms, e_ms = sim.profile_step(steps)
     torch.cuda.synchronize()
@@ -68,18 +70,18 @@ def run_gpu(wl, dtype, steps, warmup):
                 nonfinite=int(bad), energy=W)
 
 
-def measured_traffic(dtype_name):
-    """HBM bytes per E-pass launch from the committed rocprofv3 counter summary, or None when the
+def measured_traffic(dtype_name, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when the
     kernel source changed after the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "e_pass_kernel_roofline_256cube.md")
+    path = os.path.join(ROOT, "profiles", "forward_kernels_roofline_256cube.md")
     src = os.path.join(ROOT, "paper_2305_13419_amd", "csrc", "kernels_fwd.hip")
     if not os.path.exists(path):
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     for line in open(path):
-        m = re.match(r"TRAFFIC (\w+) e_pass_kernel bytes_per_launch=(\S+) kernels_fwd_sha=(\w+)", line.strip())
-        if m and m.group(1) == dtype_name and m.group(3) == sha:
-            return float(m.group(2))
+        m = re.match(r"TRAFFIC (\w+) (\w+) bytes_per_launch=(\S+) kernels_fwd_sha=(\w+)", line.strip())
+        if m and m.group(1) == dtype_name and m.group(2) == kernel:
+            return float(m.group(3)) if m.group(4) == sha else None
     return None
 
 
@@ -249,25 +251,34 @@ def main():
     fJ = sc_edge_fraction(wl["maps"][2])
     res = {}
     for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
-        print(f"# {name}: {args.warmup} warm-up + {args.steps} timed steps on {wl['name']}", file=sys.stderr,
-              flush=True)
-        res[name] = run_gpu(wl, dt, args.steps, args.warmup)
+        for fused in (True, False):
+            print(f"# {name} {'fused sweep' if fused else 'two passes'}: {args.warmup} warm-up + {args.steps} "
+                  f"timed steps on {wl['name']}", file=sys.stderr, flush=True)
+            res[name, fused] = run_gpu(wl, dt, args.steps, args.warmup, fused)
     out = {}
     for name, w in (("f64", 8), ("f32", 4)):
-        r = res[name]
-        gcell = ncell / (r["step_ms"] * 1e-3) / 1e9
+        # the product path on this all-periodic grid: one fused sweep per step
+        r = res[name, True]
+        f_bytes = w * (15 + 6 * fJ) * ncell      # E, H, maps read; E, H written; Js r/w on SC edges
+        f_gbs = f_bytes / (r["h_ms"] * 1e-3) / 1e9
+        # the two passes (the path of grids with CPML)
+        t = res[name, False]
         e_bytes = w * (12 + 6 * fJ) * ncell      # E pass: H, E, maps read; E written; Js r/w on SC edges
         h_bytes = w * 9 * ncell                   # H pass: E, H read; H written
-        step_bytes = e_bytes + h_bytes
-        e_gbs = e_bytes / (r["e_ms"] * 1e-3) / 1e9
+        e_gbs = e_bytes / (t["e_ms"] * 1e-3) / 1e9
         out[name] = dict(
-            value=gcell, ms_per_step=r["step_ms"], h_pass_ms=r["h_ms"], e_pass_ms=r["e_ms"],
-            step_GBs=step_bytes / (r["step_ms"] * 1e-3) / 1e9,
-            h_pass_GBs=h_bytes / (r["h_ms"] * 1e-3) / 1e9, e_pass_GBs=e_gbs,
-            nonfinite=r["nonfinite"],
-            roofline=dict(bound="hbm", kernel="e_pass_kernel", achieved=e_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                          frac=e_gbs / HBM_PEAK_GBS, traffic=measured_traffic(name),
-                          bytes_per_cell=w * (12 + 6 * fJ), algorithmic_bytes_per_launch=e_bytes),
+            value=ncell / (r["step_ms"] * 1e-3) / 1e9, ms_per_step=r["step_ms"], fused_step_ms=r["h_ms"],
+            fused_step_GBs=f_gbs, nonfinite=r["nonfinite"],
+            roofline=dict(bound="hbm", kernel="fused_step_kernel", achieved=f_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=f_gbs / HBM_PEAK_GBS, traffic=measured_traffic(name, "fused_step_kernel"),
+                          bytes_per_cell=w * (15 + 6 * fJ), algorithmic_bytes_per_launch=f_bytes),
+            two_pass=dict(
+                value=ncell / (t["step_ms"] * 1e-3) / 1e9, ms_per_step=t["step_ms"], h_pass_ms=t["h_ms"],
+                e_pass_ms=t["e_ms"], h_pass_GBs=h_bytes / (t["h_ms"] * 1e-3) / 1e9, e_pass_GBs=e_gbs,
+                nonfinite=t["nonfinite"],
+                roofline=dict(bound="hbm", kernel="e_pass_kernel", achieved=e_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=e_gbs / HBM_PEAK_GBS, traffic=measured_traffic(name, "e_pass_kernel"),
+                              bytes_per_cell=w * (12 + 6 * fJ), algorithmic_bytes_per_launch=e_bytes)),
         )
     f64 = out["f64"]
     line = {

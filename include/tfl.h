@@ -146,6 +146,22 @@ int tfl_bind_state(tfl_sim *sim, void *const E[3], void *const H[3], void *const
  * workspace may be NULL when its size is 0. */
 int tfl_bind_workspace(tfl_sim *sim, void *workspace, void *scratch, void *stream);
 
+/* Optional second set of E and H fields for the fused sweep (grids with
+ * periodic boundaries on every axis).  tfl_fused_buffer_bytes reports its size
+ * (6 fields, each padded to 256 bytes; 0 when the grid has a CPML axis).
+ * With a buffer bound, tfl_step runs H and E updates of a step in one sweep
+ * (Algorithm 1, steps 1-5 of a time step fused): it reads E^n, H^{n-1/2} from
+ * one set and writes E^{n+1}, H^{n+1/2} to the other, recomputing the few H
+ * values a cell needs from its x-1 and y-1 neighbours, so each cell's fields
+ * cross HBM once per step instead of twice; results equal those of the two
+ * passes.  Steps run in pairs (bound fields -> buffer -> bound fields), an odd
+ * last step with the two passes, so the state is in the bound fields after
+ * every call.  The buffer is caller-owned device memory, 256-byte aligned,
+ * holding nothing between calls; bind NULL to go back to the two passes.
+ * TFL_E_INVAL on a grid with a CPML axis or a misaligned buffer. */
+int tfl_fused_buffer_bytes(const tfl_sim *sim, size_t *bytes);
+int tfl_bind_fused_buffer(tfl_sim *sim, void *buffer);
+
 /* Bind the per-cell maps (device, dtype, N elements each).  Validates them
  * on the device (eps_r > 0, sigma >= 0, inv_lambda2 >= 0, all finite) and
  * checks dt against the stability bound of the scheme with the London term,

@@ -16,6 +16,9 @@ HIPCC_FLAGS = [
     "-shared",
     "-Wall",
     "-Wno-unused-function",
+    # no contraction into fused multiply-adds: every sweep rounds the same expressions the same way,
+    # so the fused step and the two passes give identical bits
+    "-ffp-contract=off",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

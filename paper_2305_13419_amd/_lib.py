@@ -123,6 +123,8 @@ SIGNATURES = {
     "tfl_adjoint": [P, ctypes.POINTER(tfl_objective), ctypes.c_int64, ctypes.c_int64, P,
                     ctypes.POINTER(ctypes.c_double), P, P, P, P, P],
     "tfl_ringdown_fit": [P, ctypes.c_int, ctypes.POINTER(tfl_fit_req), ctypes.POINTER(tfl_fit_result), P],
+    "tfl_fused_buffer_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
+    "tfl_bind_fused_buffer": [P, P],
     "tfl_esprit_fit": [P, ctypes.c_int, ctypes.POINTER(tfl_fit_req), ctypes.c_int32, ctypes.POINTER(tfl_fit_result),
                        P],
     "tfl_adjoint_nested_sizes": [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t),

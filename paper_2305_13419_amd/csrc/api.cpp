@@ -112,6 +112,7 @@ StepArgs<T> make_args(const tfl_sim *s)
         a.E[q] = (T *)s->E[q];
         a.Eout[q] = (T *)s->E[q];
         a.H[q] = (T *)s->H[q];
+        a.Hout[q] = (T *)s->H[q];
         a.J[q] = (T *)s->J[q];
     }
     a.eps = (const T *)s->eps;
@@ -169,11 +170,36 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
         if ((e = launch_probes<T>(pa, np, st)) != hipSuccess) return hip_fail(s, e, "probe");
         s->sampled0 = true;
     }
+    // With a fused buffer bound, steps go A -> B -> A in pairs through the fused sweep (A the bound
+    // fields, B the buffer), so the state is back in A after every call; an odd last step runs the
+    // two passes in place on A.
+    StepArgs<T> ab = a, ba = a;
+    if (s->fused) {
+        const size_t fb = round256((size_t)s->N * s->esz);
+        for (int q = 0; q < 3; ++q) {
+            T *eb = (T *)((char *)s->fused + q * fb), *hb = (T *)((char *)s->fused + (3 + q) * fb);
+            ab.Eout[q] = eb;
+            ab.Hout[q] = hb;
+            ba.E[q] = eb;
+            ba.H[q] = hb;
+        }
+    }
+    bool inB = false;
     for (int64_t it = 0; it < nsteps; ++it) {
         if (ev && (e = hipEventRecord(ev[2 * it], st)) != hipSuccess) return hip_fail(s, e, "event");
-        if ((e = launch_h_pass<T>(a, st)) != hipSuccess) return hip_fail(s, e, "h_pass");
-        if (ev && (e = hipEventRecord(ev[2 * it + 1], st)) != hipSuccess) return hip_fail(s, e, "event");
-        if ((e = launch_e_pass<T>(a, st)) != hipSuccess) return hip_fail(s, e, "e_pass");
+        if (s->fused && (inB || it + 1 < nsteps)) {
+            if ((e = launch_fused_step<T>(inB ? ba : ab, st)) != hipSuccess) return hip_fail(s, e, "fused step");
+            if (ev && (e = hipEventRecord(ev[2 * it + 1], st)) != hipSuccess) return hip_fail(s, e, "event");
+            inB = !inB;
+        } else {
+            if ((e = launch_h_pass<T>(a, st)) != hipSuccess) return hip_fail(s, e, "h_pass");
+            if (ev && (e = hipEventRecord(ev[2 * it + 1], st)) != hipSuccess) return hip_fail(s, e, "event");
+            if ((e = launch_e_pass<T>(a, st)) != hipSuccess) return hip_fail(s, e, "e_pass");
+        }
+        for (int q = 0; q < 3; ++q) {
+            sa.E[q] = inB ? ab.Eout[q] : a.E[q];
+            pa.E[q] = sa.E[q];
+        }
         if (sa.nsrc > 0) {
             sa.t = (double)(s->step + 1) * s->cfg.dt;
             if ((e = launch_sources<T>(sa, st)) != hipSuccess) return hip_fail(s, e, "source");
@@ -186,6 +212,13 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
     }
     if (ev && nsteps > 0 && (e = hipEventRecord(ev[2 * nsteps], st)) != hipSuccess) return hip_fail(s, e, "event");
     return TFL_OK;
+}
+
+bool fused_eligible(const tfl_sim *s)
+{
+    for (int a = 0; a < 3; ++a)
+        if (s->cfg.bc[a] != TFL_PERIODIC) return false;
+    return true;
 }
 
 int upload_probes(tfl_sim *s, hipStream_t st)
@@ -374,6 +407,23 @@ int tfl_bind_workspace(tfl_sim *s, void *workspace, void *scratch, void *stream)
     rc = clear_psi(s, st);
     if (rc != TFL_OK) return rc;
     s->work_bound = true;
+    return TFL_OK;
+}
+
+
+int tfl_fused_buffer_bytes(const tfl_sim *s, size_t *bytes)
+{
+    if (!s || !bytes) return fail(nullptr, TFL_E_INVAL, "null argument");
+    *bytes = fused_eligible(s) ? 6 * round256((size_t)s->N * s->esz) : 0;
+    return TFL_OK;
+}
+
+int tfl_bind_fused_buffer(tfl_sim *s, void *buf)
+{
+    if (!s) return fail(nullptr, TFL_E_INVAL, "null handle");
+    if (buf && !fused_eligible(s)) return fail(s, TFL_E_INVAL, "the fused sweep needs periodic boundaries on every axis");
+    if (buf && !aligned(buf)) return fail(s, TFL_E_INVAL, "fused buffer must be 256-byte aligned");
+    s->fused = buf;
     return TFL_OK;
 }
 

@@ -235,6 +235,147 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const
 }
 
 // ---------------------------------------------------------------------------
+// Fused step (H and E pass in one sweep, grids without CPML)
+// ---------------------------------------------------------------------------
+// Each lane updates E at its own edges and H at its own faces.  The E update
+// needs H^{n+1/2} also at the faces x-1 (Hz, Hy) and y-1 (Hz, Hx) of its cell,
+// which belong to other lanes or blocks: the lane recomputes them from E^n and
+// H^{n-1/2}, which the sweep only reads (the new fields go to the other pair of
+// buffers), with the same arithmetic as the H pass.  H^{n+1/2} at z-1 is the
+// lane's own value from the previous plane.  Per cell the sweep reads E, H, the
+// maps and Js and writes E, H and Js once: 15 + 6 f_J words instead of the
+// 21 + 6 f_J of the two passes.
+template <typename T, int TY, int TZ>
+__global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void fused_step_kernel(const StepArgs<T> a)
+{
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    int i, j, k0, k1;
+    if (!tile_of<TY, TZ>(nx, ny, nz, i, j, k0, k1)) return;
+    const long long sxy = a.g.sxy;
+    const int im = (i == 0) ? nx - 1 : i - 1, ip = (i + 1 == nx) ? 0 : i + 1;
+    const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j + 1 == ny) ? 0 : j + 1;
+    constexpr uint32_t w = sizeof(T);
+    const uint32_t o00 = uint32_t(j * nx + i) * w, o10 = uint32_t(j * nx + im) * w;
+    const uint32_t o01 = uint32_t(jm * nx + i) * w, o11 = uint32_t(jm * nx + im) * w;
+    const uint32_t oxp = uint32_t(j * nx + ip) * w, oyp = uint32_t(jp * nx + i) * w;
+    const uint32_t oxm_yp = uint32_t(jp * nx + im) * w, oxp_ym = uint32_t(jm * nx + ip) * w;
+    const T rdx = a.rd[0], rdy = a.rd[1], rdz = a.rd[2];
+    const T dt = a.dt, theta = a.theta, hdt = a.hdt;
+
+    T pe00, pe10, pe01, ps00, ps10, ps01, pl00, pl10, pl01;
+    EdgeCoef<T> cx, cy, cz;
+    struct Maps {
+        T e00, e10, e01, e11, s00, s10, s01, s11, l00, l10, l01, l11;
+    };
+    auto load_maps = [&](int kk) {
+        const long long b = opaque_offset((long long)kk * sxy);
+        const T *me = a.eps + b, *ms = a.sig + b, *ml = a.ell + b;
+        return Maps{ldp(me, o00), ldp(me, o10), ldp(me, o01), ldp(me, o11),
+                    ldp(ms, o00), ldp(ms, o10), ldp(ms, o01), ldp(ms, o11),
+                    ldp(ml, o00), ldp(ml, o10), ldp(ml, o01), ldp(ml, o11)};
+    };
+    auto coefs = [&](const Maps &m) {
+        {   // Ex: cells (j,k), (j,k-1), (j-1,k), (j-1,k-1)
+            const T e[4] = {m.e00, pe00, m.e01, pe01}, s[4] = {m.s00, ps00, m.s01, ps01},
+                    l[4] = {m.l00, pl00, m.l01, pl01};
+            cx = edge_coef(e, s, l, dt, theta, hdt);
+        }
+        {   // Ey: cells (k,i), (k,i-1), (k-1,i), (k-1,i-1)
+            const T e[4] = {m.e00, m.e10, pe00, pe10}, s[4] = {m.s00, m.s10, ps00, ps10},
+                    l[4] = {m.l00, m.l10, pl00, pl10};
+            cy = edge_coef(e, s, l, dt, theta, hdt);
+        }
+        {   // Ez: cells (i,j), (i,j-1), (i-1,j), (i-1,j-1)
+            const T e[4] = {m.e00, m.e01, m.e10, m.e11}, s[4] = {m.s00, m.s01, m.s10, m.s11},
+                    l[4] = {m.l00, m.l01, m.l10, m.l11};
+            cz = edge_coef(e, s, l, dt, theta, hdt);
+        }
+        pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
+        ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
+        pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
+    };
+    // H^{n+1/2} (Hx, Hy) at plane k0-1 of the lane's own faces, and E^n of plane k0 that the
+    // loop carries from one plane to the next: Ex at (i,j), (i-1,j); Ey at (i,j), (i,j-1)
+    const int km0 = (k0 == 0) ? nz - 1 : k0 - 1;
+    T hx_km, hy_km, ex0, exm, ey0, eym;
+    {
+        const long long bm = (long long)km0 * sxy, b = (long long)k0 * sxy;
+        const T *Ex = a.E[0] + bm, *Ey = a.E[1] + bm, *Ez = a.E[2] + bm;
+        const T exk = ldp(Ex, o00), eyk = ldp(Ey, o00), ez = ldp(Ez, o00);
+        const T exk1 = ldp(a.E[0] + b, o00), eyk1 = ldp(a.E[1] + b, o00);
+        const T ez_x = ldp(Ez, oxp), ez_y = ldp(Ez, oyp);
+        const T dyEz = (ez_y - ez) * rdy, dzEy = (eyk1 - eyk) * rdz;
+        const T dzEx = (exk1 - exk) * rdz, dxEz = (ez_x - ez) * rdx;
+        hx_km = ldp(a.H[0] + bm, o00) - hdt * (dyEz - dzEy);
+        hy_km = ldp(a.H[1] + bm, o00) - hdt * (dzEx - dxEz);
+        const Maps m = load_maps(km0);
+        pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
+        ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
+        pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
+        ex0 = exk1;
+        ey0 = eyk1;
+        exm = ldp(a.E[0] + b, o10);
+        eym = ldp(a.E[1] + b, o01);
+    }
+    coefs(load_maps(k0));
+
+    for (int k = k0; k < k1; ++k) {
+        const int kp = (k + 1 == nz) ? 0 : k + 1;
+        const long long b = opaque_offset((long long)k * sxy), bp = opaque_offset((long long)kp * sxy);
+        T *Jx = a.J[0] + b, *Jy = a.J[1] + b, *Jz = a.J[2] + b;
+        const EdgeCoef<T> qx = cx, qy = cy, qz = cz;
+        T jx = T(0), jy = T(0), jz = T(0);
+        if (qx.cj > T(0)) jx = ldp(Jx, o00);
+        if (qy.cj > T(0)) jy = ldp(Jy, o00);
+        if (qz.cj > T(0)) jz = ldp(Jz, o00);
+        const T *Ex = a.E[0] + b, *Ey = a.E[1] + b, *Ez = a.E[2] + b;
+        const T *Hx = a.H[0] + b, *Hy = a.H[1] + b, *Hz = a.H[2] + b;
+        // E^n of this plane and the next
+        const T ex_yp = ldp(Ex, oyp), exm_yp = ldp(Ex, oxm_yp), ex_ym = ldp(Ex, o01);
+        const T ey_xp = ldp(Ey, oxp), ey_xm = ldp(Ey, o10), eym_xp = ldp(Ey, oxp_ym);
+        const T ez = ldp(Ez, o00), ez_xp = ldp(Ez, oxp), ez_yp = ldp(Ez, oyp), ez_xm = ldp(Ez, o10), ez_ym = ldp(Ez, o01);
+        const T ex1 = ldp(a.E[0] + bp, o00), exm1 = ldp(a.E[0] + bp, o10);
+        const T ey1 = ldp(a.E[1] + bp, o00), eym1 = ldp(a.E[1] + bp, o01);
+        // H^{n-1/2}: own faces, Hz and Hy at x-1, Hz and Hx at y-1
+        const T hx = ldp(Hx, o00), hy = ldp(Hy, o00), hz = ldp(Hz, o00);
+        const T hz_xm = ldp(Hz, o10), hy_xm = ldp(Hy, o10), hz_ym = ldp(Hz, o01), hx_ym = ldp(Hx, o01);
+        const Maps mn = load_maps(k + 1 < nz ? k + 1 : k);
+
+        // H^{n+1/2} with the H pass's arithmetic
+        const T nhx = hx - hdt * ((ez_yp - ez) * rdy - (ey1 - ey0) * rdz);
+        const T nhy = hy - hdt * ((ex1 - ex0) * rdz - (ez_xp - ez) * rdx);
+        const T nhz = hz - hdt * ((ey_xp - ey0) * rdx - (ex_yp - ex0) * rdy);
+        const T nhz_xm = hz_xm - hdt * ((ey0 - ey_xm) * rdx - (exm_yp - exm) * rdy);
+        const T nhy_xm = hy_xm - hdt * ((exm1 - exm) * rdz - (ez - ez_xm) * rdx);
+        const T nhz_ym = hz_ym - hdt * ((eym_xp - eym) * rdx - (ex0 - ex_ym) * rdy);
+        const T nhx_ym = hx_ym - hdt * ((ez - ez_ym) * rdy - (eym1 - eym) * rdz);
+        T *Hxo = a.Hout[0] + b, *Hyo = a.Hout[1] + b, *Hzo = a.Hout[2] + b;
+        stp(Hxo, o00, nhx);
+        stp(Hyo, o00, nhy);
+        stp(Hzo, o00, nhz);
+
+        // E^{n+1} with the E pass's arithmetic
+        const T dyHz = (nhz - nhz_ym) * rdy, dzHy = (nhy - hy_km) * rdz;  // Ex
+        const T dzHx = (nhx - hx_km) * rdz, dxHz = (nhz - nhz_xm) * rdx;  // Ey
+        const T dxHy = (nhy - nhy_xm) * rdx, dyHx = (nhx - nhx_ym) * rdy;  // Ez
+        if (qx.cj > T(0)) { jx = jx + qx.cj * ex0; stp(Jx, o00, jx); }
+        if (qy.cj > T(0)) { jy = jy + qy.cj * ey0; stp(Jy, o00, jy); }
+        if (qz.cj > T(0)) { jz = jz + qz.cj * ez; stp(Jz, o00, jz); }
+        T *Exo = a.Eout[0] + b, *Eyo = a.Eout[1] + b, *Ezo = a.Eout[2] + b;
+        stp(Exo, o00, qx.ca * ex0 + qx.cb * ((dyHz - dzHy) - jx));
+        stp(Eyo, o00, qy.ca * ey0 + qy.cb * ((dzHx - dxHz) - jy));
+        stp(Ezo, o00, qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz));
+        hx_km = nhx;
+        hy_km = nhy;
+        ex0 = ex1;
+        exm = exm1;
+        ey0 = ey1;
+        eym = eym1;
+        coefs(mn);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Soft sources and probes
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double waveform(int wave, double f, double t0, double tw, double t)
@@ -553,22 +694,22 @@ __global__ void fill_zero_kernel(uint32_t *p, size_t nwords)
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-// Tile shapes of the two forward sweeps per storage type: rows of 64-wide
+// Tile shapes of the forward sweeps per storage type: rows of 64-wide
 // wavefronts per block, the longest z run, and the wavefronts a launch should
-// at least provide (from a sweep of shapes on MI355X: the FP64 H pass is
+// at least provide (from sweeps of shapes on MI355X: the FP64 H pass is
 // fastest with all its tiles resident in one round, the other sweeps with
-// about two rounds of waves).
+// about two rounds of waves; the fused sweep varies by < 3 % over shapes).
 template <typename T>
 struct FwdTiles;
 template <>
 struct FwdTiles<double> {
-    static constexpr int hy = 4, hz_max = 64, ey = 8, ez_max = 64;
-    static constexpr long long h_waves = 4096, e_waves = 8192;
+    static constexpr int hy = 4, hz_max = 64, ey = 8, ez_max = 64, fy = 4, fz_max = 64;
+    static constexpr long long h_waves = 4096, e_waves = 8192, f_waves = 8192;
 };
 template <>
 struct FwdTiles<float> {
-    static constexpr int hy = 4, hz_max = 64, ey = 4, ez_max = 64;
-    static constexpr long long h_waves = 8192, e_waves = 8192;
+    static constexpr int hy = 4, hz_max = 64, ey = 4, ez_max = 64, fy = 4, fz_max = 64;
+    static constexpr long long h_waves = 8192, e_waves = 8192, f_waves = 16384;
 };
 
 // Launch kernel template K<T, TY, TZ> with TZ in {8, 16, 32, 64} chosen at run time.
@@ -599,6 +740,15 @@ hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t s)
     using C = FwdTiles<T>;
     const int tz = pick_tile_z(a.g, C::ey, C::e_waves, C::ez_max);
     TFL_LAUNCH_TZ(e_pass_kernel, T, C::ey, tz, a, s);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s)
+{
+    using C = FwdTiles<T>;
+    const int tz = pick_tile_z(a.g, C::fy, C::f_waves, C::fz_max);
+    TFL_LAUNCH_TZ(fused_step_kernel, T, C::fy, tz, a, s);
     return hipGetLastError();
 }
 
@@ -670,6 +820,7 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
 #define TFL_INSTANTIATE(T)                                                                                  \
     template hipError_t launch_h_pass<T>(const StepArgs<T> &, hipStream_t);                                 \
     template hipError_t launch_e_pass<T>(const StepArgs<T> &, hipStream_t);                                 \
+    template hipError_t launch_fused_step<T>(const StepArgs<T> &, hipStream_t);                             \
     template hipError_t launch_sources<T>(const SrcArgs<T> &, hipStream_t);                                 \
     template hipError_t launch_probes<T>(const ProbeArgs<T> &, int, hipStream_t);                           \
     template hipError_t launch_half_kick<T>(const StepArgs<T> &, T, T *const[3], T *const[3], hipStream_t); \

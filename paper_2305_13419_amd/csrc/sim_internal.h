@@ -19,6 +19,7 @@ struct tfl_sim {
     const void *eps = nullptr, *sig = nullptr, *ell = nullptr;
     void *work = nullptr;
     double *scratch = nullptr;
+    void *fused = nullptr;  // second E, H set of the fused sweep (caller-owned), or null
     bool state_bound = false, work_bound = false, maps_bound = false;
     size_t work_bytes = 0;
     // workspace layout (element offsets in units of the field type)
@@ -53,6 +54,8 @@ template <typename T> StepArgs<T> make_args(const tfl_sim *s);
 template <typename T> int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev = nullptr,
                                   bool probes = true);
 int copy_state(tfl_sim *s, void *dst, const void *src, bool save, hipStream_t st);
+// The fused sweep needs periodic boundaries on every axis.
+bool fused_eligible(const tfl_sim *s);
 
 // scratch buffer layout: reduction partials, the objective DFT, probe descriptors
 constexpr size_t kScratchBytes = 1 << 17;

@@ -47,6 +47,7 @@ struct StepArgs {
     T *E[3];
     T *Eout[3];  // where the E pass writes E^{n+1} (E itself except in recomputation)
     T *H[3];
+    T *Hout[3];  // where the fused sweep writes H^{n+1/2} (the two-pass H pass updates H in place)
     T *J[3];
     const T *eps, *sig, *ell;  // per-cell maps
     T rd[3];                   // 1/dx, 1/dy, 1/dz
@@ -135,6 +136,9 @@ inline int tile_blocks(const GridDims &g, int ty, int tz)
 // Host-side launchers (kernels_fwd.hip).
 template <typename T> hipError_t launch_h_pass(const StepArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t s);
+// One whole step in one sweep on grids without CPML: reads E^n (E) and H^{n-1/2} (H), writes
+// E^{n+1} (Eout) and H^{n+1/2} (Hout); Js in place.  E, Eout and H, Hout must not overlap.
+template <typename T> hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_sources(const SrcArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_probes(const ProbeArgs<T> &a, int nprobe, hipStream_t s);
 // Integer-time half kick: Hout = Hin + sgn dt/(2 mu0) curlE (stretched, with

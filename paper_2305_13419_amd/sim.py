@@ -33,7 +33,7 @@ class Simulation:
     """
 
     def __init__(self, shape, spacing, dt, theta=1.0, dtype=torch.float64, pml=(None, None, None),
-                 pml_order=3.0, pml_scale=1.0, kappa_max=1.0, alpha_max=0.0, device="cuda"):
+                 pml_order=3.0, pml_scale=1.0, kappa_max=1.0, alpha_max=0.0, device="cuda", fused=True):
         if dtype not in _DT:
             raise ValueError("dtype must be torch.float64 or torch.float32")
         self.nx, self.ny, self.nz = (int(v) for v in shape)
@@ -74,6 +74,13 @@ class Simulation:
         self._call("tfl_bind_state", e3, h3, j3)
         self._call("tfl_bind_workspace", ctypes.c_void_p(self.workspace.data_ptr() if ws.value else 0),
                    ctypes.c_void_p(self.scratch.data_ptr()), _stream())
+        # second E, H set for the one-sweep step on all-periodic grids (fused=False keeps two passes)
+        fb = ctypes.c_size_t()
+        self._call("tfl_fused_buffer_bytes", ctypes.byref(fb))
+        self.fused_buffer = None
+        if fused and fb.value:
+            self.fused_buffer = torch.empty(fb.value, dtype=torch.uint8, device=self.device)
+            self._call("tfl_bind_fused_buffer", ctypes.c_void_p(self.fused_buffer.data_ptr()))
         self.maps = None
         self._probes = []
         self._sources = []
