@@ -12,6 +12,7 @@ against its checkpointed forward run.  Prints one JSON line.
     python bench.py --large      # the 1024 x 512 x 256 workload: FP32 forward 8192 steps and the
                                  # three-level adjoint, plus a finite-difference check of the FP64
                                  # gradient over 512 steps (several minutes)
+    python bench.py --table1     # the paper's skin-depth sweep, 12 rows (about 8 minutes)
 """
 import argparse
 import hashlib
@@ -223,6 +224,49 @@ def cpu_baseline(wl, steps):
                 sample=f"{steps} FP64 steps of the same {wl['shape'][0]}^3 grid ({dt:.1f} s)")
 
 
+def table1_run():
+    """The paper's skin-depth sweep (Sec. 4.1, Table 1): all twelve (sigma, f) rows in FP64 on 1-D lines
+    with CPML ends, five periods each (the undamped 100 THz row, 16 % below the cutoff, also after 200
+    periods); skin depth from the steady-state amplitudes at the source and at z0."""
+    import numpy as np
+    import torch
+
+    from oracle import closed_forms as cf
+    from paper_2305_13419_amd import Simulation, workloads
+
+    ell = 1.0 / (400e-9) ** 2
+    rows = []
+    runs = [(s, f, p, 5) for s, f, p in workloads.TABLE1_ROWS] + [(0.0, 1e14, 739, 200)]
+    for sigma, freq, paper, periods in runs:
+        theory = float(cf.skin_depth(freq, 1.0, sigma, ell))
+        wl = workloads.table1_grid(sigma, freq, theory, periods=periods)
+        sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], 1.0, torch.float64, wl["pml"])
+        sim.set_materials(*wl["maps"])
+        for src in wl["sources"]:
+            sim.add_source(**src)
+        pids = [sim.add_probe(p["comp"], p["box"], wl["steps"] + 1) for p in wl["probes"]]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        left = wl["steps"]
+        while left > 0:
+            c = min(left, 1000000)
+            sim.step(c)
+            left -= c
+            torch.cuda.synchronize()
+            print(f"# table1 sigma={sigma:g} f={freq:g}: {wl['steps'] - left} / {wl['steps']} steps, "
+                  f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+        el = time.perf_counter() - t0
+        fit = 50 if periods > 5 else 2
+        a0, a1 = (workloads.steady_amplitude(sim.probe(p)[0], wl["dt"], freq, periods=fit) for p in pids)
+        sim.close()
+        rows.append(dict(sigma=sigma, f=freq, periods=periods, steps=wl["steps"], seconds=el,
+                         computed_nm=wl["z0"] / np.log(a0 / a1) * 1e9,
+                         discrete_nm=float(cf.discrete_skin_depth(freq, 10e-9, wl["dt"], 1.0, 1.0, sigma, ell)) * 1e9,
+                         theory_nm=theory * 1e9, paper_computed_nm=paper))
+        print(f"# {rows[-1]}", file=sys.stderr, flush=True)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +277,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--large", action="store_true")
+    ap.add_argument("--table1", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1).", file=sys.stderr)
@@ -244,6 +289,9 @@ def main():
 
     if args.large:
         print(json.dumps({"metric": METRIC, "large": large_run()}), flush=True)
+        return
+    if args.table1:
+        print(json.dumps({"metric": "skin depth (nm), Table 1 sweep", "table1": table1_run()}), flush=True)
         return
 
     wl = workloads.roofline_grid(args.n, steps=args.steps)

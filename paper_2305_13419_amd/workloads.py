@@ -181,3 +181,43 @@ def large_mixed_grid(seed=5, steps=8192):
                               t0=4 * tw, tw=tw)],
                 probes=[dict(comp=1, box=(512, 513, 0, 512, 128, 129))], freq=f, steps=steps,
                 objective=(1, (512, 513, 0, 512, 128, 129), None))
+
+
+# Rows of the paper's skin-depth sweep (Sec. 4.1, Table 1): (sigma S/m, f Hz, paper's computed delta nm).
+TABLE1_ROWS = [(0.0, 25e9, 400), (0.0, 100e9, 400), (0.0, 1e12, 400), (0.0, 1e14, 739),
+               (1e4, 25e9, 400), (1e4, 100e9, 400), (1e4, 1e12, 400), (1e4, 1e14, 450),
+               (1e7, 25e9, 395), (1e7, 100e9, 350), (1e7, 1e12, 153), (1e7, 1e14, 13)]
+
+
+def table1_grid(sigma, freq, delta_theory, half=3000, npml=32, periods=5):
+    """One row of the skin-depth sweep: a homogeneous superconductor (lambda_L = 400 nm, eps_r = 1,
+    sigma_n = sigma) on a 1-D line of 10 nm cells along x (ny = nz = 1; dy = dz = 1 m so the stability
+    bound is the 1-D one), dt = 0.03 fs, a soft Ey sine of frequency freq on the centre node, run to 5
+    periods (the paper's run) unless `periods` says otherwise.  The paper's domains (+-32 um .. +-128 mm) only keep the start-up transient away from the
+    ends; here `half` cells on each side (30 um, > 40 skin depths) end in CPML slabs that absorb it.
+    Probes: Ey at the source node and at the node nearest to delta_theory from it (the paper's z0)."""
+    d = 10e-9
+    nx = 2 * half + 2 * npml + 1
+    shp = (1, 1, nx)
+    ic = nx // 2
+    z0 = max(1, int(round(delta_theory / d)))
+    dt = 3e-17
+    steps = int(np.ceil(periods / freq / dt))
+    return dict(name=f"table1 sigma={sigma:g} f={freq:g}", shape=(nx, 1, 1), spacing=(d, 1.0, 1.0), dt=dt,
+                theta=1.0, pml=((npml, npml), None, None),
+                maps=(np.ones(shp), np.full(shp, float(sigma)), np.full(shp, 1.0 / (400e-9) ** 2)),
+                fields=None,
+                sources=[dict(comp=1, box=(ic, ic + 1, 0, 1, 0, 1), amplitude=1.0, waveform="sin", freq=freq)],
+                probes=[dict(comp=1, box=(ic, ic + 1, 0, 1, 0, 1)), dict(comp=1, box=(ic + z0, ic + z0 + 1, 0, 1, 0, 1))],
+                z0=z0 * d, freq=freq, steps=steps)
+
+
+def steady_amplitude(series, dt, freq, periods=2):
+    """Amplitude of the steady oscillation at freq: least-squares fit of a cos + b sin + c over the last
+    `periods` periods of the series (sample n at time n dt)."""
+    series = np.asarray(series, dtype=np.float64)
+    m = int(round(periods / freq / dt))
+    t = np.arange(series.size - m, series.size) * dt
+    A = np.stack([np.cos(2 * np.pi * freq * t), np.sin(2 * np.pi * freq * t), np.ones_like(t)], axis=1)
+    coef, *_ = np.linalg.lstsq(A, series[-m:], rcond=None)
+    return float(np.hypot(coef[0], coef[1]))

@@ -518,3 +518,20 @@ def test_probe_dft_closed_form():
         z = np.exp(-2j * np.pi * m * f * dt)
         closed = A * dt * z * (1 - (N + 1) * z**N + N * z ** (N + 1)) / (1 - z) ** 2
         assert abs(F - closed) <= 1e-10 * abs(closed)
+
+
+def test_table1_row_100THz_sigma1e4_reproduced_by_the_oracle():
+    """Sec. 4.1, Table 1, row sigma = 1e4 S/m, f = 100 THz (lambda_L = 400 nm, dz = 10 nm, dt = 0.03 fs,
+    five periods of a soft sine): the skin depth measured from the oracle's field, z0 / ln(A(0)/A(z0)),
+    equals the discrete prediction 1 / Im k and the paper's computed 450 nm (the continuum value is
+    447.9 nm)."""
+    from paper_2305_13419_amd import workloads
+    from tests.helpers import run_oracle
+    ell = 1.0 / (400e-9) ** 2
+    theory = float(cf.skin_depth(1e14, 1.0, 1e4, ell))
+    wl = workloads.table1_grid(1e4, 1e14, theory, half=600)
+    _, _, _, probes = run_oracle(wl, wl["steps"])
+    a0, a1 = (workloads.steady_amplitude(p[0], wl["dt"], 1e14) for p in probes)
+    delta = wl["z0"] / np.log(a0 / a1)
+    assert abs(delta / cf.discrete_skin_depth(1e14, 10e-9, wl["dt"], 1.0, 1.0, 1e4, ell) - 1) < 1e-4
+    assert abs(delta * 1e9 - 450) < 0.5 and abs(theory * 1e9 - 447.92) < 0.01
