@@ -13,6 +13,7 @@ against its checkpointed forward run.  Prints one JSON line.
                                  # three-level adjoint, plus a finite-difference check of the FP64
                                  # gradient over 512 steps (several minutes)
     python bench.py --table1     # the paper's skin-depth sweep, 12 rows (about 8 minutes)
+    python bench.py --paper-cpw  # step rate on the paper's CPW resonator at its own size, 4 film cases
 """
 import argparse
 import hashlib
@@ -267,6 +268,42 @@ def table1_run():
     return rows
 
 
+def paper_cpw_run(steps=200, warmup=10):
+    """Step rate on the paper's CPW resonator at its own size (196 M cells with the CPML slabs), each
+    film case, FP32 and FP64, against the paper's ~0.05 s per step on 32 A100 GPUs."""
+    import numpy as np
+    import torch
+
+    from paper_2305_13419_amd import Simulation, workloads
+
+    rows = []
+    for case in (1, 2, 3, 4):
+        wl = workloads.paper_cpw_grid(case)
+        for dtype, npdt in ((torch.float32, np.float32), (torch.float64, np.float64)):
+            sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"])
+            sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
+            for src in wl["sources"]:
+                sim.add_source(**src)
+            pids = [sim.add_probe(p["comp"], p["box"], steps + warmup + 1) for p in wl["probes"]]
+            sim.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            W, bad = sim.energy()
+            series_ok = bool(np.all(np.isfinite(sim.probe(pids[1])[0])))
+            sim.close()
+            n = int(np.prod(wl["shape"]))
+            rows.append(dict(case=case, dtype=str(dtype)[6:], cells=n, steps=steps, ms_per_step=el / steps * 1e3,
+                             Gcells=n * steps / el / 1e9, dt_s=wl["dt"], nonfinite=int(bad), probes_finite=series_ok,
+                             paper_s_per_step=0.05, speedup_per_step=0.05 / (el / steps)))
+            print(f"# {rows[-1]}", file=sys.stderr, flush=True)
+            del sim
+            torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +315,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--large", action="store_true")
     ap.add_argument("--table1", action="store_true")
+    ap.add_argument("--paper-cpw", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1).", file=sys.stderr)
@@ -289,6 +327,10 @@ def main():
 
     if args.large:
         print(json.dumps({"metric": METRIC, "large": large_run()}), flush=True)
+        return
+    if args.paper_cpw:
+        print(json.dumps({"metric": "step rate on the paper's CPW resonator", "paper_cpw": paper_cpw_run()}),
+              flush=True)
         return
     if args.table1:
         print(json.dumps({"metric": "skin depth (nm), Table 1 sweep", "table1": table1_run()}), flush=True)

@@ -221,3 +221,71 @@ def steady_amplitude(series, dt, freq, periods=2):
     A = np.stack([np.cos(2 * np.pi * freq * t), np.sin(2 * np.pi * freq * t), np.ones_like(t)], axis=1)
     coef, *_ = np.linalg.lstsq(A, series[-m:], rcond=None)
     return float(np.hypot(coef[0], coef[1]))
+
+
+# Material of the film in the four cases of the paper's CPW study (Sec. 5, Table 7): (sigma S/m,
+# 1/lambda_L^2 m^-2) and the paper's Q and computed resonance (GHz).
+PAPER_CPW_CASES = {1: (6e7, 0.0, 24, 96.9), 2: (1e10, 0.0, 491, 98.2), 3: (6e7, 1e14, 316, 97.1),
+                   4: (0.0, 1e14, 973, 97.1)}
+
+
+def paper_cpw_grid(case=3, npml=(8, 8, 16), fields=None, seed=11, dz=50e-9, dt=None):
+    """The paper's coplanar-waveguide resonator at its own size (Sec. 5): the domain [-65, 65] um x
+    [-504, 504] um x [0, 64] um in 130 x 1008 x 1280 cells (dx = dy = 1 um, dz = 50 nm), with CPML
+    slabs of npml cells added outside it on every face (the paper's PML is outside its domain too).
+    Silicon substrate (eps_r = 11.7) for z < 32 um, a 200 nm film on it patterned as two ground planes
+    (50 um wide, 1000 um long), two 6 um gaps and the 10 um centre line cut along y into input port
+    [-500, -400] um, coupling gap, resonator [-300, 300] um, coupling gap, output port [400, 500] um;
+    vacuum above; the film material is that of `case` (PAPER_CPW_CASES).  Source: opposite soft Ex
+    Gaussian-modulated sines exp(-(t - 4T)^2 / (2 T^2)) sin(2 pi t / T), T = 1 / 100 GHz, in the two gaps
+    at y = -500 um over the film thickness.  Probes: Ex in the left gap at y = -450 um and -300 um, on
+    the film's middle plane.  dt defaults to 0.95 x the stable limit with the London term (0.158 fs,
+    the paper's).  fields='random' gives seeded N(0, 1) initial fields (parity tests)."""
+    sig_f, ell_f, _, _ = PAPER_CPW_CASES[case]
+    px, py, pz = npml
+    dx = dy = 1e-6
+    nx, ny, nz = 130 + 2 * px, 1008 + 2 * py, int(round(64e-6 / dz)) + 2 * pz
+    shp = (nz, ny, nx)
+    # cell centres in um (x, y) and nm-free z index of the domain
+    xc = (np.arange(nx) - px) * 1.0 - 65.0 + 0.5
+    yc = (np.arange(ny) - py) * 1.0 - 504.0 + 0.5
+    kz = np.arange(nz) - pz                         # cell k spans [kz dz, (kz + 1) dz]
+    k_sub = int(round(32e-6 / dz))                  # substrate cells kz < k_sub
+    k_film = k_sub + int(round(200e-9 / dz))        # film cells k_sub <= kz < k_film
+    eps = np.ones(shp)
+    eps[kz < k_sub] = 11.7
+    X, Y = np.meshgrid(xc, yc)                      # (ny, nx)
+    inside_y = np.abs(Y) < 500.0
+    ground = inside_y & (np.abs(X) > 11.0) & (np.abs(X) < 61.0)
+    line = (np.abs(X) < 5.0) & (((Y > -500.0) & (Y < -400.0)) | ((Y > -300.0) & (Y < 300.0)) |
+                                ((Y > 400.0) & (Y < 500.0)))
+    film = ground | line
+    sig = np.zeros(shp)
+    ell = np.zeros(shp)
+    fz = (kz >= k_sub) & (kz < k_film)
+    sig[np.ix_(fz, np.ones(ny, bool), np.ones(nx, bool))] = np.where(film, sig_f, 0.0)[None]
+    ell[np.ix_(fz, np.ones(ny, bool), np.ones(nx, bool))] = np.where(film, ell_f, 0.0)[None]
+    if dt is None:
+        dt = courant_dt((dx, dy, dz), 1e14, 0.95)
+    f = 100e9
+    T = 1.0 / f
+    i_of = lambda x: int(np.floor(x + 65.0)) + px    # noqa: E731  (cell index holding coordinate x um)
+    j_of = lambda y: int(np.floor(y + 504.0)) + py   # noqa: E731
+    k0, k1 = k_sub + pz, k_film + pz + 1             # Ex edges on the film's node planes
+    js = j_of(-500.0)
+    src = [dict(comp=0, box=(i_of(-11.0), i_of(-5.0), js, js + 1, k0, k1), amplitude=1.0, waveform="mod_gauss",
+                freq=f, t0=4 * T, tw=T),
+           dict(comp=0, box=(i_of(5.0), i_of(11.0), js, js + 1, k0, k1), amplitude=-1.0, waveform="mod_gauss",
+                freq=f, t0=4 * T, tw=T)]
+    km = (k_sub + k_film) // 2 + pz
+    probes = [dict(comp=0, box=(i_of(-8.0), i_of(-8.0) + 1, j_of(-450.0), j_of(-450.0) + 1, km, km + 1)),
+              dict(comp=0, box=(i_of(-8.0), i_of(-8.0) + 1, j_of(-300.0), j_of(-300.0) + 1, km, km + 1))]
+    F = None
+    if fields == "random":
+        rng = np.random.default_rng(seed)
+        E = [rng.standard_normal(shp) for _ in range(3)]
+        H = [rng.standard_normal(shp) / 377.0 for _ in range(3)]
+        F = (E, H, None)
+    return dict(name=f"paper cpw {nx}x{ny}x{nz} case {case}", shape=(nx, ny, nz), spacing=(dx, dy, dz), dt=dt,
+                theta=1.0, pml=((px, px), (py, py), (pz, pz)), maps=(eps, sig, ell), fields=F, sources=src,
+                probes=probes, freq=f, steps=850000)
