@@ -14,6 +14,7 @@ against its checkpointed forward run.  Prints one JSON line.
                                  # gradient over 512 steps (several minutes)
     python bench.py --table1     # the paper's skin-depth sweep, 12 rows (about 8 minutes)
     python bench.py --paper-cpw  # step rate on the paper's CPW resonator at its own size, 4 film cases
+    python bench.py --paper-cpw-q 1,2   # Q and f of film cases 1 and 2 at dz = 200 nm (~8 min per case)
 """
 import argparse
 import hashlib
@@ -304,6 +305,60 @@ def paper_cpw_run(steps=200, warmup=10):
     return rows
 
 
+def paper_cpw_q_run(cases=(1, 2, 3, 4), dz=200e-9, t_end=134e-12, t_fit=80e-12):
+    """Q and resonance of the paper's CPW (Sec. 5, Table 7) at a coarser z resolution (dz = 200 nm, the
+    film one cell thick; the paper's 50 nm needs 850 000 steps of 196 M cells): FP32 fields, FP64 probe
+    series, run to t_end; ESPRIT (and the linear predictor) on the Ex probe at the resonator's front edge
+    from t_fit on, decimated to ~32 samples per period of the DFT peak."""
+    import numpy as np
+    import torch
+
+    from paper_2305_13419_amd import Simulation, workloads
+
+    rows = []
+    for case in cases:
+        wl = workloads.paper_cpw_grid(case, dz=dz)
+        steps = int(np.ceil(t_end / wl["dt"]))
+        sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], torch.float32, wl["pml"])
+        sim.set_materials(*[np.asarray(m, dtype=np.float32) for m in wl["maps"]])
+        for src in wl["sources"]:
+            sim.add_source(**src)
+        pids = [sim.add_probe(p["comp"], p["box"], steps + 1) for p in wl["probes"]]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            c = min(steps - done, 20000)
+            sim.step(c)
+            done += c
+            torch.cuda.synchronize()
+            print(f"# paper cpw case {case}: {done} / {steps} steps, {time.perf_counter() - t0:.0f} s", file=sys.stderr,
+                  flush=True)
+        el = time.perf_counter() - t0
+        series = np.asarray(sim.probe(pids[1])[0])
+        start = int(t_fit / wl["dt"])
+        tail = series[start:]
+        freqs = np.linspace(50e9, 150e9, 2001)
+        t = np.arange(tail.size) * wl["dt"]
+        spec = np.abs(np.exp(-2j * np.pi * np.outer(freqs, t)) @ tail)
+        fh = float(freqs[np.argmax(spec)])
+        decim = max(1, int(round(1.0 / fh / wl["dt"] / 32)))
+        count = (steps - start) // decim
+        esp = sim.esprit_fit(pids[1], start, count, decim, 0, 0, f_hint=fh)
+        lp = sim.ringdown_fit(pids[1], start, count, decim, 0, f_hint=fh)
+        sim.close()
+        _, _, q_paper, f_paper = workloads.PAPER_CPW_CASES[case]
+        rows.append(dict(case=case, dz=dz, cells=int(np.prod(wl["shape"])), steps=steps, seconds=el, dft_peak_GHz=fh / 1e9,
+                         esprit=dict(f_GHz=esp["f0"] / 1e9, Q=esp["Q"], order=esp["order"]),
+                         linear_prediction=dict(f_GHz=lp["f0"] / 1e9, Q=lp["Q"], order=lp["order"]),
+                         paper=dict(f_GHz=f_paper, Q=q_paper), window=dict(start=start, count=count, decim=decim)))
+        print(f"# {rows[-1]}", file=sys.stderr, flush=True)
+        np.save(os.path.join(ROOT, "gpurun_out", f"paper_cpw_q_case{case}.npy"), series[::16])
+        del sim
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,6 +371,7 @@ def main():
     ap.add_argument("--large", action="store_true")
     ap.add_argument("--table1", action="store_true")
     ap.add_argument("--paper-cpw", action="store_true")
+    ap.add_argument("--paper-cpw-q", type=str, default="", help="comma-separated film cases, e.g. 1,2")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1).", file=sys.stderr)
@@ -327,6 +383,11 @@ def main():
 
     if args.large:
         print(json.dumps({"metric": METRIC, "large": large_run()}), flush=True)
+        return
+    if args.paper_cpw_q:
+        cases = tuple(int(c) for c in args.paper_cpw_q.split(","))
+        print(json.dumps({"metric": "Q and f of the paper's CPW at dz = 200 nm", "paper_cpw_q": paper_cpw_q_run(cases)}),
+              flush=True)
         return
     if args.paper_cpw:
         print(json.dumps({"metric": "step rate on the paper's CPW resonator", "paper_cpw": paper_cpw_run()}),
