@@ -48,15 +48,24 @@ def sc_edge_fraction(ell):
     return float(np.mean(fr))
 
 
-def run_gpu(wl, dtype, steps, warmup, fused=True):
+def run_gpu(wl, dtype, steps, warmup, fused=True, classes=True):
     import numpy as np
     import torch
 
     from paper_2305_13419_amd import Simulation
 
     npdt = np.float64 if dtype == torch.float64 else np.float32
-    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"], fused=fused)
-    sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
+    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"], fused=fused,
+                     edge_classes=classes)
+    maps = [np.asarray(m, dtype=npdt) for m in wl["maps"]]
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    sim.set_materials(*maps)
+    torch.cuda.synchronize()
+    bind_s = time.perf_counter() - tb
+    ncls = sim.edge_classes
+    if classes and not ncls:
+        raise RuntimeError("edge classes requested but the grid has too many distinct materials")
     E, H, _ = wl["fields"]
     sim.set_fields([np.asarray(a, dtype=npdt) for a in E], [np.asarray(a, dtype=npdt) for a in H])
     sim.step(warmup)
@@ -70,7 +79,7 @@ def run_gpu(wl, dtype, steps, warmup, fused=True):
     W, bad = sim.energy()
     sim.close()
     return dict(h_ms=h_ms / steps, e_ms=e_ms / steps, step_ms=(h_ms + e_ms) / steps, wall_s=wall,
-                nonfinite=int(bad), energy=W)
+                nonfinite=int(bad), energy=W, edge_classes=ncls, bind_materials_s=bind_s)
 
 
 def measured_traffic(dtype_name, kernel):
@@ -401,35 +410,42 @@ def main():
     ncell = args.n**3
     fJ = sc_edge_fraction(wl["maps"][2])
     res = {}
+    # product path: the fused sweep with edge classes; beside it the fused sweep on the per-cell maps
+    # and the two passes (the path of grids with CPML) with edge classes
+    modes = {"fused": (True, True), "fused_maps": (True, False), "two_pass": (False, True)}
     for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
-        for fused in (True, False):
-            print(f"# {name} {'fused sweep' if fused else 'two passes'}: {args.warmup} warm-up + {args.steps} "
-                  f"timed steps on {wl['name']}", file=sys.stderr, flush=True)
-            res[name, fused] = run_gpu(wl, dt, args.steps, args.warmup, fused)
+        for mode, (fused, classes) in modes.items():
+            print(f"# {name} {mode}: {args.warmup} warm-up + {args.steps} timed steps on {wl['name']}",
+                  file=sys.stderr, flush=True)
+            res[name, mode] = run_gpu(wl, dt, args.steps, args.warmup, fused, classes)
     out = {}
     for name, w in (("f64", 8), ("f32", 4)):
-        # the product path on this all-periodic grid: one fused sweep per step
-        r = res[name, True]
-        f_bytes = w * (15 + 6 * fJ) * ncell      # E, H, maps read; E, H written; Js r/w on SC edges
-        f_gbs = f_bytes / (r["h_ms"] * 1e-3) / 1e9
-        # the two passes (the path of grids with CPML)
-        t = res[name, False]
-        e_bytes = w * (12 + 6 * fJ) * ncell      # E pass: H, E, maps read; E written; Js r/w on SC edges
-        h_bytes = w * 9 * ncell                   # H pass: E, H read; H written
-        e_gbs = e_bytes / (t["e_ms"] * 1e-3) / 1e9
+        # per cell: E, H read and written (fused) or E read and written, H read (E pass); Js read and
+        # written on the f_J superconducting edges; the E update's coefficients as three 16-bit edge
+        # classes (6 B) or three per-cell maps (3 w)
+        f_cell = w * (12 + 6 * fJ) + 6
+        m_cell = w * (15 + 6 * fJ)
+        e_cell = w * (9 + 6 * fJ) + 6
+        h_cell = w * 9                             # H pass: E, H read; H written
+
+        def roof(kernel, ms, cell, traffic_key):
+            gbs = cell * ncell / (ms * 1e-3) / 1e9
+            return dict(bound="hbm", kernel=kernel, achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=gbs / HBM_PEAK_GBS, traffic=measured_traffic(name, traffic_key), bytes_per_cell=cell,
+                        algorithmic_bytes_per_launch=cell * ncell)
+
+        r, m, t = res[name, "fused"], res[name, "fused_maps"], res[name, "two_pass"]
         out[name] = dict(
             value=ncell / (r["step_ms"] * 1e-3) / 1e9, ms_per_step=r["step_ms"], fused_step_ms=r["h_ms"],
-            fused_step_GBs=f_gbs, nonfinite=r["nonfinite"],
-            roofline=dict(bound="hbm", kernel="fused_step_kernel", achieved=f_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                          frac=f_gbs / HBM_PEAK_GBS, traffic=measured_traffic(name, "fused_step_kernel"),
-                          bytes_per_cell=w * (15 + 6 * fJ), algorithmic_bytes_per_launch=f_bytes),
+            nonfinite=r["nonfinite"], edge_classes=r["edge_classes"], bind_materials_s=r["bind_materials_s"],
+            roofline=roof("fused_step_kernel (edge classes)", r["h_ms"], f_cell, "fused_step_kernel"),
+            maps_path=dict(
+                value=ncell / (m["step_ms"] * 1e-3) / 1e9, ms_per_step=m["step_ms"], nonfinite=m["nonfinite"],
+                roofline=roof("fused_step_kernel (maps)", m["h_ms"], m_cell, "fused_step_kernel_maps")),
             two_pass=dict(
                 value=ncell / (t["step_ms"] * 1e-3) / 1e9, ms_per_step=t["step_ms"], h_pass_ms=t["h_ms"],
-                e_pass_ms=t["e_ms"], h_pass_GBs=h_bytes / (t["h_ms"] * 1e-3) / 1e9, e_pass_GBs=e_gbs,
-                nonfinite=t["nonfinite"],
-                roofline=dict(bound="hbm", kernel="e_pass_kernel", achieved=e_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                              frac=e_gbs / HBM_PEAK_GBS, traffic=measured_traffic(name, "e_pass_kernel"),
-                              bytes_per_cell=w * (12 + 6 * fJ), algorithmic_bytes_per_launch=e_bytes)),
+                e_pass_ms=t["e_ms"], h_pass_GBs=h_cell * ncell / (t["h_ms"] * 1e-3) / 1e9, nonfinite=t["nonfinite"],
+                roofline=roof("e_pass_kernel (edge classes)", t["e_ms"], e_cell, "e_pass_kernel")),
         )
     f64 = out["f64"]
     line = {

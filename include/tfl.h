@@ -61,7 +61,8 @@ enum {
     TFL_E_UNSTABLE = -3,  /* dt above the stability bound of the scheme       */
     TFL_E_NONFINITE = -4, /* NaN or Inf found in the state                     */
     TFL_E_DEVICE = -5,    /* a HIP runtime error; the message names it        */
-    TFL_E_NOMEM = -6      /* a caller buffer is smaller than required          */
+    TFL_E_NOMEM = -6,     /* a caller buffer is smaller than required          */
+    TFL_E_RANGE = -7      /* more distinct values than a compact table holds   */
 };
 
 enum { TFL_F64 = 0, TFL_F32 = 1 };
@@ -173,6 +174,33 @@ int tfl_bind_fused_buffer(tfl_sim *sim, void *buffer);
  * then takes the mean of (eps_r, sigma, inv_lambda2) over those cells;
  * otherwise it takes the mean of (eps_r, sigma) over all four. */
 int tfl_bind_materials(tfl_sim *sim, const void *eps_r, const void *sigma_n, const void *inv_lambda2, void *stream);
+
+/* Edge-coefficient classes (optional; forward sweeps only).  The E update of
+ * an edge uses three coefficients fixed by the four cells sharing it (Sec. 3
+ * edge rule, Algorithm 1 step 3): E^{n+1} = ca E^n + cb (curl H - Js^{n+1/2}),
+ * Js^{n+1/2} = Js^{n-1/2} + cj E^n.  When the grid holds few distinct
+ * materials, tfl_bind_edge_classes replaces the three per-cell maps read by
+ * the E update with one 16-bit class per edge and a table of (ca, cb, cj):
+ * 6 bytes per cell instead of 3 x sizeof(dtype) plus neighbour reads.  The
+ * table entries are computed on the device by the same code as the per-edge
+ * coefficients of the map path, so results are bit-identical.
+ *
+ * buffer: caller-owned device memory of tfl_edge_class_bytes bytes, 256-byte
+ * aligned; holds, in this order, the classes of the x, y and z edges (N
+ * uint16 each, each array padded to 256 bytes), the table
+ * (TFL_MAX_EDGE_CLASSES entries of 4 dtype values: ca, cb, cj, 0) and the
+ * staging area the table is built from.  The classes are a snapshot of the
+ * maps bound when the call is made: tfl_bind_materials unbinds them, so after
+ * binding (or changing) the maps, bind the classes again.  Builds on the host
+ * (the maps are copied to host memory) and synchronises `stream`.
+ * *nclasses (may be NULL) receives the number of classes.  TFL_E_RANGE, with
+ * the simulation left on the map path, when the grid has more than 65536
+ * distinct cell materials or more than TFL_MAX_EDGE_CLASSES distinct edge
+ * materials; TFL_E_STATE without bound maps.  A NULL buffer unbinds.  The
+ * adjoint sweeps always read the maps. */
+#define TFL_MAX_EDGE_CLASSES 65535
+int tfl_edge_class_bytes(const tfl_sim *sim, size_t *bytes);
+int tfl_bind_edge_classes(tfl_sim *sim, void *buffer, int *nclasses, void *stream);
 
 /* The bound H and Js hold integer-time values H^0, Js^0 (E holds E^0):
  * replace them with H^{-1/2} and Js^{-1/2} by running the first half

@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtfl.so")
 
-SOURCES = ["kernels_fwd.hip", "kernels_adj.hip", "fit.hip", "api.cpp", "api_adj.cpp", "api_fit.cpp"]
+SOURCES = ["kernels_fwd.hip", "kernels_adj.hip", "fit.hip", "api.cpp", "api_adj.cpp", "api_fit.cpp", "api_cls.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

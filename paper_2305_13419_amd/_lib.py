@@ -20,6 +20,7 @@ TFL_E_UNSTABLE = -3
 TFL_E_NONFINITE = -4
 TFL_E_DEVICE = -5
 TFL_E_NOMEM = -6
+TFL_E_RANGE = -7
 ERROR_NAMES = {
     TFL_E_INVAL: "TFL_E_INVAL",
     TFL_E_STATE: "TFL_E_STATE",
@@ -27,6 +28,7 @@ ERROR_NAMES = {
     TFL_E_NONFINITE: "TFL_E_NONFINITE",
     TFL_E_DEVICE: "TFL_E_DEVICE",
     TFL_E_NOMEM: "TFL_E_NOMEM",
+    TFL_E_RANGE: "TFL_E_RANGE",
 }
 
 TFL_F64, TFL_F32 = 0, 1
@@ -35,6 +37,7 @@ TFL_WAVE_SIN, TFL_WAVE_GAUSS, TFL_WAVE_MOD_GAUSS = 0, 1, 2
 TFL_MAX_SOURCES = 32
 TFL_MAX_PROBES = 32
 TFL_MAX_FREQS = 16
+TFL_MAX_EDGE_CLASSES = 65535
 
 
 class tfl_config(ctypes.Structure):
@@ -125,6 +128,8 @@ SIGNATURES = {
     "tfl_ringdown_fit": [P, ctypes.c_int, ctypes.POINTER(tfl_fit_req), ctypes.POINTER(tfl_fit_result), P],
     "tfl_fused_buffer_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
     "tfl_bind_fused_buffer": [P, P],
+    "tfl_edge_class_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
+    "tfl_bind_edge_classes": [P, P, ctypes.POINTER(ctypes.c_int), P],
     "tfl_esprit_fit": [P, ctypes.c_int, ctypes.POINTER(tfl_fit_req), ctypes.c_int32, ctypes.POINTER(tfl_fit_result),
                        P],
     "tfl_adjoint_nested_sizes": [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t),

@@ -118,6 +118,9 @@ StepArgs<T> make_args(const tfl_sim *s)
     a.eps = (const T *)s->eps;
     a.sig = (const T *)s->sig;
     a.ell = (const T *)s->ell;
+    const void *tab;
+    class_pointers(s, a.cls, &tab);
+    a.ctab = (const T *)tab;
     a.rd[0] = (T)(1.0 / c.dx);
     a.rd[1] = (T)(1.0 / c.dy);
     a.rd[2] = (T)(1.0 / c.dz);
@@ -431,6 +434,8 @@ int tfl_bind_materials(tfl_sim *s, const void *eps_r, const void *sigma_n, const
 {
     if (!s) return fail(nullptr, TFL_E_INVAL, "null handle");
     if (!s->work_bound) return fail(s, TFL_E_STATE, "bind the workspace (scratch) before the materials");
+    s->cls = nullptr;  // edge classes are a snapshot of the previous maps
+    s->ncls = 0;
     if (!eps_r || !sigma_n || !inv_lambda2) return fail(s, TFL_E_INVAL, "null map pointer");
     if (!aligned(eps_r) || !aligned(sigma_n) || !aligned(inv_lambda2))
         return fail(s, TFL_E_INVAL, "map pointers must be 256-byte aligned");

@@ -107,13 +107,20 @@ int forward_ckpt(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg
     return TFL_OK;
 }
 
+// Value a soft source adds at time t (the waveforms of the source kernel).
+double source_value(const SourceDesc &d, double t)
+{
+    if (d.wave == TFL_WAVE_SIN) return d.amp * std::sin(kTwoPi * d.f * t);
+    const double g = std::exp(-(t - d.t0) * (t - d.t0) / (2.0 * d.tw * d.tw));
+    return d.amp * (d.wave == TFL_WAVE_GAUSS ? g : g * std::sin(kTwoPi * d.f * t));
+}
+
 template <typename T>
 struct Reverse {
     tfl_sim *s;
     const tfl_objective *o;
     const double *F;
     AdjArgs<T> A;
-    SrcArgs<T> sa;   // the sources with negated amplitudes (removes them from a snapshot)
     void *snap;
     size_t fb;
     int64_t n0, nend;
@@ -164,11 +171,7 @@ struct Reverse {
         const int64_t end = s0 + len;
         for (int64_t n = end; n >= s0 + 1; --n) {
             if (n != end && (e = launch_adj_faces<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint faces");
-            if (sa.nsrc > 0) {
-                for (int q = 0; q < 3; ++q) sa.E[q] = snapE(n - s0, q);
-                sa.t = (double)n * dt;
-                if ((e = launch_sources<T>(sa, st)) != hipSuccess) return hip_fail(s, e, "snapshot sources");
-            }
+            for (int q = 0; q < A.nsrc; ++q) A.sg[q] = source_value(s->src[q], (double)n * dt);
             A.doC = (n != nend);
             A.doA = 1;
             A.obj = 1;
@@ -228,12 +231,11 @@ int make_reverse(tfl_sim *s, const tfl_objective *o, const double F[2], void *sn
     for (int q = 0; q < 3; ++q) { A.gS[q] = (double *)p; p += L.grad; }
     A.ocomp = o->comp;
     for (int q = 0; q < 6; ++q) A.ob[q] = (int)o->box[q];
-    R.sa = SrcArgs<T>{};
-    R.sa.g = A.f.g;
-    R.sa.nsrc = (int)s->src.size();
-    for (int q = 0; q < R.sa.nsrc; ++q) {
-        R.sa.src[q] = s->src[q];
-        R.sa.src[q].amp = -R.sa.src[q].amp;
+    A.nsrc = (int)s->src.size();
+    for (int q = 0; q < A.nsrc; ++q) {
+        const SourceDesc &d = s->src[q];
+        const int bx[7] = {d.comp, d.i0, d.i1, d.j0, d.j1, d.k0, d.k1};
+        for (int c = 0; c < 7; ++c) A.sbox[q][c] = bx[c];
     }
     return TFL_OK;
 }

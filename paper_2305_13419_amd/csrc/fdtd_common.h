@@ -97,6 +97,30 @@ static __device__ __forceinline__ void edge_material(const T e[4], const T s[4],
     ell = sl * ic;
 }
 
+// Coefficients of one edge: E^{n+1} = ca E^n + cb (curl H - Js^{n+1/2}) and
+// Js^{n+1/2} = Js^{n-1/2} + cj E^n with cj = dt ell_e / mu0 (cj = 0 off the
+// superconductor, where Js stays zero and is neither read nor written).
+template <typename T>
+struct EdgeCoef {
+    T ca, cb, cj;
+};
+
+// Coefficients of class c from the class table (4 values per entry: ca, cb, cj, 0).
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef double double2_t __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ EdgeCoef<T> class_coef(const T *tab, uint32_t c)
+{
+    if constexpr (sizeof(T) == 8) {
+        const double2_t ab = ldp(reinterpret_cast<const double2_t *>(tab), c * 32u);
+        return {ab.x, ab.y, ldp(tab, c * 32u + 16u)};
+    } else {
+        const float4_t v = ldp(reinterpret_cast<const float4_t *>(tab), c * 16u);
+        return {v.x, v.y, v.z};
+    }
+}
+
 // Stretched derivative: d <- kappa^-1 d + psi, psi <- b psi + c d.
 template <typename T>
 static __device__ __forceinline__ T stretch(T d, T *psi, long long pidx, T b, T c, T kinv)

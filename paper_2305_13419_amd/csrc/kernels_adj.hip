@@ -154,12 +154,7 @@ __device__ __forceinline__ void edge_cells(const StepArgs<T> &f, int comp, int i
 
 // Coefficients of one edge (as in the forward E pass): a, b and j = dt ell/mu0.
 template <typename T>
-struct AdjCoef {
-    T ca, cb, cj;
-};
-
-template <typename T>
-__device__ __forceinline__ AdjCoef<T> adj_coef(const T e4[4], const T s4[4], const T l4[4], T dt, T theta, T hdt)
+__device__ __forceinline__ EdgeCoef<T> adj_coef(const T e4[4], const T s4[4], const T l4[4], T dt, T theta, T hdt)
 {
     T eps, sig, ell;
     edge_material(e4, s4, l4, eps, sig, ell);
@@ -173,7 +168,7 @@ __device__ __forceinline__ AdjCoef<T> adj_coef(const T e4[4], const T s4[4], con
 // loaded by the caller: lJ and gL (superconducting edges only), gS, E^n, E'_pre.
 template <typename T>
 __device__ __forceinline__ void adj_edge_local(const AdjArgs<T> &A, int q, long long b, uint32_t ow, uint32_t od,
-                                               const int pos[3], T lEq, const AdjCoef<T> &k, T En, T Ep, T lJ,
+                                               const int pos[3], T lEq, const EdgeCoef<T> &k, T En, T Ep, T lJ,
                                                double gL, double gS)
 {
     const int nx = A.f.g.nx, ny = A.f.g.ny;
@@ -210,7 +205,7 @@ __device__ __forceinline__ void adj_edge_local(const AdjArgs<T> &A, int q, long 
 // the curl^T at k-1 are carried in registers, and the edge coefficients of a
 // plane are formed one iteration ahead so that all loads of an iteration
 // (including lJ and gL on superconducting edges) are issued before the first wait.
-template <typename T, int TY, int TZ>
+template <typename T, int TY, int TZ, bool CLS>
 __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A)
 {
     const int nx = A.f.g.nx, ny = A.f.g.ny, nz = A.f.g.nz;
@@ -236,42 +231,58 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
     }
     T pe00 = T(0), pe10 = T(0), pe01 = T(0), ps00 = T(0), ps10 = T(0), ps01 = T(0), pl00 = T(0), pl10 = T(0),
       pl01 = T(0);
-    AdjCoef<T> cq[3] = {};
+    EdgeCoef<T> cq[3] = {};
     struct Maps {
         T e00, e10, e01, e11, s00, s10, s01, s11, l00, l10, l01, l11;
     };
+    struct Classes {
+        uint32_t x, y, z;
+    };
+    const uint32_t oc = cell * 2u;  // byte offset into a class plane
     auto load_maps = [&](int kk) {
         const long long b = opaque_offset((long long)kk * sxy);
-        const T *me = A.f.eps + b, *ms = A.f.sig + b, *ml = A.f.ell + b;
-        return Maps{ldp(me, o00), ldp(me, o10), ldp(me, o01), ldp(me, o11),
-                    ldp(ms, o00), ldp(ms, o10), ldp(ms, o01), ldp(ms, o11),
-                    ldp(ml, o00), ldp(ml, o10), ldp(ml, o01), ldp(ml, o11)};
+        if constexpr (CLS) {
+            return Classes{ldp(A.f.cls[0] + b, oc), ldp(A.f.cls[1] + b, oc), ldp(A.f.cls[2] + b, oc)};
+        } else {
+            const T *me = A.f.eps + b, *ms = A.f.sig + b, *ml = A.f.ell + b;
+            return Maps{ldp(me, o00), ldp(me, o10), ldp(me, o01), ldp(me, o11),
+                        ldp(ms, o00), ldp(ms, o10), ldp(ms, o01), ldp(ms, o11),
+                        ldp(ml, o00), ldp(ml, o10), ldp(ml, o01), ldp(ml, o11)};
+        }
     };
-    auto coefs = [&](const Maps &m) {
-        {   // Ex: cells (j,k), (j,k-1), (j-1,k), (j-1,k-1)
-            const T e[4] = {m.e00, pe00, m.e01, pe01}, s[4] = {m.s00, ps00, m.s01, ps01},
-                    l[4] = {m.l00, pl00, m.l01, pl01};
-            cq[0] = adj_coef(e, s, l, dt, theta, hdt);
+    auto coefs = [&](const auto &m) {
+        if constexpr (CLS) {
+            cq[0] = class_coef(A.f.ctab, m.x);
+            cq[1] = class_coef(A.f.ctab, m.y);
+            cq[2] = class_coef(A.f.ctab, m.z);
+        } else {
+            {   // Ex: cells (j,k), (j,k-1), (j-1,k), (j-1,k-1)
+                const T e[4] = {m.e00, pe00, m.e01, pe01}, s[4] = {m.s00, ps00, m.s01, ps01},
+                        l[4] = {m.l00, pl00, m.l01, pl01};
+                cq[0] = adj_coef(e, s, l, dt, theta, hdt);
+            }
+            {   // Ey: cells (k,i), (k,i-1), (k-1,i), (k-1,i-1)
+                const T e[4] = {m.e00, m.e10, pe00, pe10}, s[4] = {m.s00, m.s10, ps00, ps10},
+                        l[4] = {m.l00, m.l10, pl00, pl10};
+                cq[1] = adj_coef(e, s, l, dt, theta, hdt);
+            }
+            {   // Ez: cells (i,j), (i,j-1), (i-1,j), (i-1,j-1)
+                const T e[4] = {m.e00, m.e01, m.e10, m.e11}, s[4] = {m.s00, m.s01, m.s10, m.s11},
+                        l[4] = {m.l00, m.l01, m.l10, m.l11};
+                cq[2] = adj_coef(e, s, l, dt, theta, hdt);
+            }
+            pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
+            ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
+            pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
         }
-        {   // Ey: cells (k,i), (k,i-1), (k-1,i), (k-1,i-1)
-            const T e[4] = {m.e00, m.e10, pe00, pe10}, s[4] = {m.s00, m.s10, ps00, ps10},
-                    l[4] = {m.l00, m.l10, pl00, pl10};
-            cq[1] = adj_coef(e, s, l, dt, theta, hdt);
-        }
-        {   // Ez: cells (i,j), (i,j-1), (i-1,j), (i-1,j-1)
-            const T e[4] = {m.e00, m.e01, m.e10, m.e11}, s[4] = {m.s00, m.s01, m.s10, m.s11},
-                    l[4] = {m.l00, m.l01, m.l10, m.l11};
-            cq[2] = adj_coef(e, s, l, dt, theta, hdt);
-        }
-        pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
-        ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
-        pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
     };
     if (A.doA) {
-        const Maps m = load_maps(km0);
-        pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
-        ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
-        pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
+        if constexpr (!CLS) {
+            const Maps m = load_maps(km0);
+            pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
+            ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
+            pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
+        }
         coefs(load_maps(k0));
     }
     for (int k = k0; k < k1; ++k) {
@@ -283,10 +294,10 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
             hx0 = ldp(Hx, o00); hy0 = ldp(Hy, o00); hz0 = ldp(Hz, o00);
             hz_ym = ldp(Hz, o01); hz_xm = ldp(Hz, o10); hx_ym = ldp(Hx, o01); hy_xm = ldp(Hy, o10);
         }
-        const AdjCoef<T> kq[3] = {cq[0], cq[1], cq[2]};
+        const EdgeCoef<T> kq[3] = {cq[0], cq[1], cq[2]};
         T En[3] = {}, Ep[3] = {}, lJ[3] = {};
         double gL[3] = {}, gS[3] = {};
-        Maps mn{};
+        decltype(load_maps(0)) mn{};
         if (A.doA) {
             for (int q = 0; q < 3; ++q) {
                 if (kq[q].cj > T(0)) {
@@ -300,6 +311,18 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
                 if (!theta_one || kq[q].cj > T(0)) En[q] = ldp(A.En[q] + b, o00);
                 Ep[q] = ldp(A.Ep[q] + b, o00);
                 gS[q] = ldp(A.gS[q] + b, od);
+            }
+            // E'_pre: the soft sources of this step taken out of the stored E^{m+1}
+            for (int sidx = 0; sidx < A.nsrc; ++sidx) {
+                if (k >= A.sbox[sidx][5] && k < A.sbox[sidx][6] && j >= A.sbox[sidx][3] && j < A.sbox[sidx][4] &&
+                    i >= A.sbox[sidx][1] && i < A.sbox[sidx][2]) {
+                    const int c = A.sbox[sidx][0];
+                    const double g = A.sg[sidx];
+                    // selects, not a store to Ep[c]: a variable index would move Ep to scratch memory
+                    Ep[0] = (c == 0) ? (T)((double)Ep[0] - g) : Ep[0];
+                    Ep[1] = (c == 1) ? (T)((double)Ep[1] - g) : Ep[1];
+                    Ep[2] = (c == 2) ? (T)((double)Ep[2] - g) : Ep[2];
+                }
             }
             // maps of the next plane (the last iteration re-reads its own plane and discards them)
             mn = load_maps(k + 1 < nz ? k + 1 : k);
@@ -408,8 +431,10 @@ static void launch_adj_tz(bool faces, const AdjArgs<T> &a, hipStream_t s)
     const dim3 blk(kTileX, TY), grd(tile_blocks(a.f.g, TY, TZ));
     if (faces)
         hipLaunchKernelGGL((adj_face_kernel<T, TY, TZ>), grd, blk, 0, s, a);
+    else if (a.f.cls[0])
+        hipLaunchKernelGGL((adj_edge_kernel<T, TY, TZ, true>), grd, blk, 0, s, a);
     else
-        hipLaunchKernelGGL((adj_edge_kernel<T, TY, TZ>), grd, blk, 0, s, a);
+        hipLaunchKernelGGL((adj_edge_kernel<T, TY, TZ, false>), grd, blk, 0, s, a);
 }
 
 template <typename T>

@@ -7,14 +7,17 @@
 //             E^{n+1} = a_e E^n + b_e (curl H^{n+1/2} - Js^{n+1/2})     (Ampere, theta scheme)
 // with a_e = (eps_e - (1-theta) sigma_e dt)/(eps_e + theta sigma_e dt) and
 // b_e = dt/(eps_e + theta sigma_e dt), i.e. Algorithm 1 step 3 multiplied out.
-// Per-edge materials are formed on the fly from the per-cell maps.
+// Per-edge materials are formed on the fly from the per-cell maps.  On grids
+// without CPML the two sweeps can be replaced by one (fused_step_kernel), which
+// reads the old fields from one set of buffers and writes the new ones to
+// another.
 //
-// Each block owns a 64 x 4 column tile of the x-y plane and marches 32
-// planes along z, so the z neighbour of every stencil comes from registers
-// and each word of a sweep is read from HBM once; x and y neighbours hit
-// L1/L2.  Blocks are renumbered so that each XCD (blocks are dealt to the 8
-// XCDs round robin) receives a contiguous range of tiles, keeping the halo
-// rows of neighbouring tiles in the same L2.
+// Each block owns a column tile of the x-y plane (one 64-wide wavefront per
+// row, 4 or 8 rows) and marches 8-64 planes along z (chosen at launch from the
+// grid size), so the z neighbour of every stencil comes from registers; x and
+// y neighbours come from L1/L2.  Blocks are renumbered so that each XCD
+// (blocks are dealt to the 8 XCDs round robin) receives a contiguous range of
+// tiles, keeping the halo rows of neighbouring tiles in the same L2.
 #include "fdtd_common.h"
 
 namespace tfl {
@@ -89,14 +92,7 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void h_pass_kernel(const
 // ---------------------------------------------------------------------------
 // E pass (London supercurrent + Ampere's law with the theta-weighted Ohmic term)
 // ---------------------------------------------------------------------------
-// Coefficients of one edge: E^{n+1} = ca E^n + cb (curl H - Js^{n+1/2}) and
-// Js^{n+1/2} = Js^{n-1/2} + cj E^n with cj = dt ell_e / mu0 (cj = 0 off the
-// superconductor, where Js stays zero and is neither read nor written).
-template <typename T>
-struct EdgeCoef {
-    T ca, cb, cj;
-};
-
+// Coefficients of one edge (EdgeCoef) from the four cells sharing it.
 template <typename T>
 __device__ __forceinline__ EdgeCoef<T> edge_coef(const T e[4], const T s[4], const T l[4], T dt, T theta, T hdt)
 {
@@ -107,7 +103,7 @@ __device__ __forceinline__ EdgeCoef<T> edge_coef(const T e[4], const T s[4], con
     return {(eps - (T(1) - theta) * sdt) * inv, dt * inv, hdt * ell};
 }
 
-template <typename T, int TY, int TZ>
+template <typename T, int TY, int TZ, bool CLS>
 __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const StepArgs<T> a)
 {
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
@@ -136,41 +132,57 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const
     struct Maps {
         T e00, e10, e01, e11, s00, s10, s01, s11, l00, l10, l01, l11;
     };
+    struct Classes {
+        uint32_t x, y, z;
+    };
+    const uint32_t oc = uint32_t(j * nx + i) * 2u;  // byte offset into a class plane
     auto load_maps = [&](int kk) {
         const long long b = opaque_offset((long long)kk * sxy);
-        const T *me = a.eps + b, *ms = a.sig + b, *ml = a.ell + b;
-        return Maps{ldp(me, o00), ldp(me, o10), ldp(me, o01), ldp(me, o11),
-                    ldp(ms, o00), ldp(ms, o10), ldp(ms, o01), ldp(ms, o11),
-                    ldp(ml, o00), ldp(ml, o10), ldp(ml, o01), ldp(ml, o11)};
+        if constexpr (CLS) {
+            return Classes{ldp(a.cls[0] + b, oc), ldp(a.cls[1] + b, oc), ldp(a.cls[2] + b, oc)};
+        } else {
+            const T *me = a.eps + b, *ms = a.sig + b, *ml = a.ell + b;
+            return Maps{ldp(me, o00), ldp(me, o10), ldp(me, o01), ldp(me, o11),
+                        ldp(ms, o00), ldp(ms, o10), ldp(ms, o01), ldp(ms, o11),
+                        ldp(ml, o00), ldp(ml, o10), ldp(ml, o01), ldp(ml, o11)};
+        }
     };
-    auto coefs = [&](const Maps &m) {
-        {   // Ex: cells (j,k), (j,k-1), (j-1,k), (j-1,k-1)
-            const T e[4] = {m.e00, pe00, m.e01, pe01}, s[4] = {m.s00, ps00, m.s01, ps01},
-                    l[4] = {m.l00, pl00, m.l01, pl01};
-            cx = edge_coef(e, s, l, dt, theta, hdt);
+    auto coefs = [&](const auto &m) {
+        if constexpr (CLS) {
+            cx = class_coef(a.ctab, m.x);
+            cy = class_coef(a.ctab, m.y);
+            cz = class_coef(a.ctab, m.z);
+        } else {
+            {   // Ex: cells (j,k), (j,k-1), (j-1,k), (j-1,k-1)
+                const T e[4] = {m.e00, pe00, m.e01, pe01}, s[4] = {m.s00, ps00, m.s01, ps01},
+                        l[4] = {m.l00, pl00, m.l01, pl01};
+                cx = edge_coef(e, s, l, dt, theta, hdt);
+            }
+            {   // Ey: cells (k,i), (k,i-1), (k-1,i), (k-1,i-1)
+                const T e[4] = {m.e00, m.e10, pe00, pe10}, s[4] = {m.s00, m.s10, ps00, ps10},
+                        l[4] = {m.l00, m.l10, pl00, pl10};
+                cy = edge_coef(e, s, l, dt, theta, hdt);
+            }
+            {   // Ez: cells (i,j), (i,j-1), (i-1,j), (i-1,j-1)
+                const T e[4] = {m.e00, m.e01, m.e10, m.e11}, s[4] = {m.s00, m.s01, m.s10, m.s11},
+                        l[4] = {m.l00, m.l01, m.l10, m.l11};
+                cz = edge_coef(e, s, l, dt, theta, hdt);
+            }
+            pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
+            ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
+            pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
         }
-        {   // Ey: cells (k,i), (k,i-1), (k-1,i), (k-1,i-1)
-            const T e[4] = {m.e00, m.e10, pe00, pe10}, s[4] = {m.s00, m.s10, ps00, ps10},
-                    l[4] = {m.l00, m.l10, pl00, pl10};
-            cy = edge_coef(e, s, l, dt, theta, hdt);
-        }
-        {   // Ez: cells (i,j), (i,j-1), (i-1,j), (i-1,j-1)
-            const T e[4] = {m.e00, m.e01, m.e10, m.e11}, s[4] = {m.s00, m.s01, m.s10, m.s11},
-                    l[4] = {m.l00, m.l01, m.l10, m.l11};
-            cz = edge_coef(e, s, l, dt, theta, hdt);
-        }
-        pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
-        ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
-        pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
     };
     const int km0 = (k0 == 0) ? nz - 1 : k0 - 1;
     T hx_km, hy_km;
     {
         const long long b = (long long)km0 * sxy;
-        const Maps m = load_maps(km0);
-        pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
-        ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
-        pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
+        if constexpr (!CLS) {
+            const Maps m = load_maps(km0);
+            pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
+            ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
+            pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
+        }
         hx_km = ldp(a.H[0] + b, o00);
         hy_km = ldp(a.H[1] + b, o00);
     }
@@ -191,7 +203,7 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const
         const T hy_xm = ldp(Hy, o10), hx_ym = ldp(Hx, o01);
         const T ex = ldp(Ex, o00), ey = ldp(Ey, o00), ez = ldp(Ez, o00);
         // materials of the next plane (the last iteration re-reads its own plane and discards them)
-        const Maps mn = load_maps(k + 1 < nz ? k + 1 : k);
+        const auto mn = load_maps(k + 1 < nz ? k + 1 : k);
 
         T dyHz = (hz - hz_ym) * rdy, dzHy = (hy - hy_km) * rdz;  // Ex
         T dzHx = (hx - hx_km) * rdz, dxHz = (hz - hz_xm) * rdx;  // Ey
@@ -245,7 +257,7 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const
 // lane's own value from the previous plane.  Per cell the sweep reads E, H, the
 // maps and Js and writes E, H and Js once: 15 + 6 f_J words instead of the
 // 21 + 6 f_J of the two passes.
-template <typename T, int TY, int TZ>
+template <typename T, int TY, int TZ, bool CLS>
 __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void fused_step_kernel(const StepArgs<T> a)
 {
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
@@ -267,32 +279,46 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void fused_step_kernel(c
     struct Maps {
         T e00, e10, e01, e11, s00, s10, s01, s11, l00, l10, l01, l11;
     };
+    struct Classes {
+        uint32_t x, y, z;
+    };
+    const uint32_t oc = uint32_t(j * nx + i) * 2u;  // byte offset into a class plane
     auto load_maps = [&](int kk) {
         const long long b = opaque_offset((long long)kk * sxy);
-        const T *me = a.eps + b, *ms = a.sig + b, *ml = a.ell + b;
-        return Maps{ldp(me, o00), ldp(me, o10), ldp(me, o01), ldp(me, o11),
-                    ldp(ms, o00), ldp(ms, o10), ldp(ms, o01), ldp(ms, o11),
-                    ldp(ml, o00), ldp(ml, o10), ldp(ml, o01), ldp(ml, o11)};
+        if constexpr (CLS) {
+            return Classes{ldp(a.cls[0] + b, oc), ldp(a.cls[1] + b, oc), ldp(a.cls[2] + b, oc)};
+        } else {
+            const T *me = a.eps + b, *ms = a.sig + b, *ml = a.ell + b;
+            return Maps{ldp(me, o00), ldp(me, o10), ldp(me, o01), ldp(me, o11),
+                        ldp(ms, o00), ldp(ms, o10), ldp(ms, o01), ldp(ms, o11),
+                        ldp(ml, o00), ldp(ml, o10), ldp(ml, o01), ldp(ml, o11)};
+        }
     };
-    auto coefs = [&](const Maps &m) {
-        {   // Ex: cells (j,k), (j,k-1), (j-1,k), (j-1,k-1)
-            const T e[4] = {m.e00, pe00, m.e01, pe01}, s[4] = {m.s00, ps00, m.s01, ps01},
-                    l[4] = {m.l00, pl00, m.l01, pl01};
-            cx = edge_coef(e, s, l, dt, theta, hdt);
+    auto coefs = [&](const auto &m) {
+        if constexpr (CLS) {
+            cx = class_coef(a.ctab, m.x);
+            cy = class_coef(a.ctab, m.y);
+            cz = class_coef(a.ctab, m.z);
+        } else {
+            {   // Ex: cells (j,k), (j,k-1), (j-1,k), (j-1,k-1)
+                const T e[4] = {m.e00, pe00, m.e01, pe01}, s[4] = {m.s00, ps00, m.s01, ps01},
+                        l[4] = {m.l00, pl00, m.l01, pl01};
+                cx = edge_coef(e, s, l, dt, theta, hdt);
+            }
+            {   // Ey: cells (k,i), (k,i-1), (k-1,i), (k-1,i-1)
+                const T e[4] = {m.e00, m.e10, pe00, pe10}, s[4] = {m.s00, m.s10, ps00, ps10},
+                        l[4] = {m.l00, m.l10, pl00, pl10};
+                cy = edge_coef(e, s, l, dt, theta, hdt);
+            }
+            {   // Ez: cells (i,j), (i,j-1), (i-1,j), (i-1,j-1)
+                const T e[4] = {m.e00, m.e01, m.e10, m.e11}, s[4] = {m.s00, m.s01, m.s10, m.s11},
+                        l[4] = {m.l00, m.l01, m.l10, m.l11};
+                cz = edge_coef(e, s, l, dt, theta, hdt);
+            }
+            pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
+            ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
+            pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
         }
-        {   // Ey: cells (k,i), (k,i-1), (k-1,i), (k-1,i-1)
-            const T e[4] = {m.e00, m.e10, pe00, pe10}, s[4] = {m.s00, m.s10, ps00, ps10},
-                    l[4] = {m.l00, m.l10, pl00, pl10};
-            cy = edge_coef(e, s, l, dt, theta, hdt);
-        }
-        {   // Ez: cells (i,j), (i,j-1), (i-1,j), (i-1,j-1)
-            const T e[4] = {m.e00, m.e01, m.e10, m.e11}, s[4] = {m.s00, m.s01, m.s10, m.s11},
-                    l[4] = {m.l00, m.l01, m.l10, m.l11};
-            cz = edge_coef(e, s, l, dt, theta, hdt);
-        }
-        pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
-        ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
-        pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
     };
     // H^{n+1/2} (Hx, Hy) at plane k0-1 of the lane's own faces, and E^n of plane k0 that the
     // loop carries from one plane to the next: Ex at (i,j), (i-1,j); Ey at (i,j), (i,j-1)
@@ -308,10 +334,12 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void fused_step_kernel(c
         const T dzEx = (exk1 - exk) * rdz, dxEz = (ez_x - ez) * rdx;
         hx_km = ldp(a.H[0] + bm, o00) - hdt * (dyEz - dzEy);
         hy_km = ldp(a.H[1] + bm, o00) - hdt * (dzEx - dxEz);
-        const Maps m = load_maps(km0);
-        pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
-        ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
-        pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
+        if constexpr (!CLS) {
+            const Maps m = load_maps(km0);
+            pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
+            ps00 = m.s00; ps10 = m.s10; ps01 = m.s01;
+            pl00 = m.l00; pl10 = m.l10; pl01 = m.l01;
+        }
         ex0 = exk1;
         ey0 = eyk1;
         exm = ldp(a.E[0] + b, o10);
@@ -339,7 +367,7 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void fused_step_kernel(c
         // H^{n-1/2}: own faces, Hz and Hy at x-1, Hz and Hx at y-1
         const T hx = ldp(Hx, o00), hy = ldp(Hy, o00), hz = ldp(Hz, o00);
         const T hz_xm = ldp(Hz, o10), hy_xm = ldp(Hy, o10), hz_ym = ldp(Hz, o01), hx_ym = ldp(Hx, o01);
-        const Maps mn = load_maps(k + 1 < nz ? k + 1 : k);
+        const auto mn = load_maps(k + 1 < nz ? k + 1 : k);
 
         // H^{n+1/2} with the H pass's arithmetic
         const T nhx = hx - hdt * ((ez_yp - ez) * rdy - (ey1 - ey0) * rdz);
@@ -683,6 +711,29 @@ __global__ __launch_bounds__(kRedThreads) void map_stats_fold_kernel(double *par
         for (int q = 0; q < 5; ++q) part[q] = r[q];
 }
 
+// One entry of the class table per thread: the coefficients of the edge whose four cells hold the cell
+// materials named by tuple[c] (16 bits each, in the order the sweeps pass them to edge_coef).
+template <typename T>
+__global__ void class_table_kernel(const StepArgs<T> a, const T *mat, const uint64_t *tuple, int ncls, T *tab)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncls) return;
+    const uint64_t t = tuple[c];
+    T e[4], s[4], l[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t m = uint32_t(t >> (16 * q)) & 0xffffu;
+        e[q] = mat[3 * m];
+        s[q] = mat[3 * m + 1];
+        l[q] = mat[3 * m + 2];
+    }
+    const EdgeCoef<T> r = edge_coef(e, s, l, a.dt, a.theta, a.hdt);
+    tab[4 * c] = r.ca;
+    tab[4 * c + 1] = r.cb;
+    tab[4 * c + 2] = r.cj;
+    tab[4 * c + 3] = T(0);
+}
+
 __global__ void fill_zero_kernel(uint32_t *p, size_t nwords)
 {
     for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += (size_t)gridDim.x * blockDim.x)
@@ -725,6 +776,28 @@ struct FwdTiles<float> {
         }                                                                                                      \
     } while (0)
 
+// The same for K<T, TY, TZ, CLS>, with the edge-class variant when classes are bound.
+#define TFL_LAUNCH_TZ_CLS(K, T, TY, TZ, a, s)                                                                    \
+    do {                                                                                                       \
+        const dim3 blk(kTileX, TY);                                                                            \
+        const dim3 grd(tile_blocks((a).g, TY, TZ));                                                            \
+        if ((a).cls[0]) {                                                                                      \
+            switch (TZ) {                                                                                      \
+            case 64: hipLaunchKernelGGL((K<T, TY, 64, true>), grd, blk, 0, s, a); break;                       \
+            case 32: hipLaunchKernelGGL((K<T, TY, 32, true>), grd, blk, 0, s, a); break;                       \
+            case 16: hipLaunchKernelGGL((K<T, TY, 16, true>), grd, blk, 0, s, a); break;                       \
+            default: hipLaunchKernelGGL((K<T, TY, 8, true>), grd, blk, 0, s, a); break;                        \
+            }                                                                                                  \
+        } else {                                                                                               \
+            switch (TZ) {                                                                                      \
+            case 64: hipLaunchKernelGGL((K<T, TY, 64, false>), grd, blk, 0, s, a); break;                      \
+            case 32: hipLaunchKernelGGL((K<T, TY, 32, false>), grd, blk, 0, s, a); break;                      \
+            case 16: hipLaunchKernelGGL((K<T, TY, 16, false>), grd, blk, 0, s, a); break;                      \
+            default: hipLaunchKernelGGL((K<T, TY, 8, false>), grd, blk, 0, s, a); break;                       \
+            }                                                                                                  \
+        }                                                                                                      \
+    } while (0)
+
 template <typename T>
 hipError_t launch_h_pass(const StepArgs<T> &a, hipStream_t s)
 {
@@ -739,7 +812,7 @@ hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t s)
 {
     using C = FwdTiles<T>;
     const int tz = pick_tile_z(a.g, C::ey, C::e_waves, C::ez_max);
-    TFL_LAUNCH_TZ(e_pass_kernel, T, C::ey, tz, a, s);
+    TFL_LAUNCH_TZ_CLS(e_pass_kernel, T, C::ey, tz, a, s);
     return hipGetLastError();
 }
 
@@ -748,7 +821,7 @@ hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s)
 {
     using C = FwdTiles<T>;
     const int tz = pick_tile_z(a.g, C::fy, C::f_waves, C::fz_max);
-    TFL_LAUNCH_TZ(fused_step_kernel, T, C::fy, tz, a, s);
+    TFL_LAUNCH_TZ_CLS(fused_step_kernel, T, C::fy, tz, a, s);
     return hipGetLastError();
 }
 
@@ -787,6 +860,15 @@ hipError_t launch_half_kick(const StepArgs<T> &a, T sgn, T *const Hout[3], T *co
 }
 
 template <typename T>
+hipError_t launch_class_table(const StepArgs<T> &a, const T *mat, const uint64_t *tuple, int ncls, T *tab,
+                              hipStream_t s)
+{
+    if (ncls <= 0) return hipSuccess;
+    hipLaunchKernelGGL(class_table_kernel<T>, dim3((ncls + 255) / 256), dim3(256), 0, s, a, mat, tuple, ncls, tab);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_energy(const StepArgs<T> &a, double *scratch, int nblocks, hipStream_t s)
 {
     hipLaunchKernelGGL(energy_kernel<T>, dim3(nblocks), dim3(kRedThreads), 0, s, a, scratch);
@@ -821,6 +903,8 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
     template hipError_t launch_h_pass<T>(const StepArgs<T> &, hipStream_t);                                 \
     template hipError_t launch_e_pass<T>(const StepArgs<T> &, hipStream_t);                                 \
     template hipError_t launch_fused_step<T>(const StepArgs<T> &, hipStream_t);                             \
+    template hipError_t launch_class_table<T>(const StepArgs<T> &, const T *, const uint64_t *, int, T *,     \
+                                              hipStream_t);                                                 \
     template hipError_t launch_sources<T>(const SrcArgs<T> &, hipStream_t);                                 \
     template hipError_t launch_probes<T>(const ProbeArgs<T> &, int, hipStream_t);                           \
     template hipError_t launch_half_kick<T>(const StepArgs<T> &, T, T *const[3], T *const[3], hipStream_t); \

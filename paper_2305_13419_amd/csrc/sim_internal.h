@@ -20,6 +20,8 @@ struct tfl_sim {
     void *work = nullptr;
     double *scratch = nullptr;
     void *fused = nullptr;  // second E, H set of the fused sweep (caller-owned), or null
+    void *cls = nullptr;    // edge classes and their table (caller-owned), or null: the maps path
+    int ncls = 0;
     bool state_bound = false, work_bound = false, maps_bound = false;
     size_t work_bytes = 0;
     // workspace layout (element offsets in units of the field type)
@@ -56,6 +58,8 @@ template <typename T> int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hi
 int copy_state(tfl_sim *s, void *dst, const void *src, bool save, hipStream_t st);
 // The fused sweep needs periodic boundaries on every axis.
 bool fused_eligible(const tfl_sim *s);
+// Device pointers of the bound edge classes (x, y, z) and class table; all null when none are bound.
+void class_pointers(const tfl_sim *s, const uint16_t *cls[3], const void **table);
 
 // scratch buffer layout: reduction partials, the objective DFT, probe descriptors
 constexpr size_t kScratchBytes = 1 << 17;

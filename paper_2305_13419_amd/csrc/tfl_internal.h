@@ -50,6 +50,8 @@ struct StepArgs {
     T *Hout[3];  // where the fused sweep writes H^{n+1/2} (the two-pass H pass updates H in place)
     T *J[3];
     const T *eps, *sig, *ell;  // per-cell maps
+    const uint16_t *cls[3];    // edge classes (x, y, z edges), or null: form coefficients from the maps
+    const T *ctab;             // class table: 4 values (ca, cb, cj, 0) per class
     T rd[3];                   // 1/dx, 1/dy, 1/dz
     T hdt;                     // dt / mu0
     T dt;
@@ -109,7 +111,10 @@ struct AdjArgs {
     T *lpsiH[3][2], *lpsiE[3][2];
     double *gL[3], *gS[3];
     const T *En[3];  // E^m: input E of the forward step m -> m+1 (A part)
-    const T *Ep[3];  // E^{m+1} before the sources (A part)
+    const T *Ep[3];  // E^{m+1} after the sources: the sweep takes them out again (A part)
+    int nsrc;        // soft sources of the step: component and box (comp, i0, i1, j0, j1, k0, k1) and
+    int sbox[TFL_MAX_SOURCES][7];  // the value they added, subtracted from Ep in source order
+    double sg[TFL_MAX_SOURCES];
     int doC, doA;
     int obj;         // add og to lE[ocomp] on the objective box
     int ocomp, ob[6];
@@ -139,6 +144,11 @@ template <typename T> hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t
 // One whole step in one sweep on grids without CPML: reads E^n (E) and H^{n-1/2} (H), writes
 // E^{n+1} (Eout) and H^{n+1/2} (Hout); Js in place.  E, Eout and H, Hout must not overlap.
 template <typename T> hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s);
+// Class table of the edge-coefficient path: entry c = coefficients of the four cells
+// mat[(tuple[c] >> 16 q) & 0xffff], q = 0..3 (mat: eps_r, sigma, ell per cell material).
+template <typename T>
+hipError_t launch_class_table(const StepArgs<T> &a, const T *mat, const uint64_t *tuple, int ncls, T *tab,
+                              hipStream_t s);
 template <typename T> hipError_t launch_sources(const SrcArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_probes(const ProbeArgs<T> &a, int nprobe, hipStream_t s);
 // Integer-time half kick: Hout = Hin + sgn dt/(2 mu0) curlE (stretched, with

@@ -33,7 +33,8 @@ class Simulation:
     """
 
     def __init__(self, shape, spacing, dt, theta=1.0, dtype=torch.float64, pml=(None, None, None),
-                 pml_order=3.0, pml_scale=1.0, kappa_max=1.0, alpha_max=0.0, device="cuda", fused=True):
+                 pml_order=3.0, pml_scale=1.0, kappa_max=1.0, alpha_max=0.0, device="cuda", fused=True,
+                 edge_classes=True):
         if dtype not in _DT:
             raise ValueError("dtype must be torch.float64 or torch.float32")
         self.nx, self.ny, self.nz = (int(v) for v in shape)
@@ -82,6 +83,11 @@ class Simulation:
             self.fused_buffer = torch.empty(fb.value, dtype=torch.uint8, device=self.device)
             self._call("tfl_bind_fused_buffer", ctypes.c_void_p(self.fused_buffer.data_ptr()))
         self.maps = None
+        # per-edge coefficient classes for the forward sweeps, built by set_materials when the grid
+        # holds few distinct materials (edge_classes=False keeps the per-cell maps path)
+        self.use_edge_classes = bool(edge_classes)
+        self.class_buffer = None
+        self.edge_classes = 0
         self._probes = []
         self._sources = []
 
@@ -111,8 +117,29 @@ class Simulation:
     def set_materials(self, eps_r, sigma, inv_lambda2):
         """Per-cell eps_r, sigma_n (S/m) and 1/lambda_L^2 (m^-2); validated and dt-checked on the device."""
         maps = [self._dev(m) for m in (eps_r, sigma, inv_lambda2)]
+        self.edge_classes = 0
         self._call("tfl_bind_materials", *[ctypes.c_void_p(m.data_ptr()) for m in maps], _stream())
         self.maps = maps
+        if self.use_edge_classes:
+            self._bind_edge_classes()
+
+    def _bind_edge_classes(self):
+        """Edge-coefficient classes of the bound maps (tfl_bind_edge_classes); stays on the maps path
+        when the grid has more distinct materials than the class table holds."""
+        if self.class_buffer is None:
+            nb = ctypes.c_size_t()
+            self._call("tfl_edge_class_bytes", ctypes.byref(nb))
+            self.class_buffer = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        n = ctypes.c_int()
+        try:
+            self._call("tfl_bind_edge_classes", ctypes.c_void_p(self.class_buffer.data_ptr()), ctypes.byref(n),
+                       _stream())
+        except L.TflError as err:
+            if err.code != L.TFL_E_RANGE:
+                raise
+            self.class_buffer = None
+            n.value = 0
+        self.edge_classes = n.value
 
     def set_fields(self, E, H, J=None):
         """Integer-time fields at t = 0 (E^0, H^0, Js^0); converted to the staggered state."""
