@@ -50,6 +50,17 @@ static __device__ __forceinline__ void stp(T *base, uint32_t off, T v)
     *(__attribute__((address_space(1))) T *)(reinterpret_cast<char *>(base) + off) = v;
 }
 
+// stp with a nontemporal hint when NT (the line is not kept in L2 / the infinity cache)
+template <bool NT, typename T>
+static __device__ __forceinline__ void stp_hint(T *base, uint32_t off, T v)
+{
+    auto *p = (__attribute__((address_space(1))) T *)(reinterpret_cast<char *>(base) + off);
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 static __device__ __forceinline__ int slab_slot(int i, int lo, int hi, int n)
 {
     if (i < lo) return i;
