@@ -160,6 +160,7 @@ def large_run(steps=8192, seg=512, seg2=32, fd_steps=512, fd_cells=4):
     t0 = time.perf_counter()
     F = sim.forward_checkpointed(obj, steps, seg, ckpt)
     t1 = time.perf_counter()
+    print(f"# large FP32: forward {t1 - t0:.1f} s; adjoint", file=sys.stderr, flush=True)
     gl, gs = sim.adjoint_nested(obj, steps, seg, seg2, ckpt, F, ckpt2, snap, work)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
