@@ -14,21 +14,21 @@ static __device__ __forceinline__ int logical_block(int b, int nblocks)
     return x * q + min(x, r) + m;
 }
 
-// Column tile of a z-marching sweep: kTileX x TY columns of the x-y plane and
-// TZ planes along z.  Tiles are numbered x fastest, then y, then z, and blocks
-// are renumbered so that each XCD takes a contiguous range: the blocks of one
-// XCD sweep neighbouring columns of the same planes at the same time.
-// Returns false for lanes outside the grid.
-template <int TY, int TZ>
+// Column tile of a z-marching sweep: TX x TY columns of the x-y plane (TX / 64
+// wavefronts per row) and TZ planes along z.  Tiles are numbered x fastest,
+// then y, then z, and blocks are renumbered so that each XCD takes a contiguous
+// range: the blocks of one XCD sweep neighbouring columns of the same planes at
+// the same time.  Returns false for lanes outside the grid.
+template <int TY, int TZ, int TX = kTileX>
 static __device__ __forceinline__ bool tile_of(int nx, int ny, int nz, int &i, int &j, int &k0, int &k1)
 {
-    const int ntx = (nx + kTileX - 1) / kTileX, nty = (ny + TY - 1) / TY, ntz = (nz + TZ - 1) / TZ;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, ntz = (nz + TZ - 1) / TZ;
     const int t = logical_block(blockIdx.x, ntx * nty * ntz);
     const int tx = t % ntx;
     const int tr = t / ntx;
     const int ty = tr % nty;
     const int tz = tr / nty;
-    i = tx * kTileX + threadIdx.x;
+    i = tx * TX + threadIdx.x;
     j = ty * TY + threadIdx.y;
     k0 = tz * TZ;
     k1 = min(k0 + TZ, nz);

@@ -259,12 +259,12 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const
 // 21 + 6 f_J of the two passes.  NT: the new E and H are stored with a
 // nontemporal hint (chosen at launch for grids well beyond the infinity cache,
 // where keeping them would only evict lines the sweep still reads).
-template <typename T, int TY, int TZ, bool CLS, bool NT>
-__global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void fused_step_kernel(const StepArgs<T> a)
+template <typename T, int TY, int TZ, bool CLS, bool NT, int TX>
+__global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const StepArgs<T> a)
 {
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     int i, j, k0, k1;
-    if (!tile_of<TY, TZ>(nx, ny, nz, i, j, k0, k1)) return;
+    if (!tile_of<TY, TZ, TX>(nx, ny, nz, i, j, k0, k1)) return;
     const long long sxy = a.g.sxy;
     const int im = (i == 0) ? nx - 1 : i - 1, ip = (i + 1 == nx) ? 0 : i + 1;
     const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j + 1 == ny) ? 0 : j + 1;
@@ -778,25 +778,24 @@ struct FwdTiles<float> {
         }                                                                                                      \
     } while (0)
 
-// The same for K<T, TY, TZ, CLS, ...>, with the edge-class variant when classes are bound; trailing
-// arguments are further template arguments of K.
-#define TFL_LAUNCH_TZ_CLS(K, T, TY, TZ, a, s, ...)                                                               \
+// The same for K<T, TY, TZ, CLS>, with the edge-class variant when classes are bound.
+#define TFL_LAUNCH_TZ_CLS(K, T, TY, TZ, a, s)                                                                    \
     do {                                                                                                       \
         const dim3 blk(kTileX, TY);                                                                            \
         const dim3 grd(tile_blocks((a).g, TY, TZ));                                                            \
         if ((a).cls[0]) {                                                                                      \
             switch (TZ) {                                                                                      \
-            case 64: hipLaunchKernelGGL((K<T, TY, 64, true __VA_OPT__(, ) __VA_ARGS__>), grd, blk, 0, s, a); break; \
-            case 32: hipLaunchKernelGGL((K<T, TY, 32, true __VA_OPT__(, ) __VA_ARGS__>), grd, blk, 0, s, a); break; \
-            case 16: hipLaunchKernelGGL((K<T, TY, 16, true __VA_OPT__(, ) __VA_ARGS__>), grd, blk, 0, s, a); break; \
-            default: hipLaunchKernelGGL((K<T, TY, 8, true __VA_OPT__(, ) __VA_ARGS__>), grd, blk, 0, s, a); break;  \
+            case 64: hipLaunchKernelGGL((K<T, TY, 64, true>), grd, blk, 0, s, a); break;                       \
+            case 32: hipLaunchKernelGGL((K<T, TY, 32, true>), grd, blk, 0, s, a); break;                       \
+            case 16: hipLaunchKernelGGL((K<T, TY, 16, true>), grd, blk, 0, s, a); break;                       \
+            default: hipLaunchKernelGGL((K<T, TY, 8, true>), grd, blk, 0, s, a); break;                        \
             }                                                                                                  \
         } else {                                                                                               \
             switch (TZ) {                                                                                      \
-            case 64: hipLaunchKernelGGL((K<T, TY, 64, false __VA_OPT__(, ) __VA_ARGS__>), grd, blk, 0, s, a); break; \
-            case 32: hipLaunchKernelGGL((K<T, TY, 32, false __VA_OPT__(, ) __VA_ARGS__>), grd, blk, 0, s, a); break; \
-            case 16: hipLaunchKernelGGL((K<T, TY, 16, false __VA_OPT__(, ) __VA_ARGS__>), grd, blk, 0, s, a); break; \
-            default: hipLaunchKernelGGL((K<T, TY, 8, false __VA_OPT__(, ) __VA_ARGS__>), grd, blk, 0, s, a); break;  \
+            case 64: hipLaunchKernelGGL((K<T, TY, 64, false>), grd, blk, 0, s, a); break;                      \
+            case 32: hipLaunchKernelGGL((K<T, TY, 32, false>), grd, blk, 0, s, a); break;                      \
+            case 16: hipLaunchKernelGGL((K<T, TY, 16, false>), grd, blk, 0, s, a); break;                      \
+            default: hipLaunchKernelGGL((K<T, TY, 8, false>), grd, blk, 0, s, a); break;                       \
             }                                                                                                  \
         }                                                                                                      \
     } while (0)
@@ -819,19 +818,50 @@ hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T, int TX, int TY, bool NT>
+static void launch_fused_tx(const StepArgs<T> &a, long long waves, int max_tz, hipStream_t s)
+{
+    const int tz = pick_tile_z(a.g, TY, waves, max_tz, TX);
+    const dim3 blk(TX, TY), grd(tile_blocks(a.g, TY, tz, TX));
+    if (a.cls[0]) {
+        switch (tz) {
+        case 64: hipLaunchKernelGGL((fused_step_kernel<T, TY, 64, true, NT, TX>), grd, blk, 0, s, a); break;
+        case 32: hipLaunchKernelGGL((fused_step_kernel<T, TY, 32, true, NT, TX>), grd, blk, 0, s, a); break;
+        case 16: hipLaunchKernelGGL((fused_step_kernel<T, TY, 16, true, NT, TX>), grd, blk, 0, s, a); break;
+        default: hipLaunchKernelGGL((fused_step_kernel<T, TY, 8, true, NT, TX>), grd, blk, 0, s, a); break;
+        }
+    } else {
+        switch (tz) {
+        case 64: hipLaunchKernelGGL((fused_step_kernel<T, TY, 64, false, NT, TX>), grd, blk, 0, s, a); break;
+        case 32: hipLaunchKernelGGL((fused_step_kernel<T, TY, 32, false, NT, TX>), grd, blk, 0, s, a); break;
+        case 16: hipLaunchKernelGGL((fused_step_kernel<T, TY, 16, false, NT, TX>), grd, blk, 0, s, a); break;
+        default: hipLaunchKernelGGL((fused_step_kernel<T, TY, 8, false, NT, TX>), grd, blk, 0, s, a); break;
+        }
+    }
+}
+
 template <typename T>
 hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s)
 {
     using C = FwdTiles<T>;
-    const int tz = pick_tile_z(a.g, C::fy, C::f_waves, C::fz_max);
     // bytes one step touches (E, H read and written, Js, coefficients): beyond twice the 256 MiB
     // infinity cache the new fields gain from bypassing it (256^3: 6-8 % faster); below, the next
     // step finds them there (128^3 runs 1.5x faster with ordinary stores)
     const double touched = (double)a.g.sxy * a.g.nz * (15.0 * sizeof(T) + 6.0);
-    if (touched > 512.0 * 1024 * 1024)
-        TFL_LAUNCH_TZ_CLS(fused_step_kernel, T, C::fy, tz, a, s, true);
-    else
-        TFL_LAUNCH_TZ_CLS(fused_step_kernel, T, C::fy, tz, a, s, false);
+    const bool nt = touched > 512.0 * 1024 * 1024;
+    // FP32: rows of 256 (or 128) cells per block when they tile the x extent exactly (4 or 2
+    // wavefronts per row, no x halo between them; 256^3: 282 -> 267 us); FP64 gains nothing from it
+    const int tx = (sizeof(T) == 4 && a.g.nx % 256 == 0) ? 256 : (sizeof(T) == 4 && a.g.nx % 128 == 0) ? 128 : 64;
+    if (tx == 256) {
+        if (nt) launch_fused_tx<T, 256, 2, true>(a, C::f_waves, C::fz_max, s);
+        else launch_fused_tx<T, 256, 2, false>(a, C::f_waves, C::fz_max, s);
+    } else if (tx == 128) {
+        if (nt) launch_fused_tx<T, 128, 2, true>(a, C::f_waves, C::fz_max, s);
+        else launch_fused_tx<T, 128, 2, false>(a, C::f_waves, C::fz_max, s);
+    } else {
+        if (nt) launch_fused_tx<T, 64, C::fy, true>(a, C::f_waves, C::fz_max, s);
+        else launch_fused_tx<T, 64, C::fy, false>(a, C::f_waves, C::fz_max, s);
+    }
     return hipGetLastError();
 }
 

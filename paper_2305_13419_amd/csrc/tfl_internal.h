@@ -125,17 +125,17 @@ struct AdjArgs {
 // longest of max_tz, ..., 16, 8 planes whose tiles still give at least
 // target_waves wavefronts (longer runs re-read fewer halo planes; enough waves
 // are needed to cover the HBM latency on small grids).
-inline int pick_tile_z(const GridDims &g, int ty, long long target_waves, int max_tz)
+inline int pick_tile_z(const GridDims &g, int ty, long long target_waves, int max_tz, int tx = kTileX)
 {
-    const long long cols = (long long)((g.nx + kTileX - 1) / kTileX) * ((g.ny + ty - 1) / ty);
+    const long long cols = (long long)((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
     int tz = max_tz;
-    while (tz > 8 && cols * ((g.nz + tz - 1) / tz) * ty < target_waves) tz /= 2;
+    while (tz > 8 && cols * ((g.nz + tz - 1) / tz) * ty * (tx / kTileX) < target_waves) tz /= 2;
     return tz;
 }
 
-inline int tile_blocks(const GridDims &g, int ty, int tz)
+inline int tile_blocks(const GridDims &g, int ty, int tz, int tx = kTileX)
 {
-    return (int)(((g.nx + kTileX - 1) / kTileX) * ((g.ny + ty - 1) / ty) * ((g.nz + tz - 1) / tz));
+    return (int)(((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty) * ((g.nz + tz - 1) / tz));
 }
 
 // Host-side launchers (kernels_fwd.hip).

@@ -42,3 +42,31 @@ def test_fused_equals_two_pass(dtype, steps, chunks):
     print(f"  max relative difference {worst:.3e}", flush=True)
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+
+
+def run_plain(wl, steps, dtype, fused):
+    from paper_2305_13419_amd import Simulation
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"], fused=fused)
+    assert (sim.fused_buffer is not None) == fused
+    sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
+    E, H, _ = wl["fields"]
+    sim.set_fields([np.asarray(a, dtype=npdt) for a in E], [np.asarray(a, dtype=npdt) for a in H])
+    sim.step(steps)
+    torch.cuda.synchronize()
+    out = [t.clone() for t in sim.E + sim.H + sim.J]
+    sim.close()
+    return out
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", [(256, 9, 12), (128, 10, 9), (256, 256, 256)])
+def test_fused_row_tiles_and_large_grids_equal_two_pass(shape, dtype):
+    """FP32 rows of 256 or 128 cells per block when they tile the x extent, and the nontemporal
+    stores of grids past the infinity cache (256^3), against the two passes bit for bit."""
+    wl = workloads.roofline_grid(shape)
+    print(f"case: fused vs two-pass, roofline boxes {shape}, {dtype}, 3 steps", flush=True)
+    a = run_plain(wl, 3, dtype, True)
+    b = run_plain(wl, 3, dtype, False)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
