@@ -12,10 +12,11 @@
 // reads the old fields from one set of buffers and writes the new ones to
 // another.
 //
-// Each block owns a column tile of the x-y plane (one 64-wide wavefront per
-// row, 4 or 8 rows) and marches 8-64 planes along z (chosen at launch from the
-// grid size), so the z neighbour of every stencil comes from registers; x and
-// y neighbours come from L1/L2.  Blocks are renumbered so that each XCD
+// Each block owns a column tile of the x-y plane (rows of 64 cells, one
+// wavefront each, 4 or 8 rows; the FP32 fused sweep takes rows of 256 or 128
+// cells when they divide nx) and marches 8-64 planes along z (chosen at launch
+// from the grid size), so the z neighbour of every stencil comes from
+// registers; x and y neighbours come from L1/L2.  Blocks are renumbered so that each XCD
 // (blocks are dealt to the 8 XCDs round robin) receives a contiguous range of
 // tiles, keeping the halo rows of neighbouring tiles in the same L2.
 #include "fdtd_common.h"
