@@ -7,7 +7,9 @@
 //             E^{n+1} = a_e E^n + b_e (curl H^{n+1/2} - Js^{n+1/2})     (Ampere, theta scheme)
 // with a_e = (eps_e - (1-theta) sigma_e dt)/(eps_e + theta sigma_e dt) and
 // b_e = dt/(eps_e + theta sigma_e dt), i.e. Algorithm 1 step 3 multiplied out.
-// Per-edge materials are formed on the fly from the per-cell maps.  On grids
+// Per-edge materials are formed on the fly from the per-cell maps, or read as
+// one 16-bit class per edge and a coefficient table when classes are bound
+// (the CLS template argument).  On grids
 // without CPML the two sweeps can be replaced by one (fused_step_kernel), which
 // reads the old fields from one set of buffers and writes the new ones to
 // another.
@@ -257,7 +259,8 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const
 // buffers), with the same arithmetic as the H pass.  H^{n+1/2} at z-1 is the
 // lane's own value from the previous plane.  Per cell the sweep reads E, H, the
 // maps and Js and writes E, H and Js once: 15 + 6 f_J words instead of the
-// 21 + 6 f_J of the two passes.  NT: the new E and H are stored with a
+// 21 + 6 f_J of the two passes (12 + 6 f_J words and three 16-bit classes with
+// edge classes).  NT: the new E and H are stored with a
 // nontemporal hint (chosen at launch for grids well beyond the infinity cache,
 // where keeping them would only evict lines the sweep still reads).
 template <typename T, int TY, int TZ, bool CLS, bool NT, int TX>
