@@ -153,3 +153,24 @@ def test_fused_buffer_only_on_periodic_grids(L):
     assert L.lib().tfl_bind_fused_buffer(h, ctypes.c_void_p(0x1000)) == L.TFL_E_INVAL
     assert b"periodic" in L.lib().tfl_last_error(h)
     L.lib().tfl_destroy(h)
+
+
+def test_edge_class_buffer_size_and_call_order(L):
+    """Class buffer: three padded uint16 arrays, the table of TFL_MAX_EDGE_CLASSES four-value
+    entries and the staging area (65536 cell materials of three values, one uint64 tuple per
+    class); binding needs bound maps and an aligned buffer; NULL unbinds."""
+    c = good_config(L)
+    rc, h = create(L, c)
+    assert rc == 0
+    b = ctypes.c_size_t()
+    assert L.lib().tfl_edge_class_bytes(h, ctypes.byref(b)) == 0
+    r256 = lambda n: (n + 255) // 256 * 256  # noqa: E731
+    n = 20 * 10 * 8
+    assert b.value == (3 * r256(2 * n) + r256(L.TFL_MAX_EDGE_CLASSES * 4 * 8) + r256(65536 * 3 * 8)
+                       + r256(L.TFL_MAX_EDGE_CLASSES * 8))
+    k = ctypes.c_int(-1)
+    assert L.lib().tfl_bind_edge_classes(h, ctypes.c_void_p(0x1001), ctypes.byref(k), None) == L.TFL_E_INVAL
+    assert L.lib().tfl_bind_edge_classes(h, ctypes.c_void_p(0x1000), ctypes.byref(k), None) == L.TFL_E_STATE
+    assert b"materials not bound" in L.lib().tfl_last_error(h)
+    assert L.lib().tfl_bind_edge_classes(h, None, ctypes.byref(k), None) == 0 and k.value == 0
+    L.lib().tfl_destroy(h)
