@@ -82,6 +82,27 @@ def run_gpu(wl, dtype, steps, warmup, fused=True, classes=True):
                 nonfinite=int(bad), energy=W, edge_classes=ncls, bind_materials_s=bind_s)
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Bandwidth of the runtime's device-to-device copy (torch copy_ of `nbytes`, read + write bytes per
+    second, GB/s), timed with events around `reps` copies: a reference rate on this GPU."""
+    import torch
+
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def measured_traffic(dtype_name, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when the
     kernel source changed after the counters were taken."""
@@ -419,6 +440,7 @@ def main():
             print(f"# {name} {mode}: {args.warmup} warm-up + {args.steps} timed steps on {wl['name']}",
                   file=sys.stderr, flush=True)
             res[name, mode] = run_gpu(wl, dt, args.steps, args.warmup, fused, classes)
+    copy_gbs = copy_bandwidth()
     out = {}
     for name, w in (("f64", 8), ("f32", 4)):
         # per cell: E, H read and written (fused) or E read and written, H read (E pass); Js read and
@@ -431,9 +453,14 @@ def main():
 
         def roof(kernel, ms, cell, traffic_key):
             gbs = cell * ncell / (ms * 1e-3) / 1e9
+            traffic = measured_traffic(name, traffic_key)
             return dict(bound="hbm", kernel=kernel, achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=gbs / HBM_PEAK_GBS, traffic=measured_traffic(name, traffic_key), bytes_per_cell=cell,
-                        algorithmic_bytes_per_launch=cell * ncell)
+                        frac=gbs / HBM_PEAK_GBS, traffic=traffic, bytes_per_cell=cell,
+                        algorithmic_bytes_per_launch=cell * ncell,
+                        # measured HBM bytes per launch over the launch time, and the algorithmic rate
+                        # against the runtime's device-to-device copy on this GPU
+                        traffic_GBs=None if traffic is None else traffic / (ms * 1e-3) / 1e9,
+                        runtime_copy_GBs=copy_gbs, frac_of_runtime_copy=gbs / copy_gbs)
 
         r, m, t = res[name, "fused"], res[name, "fused_maps"], res[name, "two_pass"]
         out[name] = dict(
