@@ -22,3 +22,19 @@ def test_large_grid_first_steps_match_oracle():
         print(f"  rel-L2 vs oracle {r}", flush=True)
         assert max(r.values()) <= tol
         del g, o
+
+
+def test_roofline_grid_full_size_matches_oracle():
+    """The 256^3 roofline grid in the configuration bench.py times (fused sweep with edge classes,
+    nontemporal stores, FP32 on 256-cell rows): 4 steps against the oracle over every cell."""
+    wl = workloads.roofline_grid(256)
+    steps = 4
+    for dtype, npdt, tol in ((torch.float64, np.float64, 1e-12), (torch.float32, np.float32, 1e-5)):
+        print(f"case: {wl['name']} {steps} steps {dtype}", flush=True)
+        g = run_gpu(wl, steps, dtype)
+        torch.cuda.empty_cache()
+        o = run_oracle(wl, steps, npdt)
+        r = compare(g, o)
+        print(f"  rel-L2 vs oracle {r}", flush=True)
+        assert max(r.values()) <= tol
+        del g, o
