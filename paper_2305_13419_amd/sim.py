@@ -30,6 +30,13 @@ class Simulation:
     theta : weight of the Ohmic term (Algorithm 1 step 3), in [0.5, 1]
     dtype : torch.float64 or torch.float32 (storage and arithmetic of E, H, Js and maps)
     pml : per axis None (periodic) or (lo, hi) absorbing cells (CPML backed by a PEC wall)
+    pml_order, pml_scale, kappa_max, alpha_max : CPML grading (tfl_config)
+    device : the GPU holding every buffer
+    fused : on grids periodic on every axis, bind a second E, H set so that a step runs as one sweep
+    edge_classes : after each set_materials, replace the maps read by the E update with one 16-bit
+        class per edge and a coefficient table when the grid has few enough distinct materials
+        (the number bound is in ``edge_classes`` afterwards, 0 on the map path); results are
+        bit-identical either way
     """
 
     def __init__(self, shape, spacing, dt, theta=1.0, dtype=torch.float64, pml=(None, None, None),
