@@ -300,7 +300,7 @@ def table1_run():
     return rows
 
 
-def paper_cpw_run(steps=200, warmup=10):
+def paper_cpw_run(steps=200, warmup=10, cases=(1, 2, 3, 4)):
     """Step rate on the paper's CPW resonator at its own size (196 M cells with the CPML slabs), each
     film case, FP32 and FP64, against the paper's ~0.05 s per step on 32 A100 GPUs."""
     import numpy as np
@@ -309,7 +309,7 @@ def paper_cpw_run(steps=200, warmup=10):
     from paper_2305_13419_amd import Simulation, workloads
 
     rows = []
-    for case in (1, 2, 3, 4):
+    for case in cases:
         wl = workloads.paper_cpw_grid(case)
         for dtype, npdt in ((torch.float32, np.float32), (torch.float64, np.float64)):
             sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"])

@@ -35,6 +35,27 @@ static __device__ __forceinline__ bool tile_of(int nx, int ny, int nz, int &i, i
     return i < nx && j < ny;
 }
 
+// The same with rows of W lanes (blockDim = (64, TY)): W = 64 is tile_of; with W = 32 or 16 a
+// wavefront covers 64 / W rows of W cells and a block 64 TY / W rows, for grids whose nx would
+// leave much of a 64-lane row idle.
+template <int TY, int TZ, int W>
+static __device__ __forceinline__ bool tile_of_w(int nx, int ny, int nz, int &i, int &j, int &k0, int &k1)
+{
+    constexpr int rows = kTileX * TY / W;
+    const int ntx = (nx + W - 1) / W, nty = (ny + rows - 1) / rows, ntz = (nz + TZ - 1) / TZ;
+    const int t = logical_block(blockIdx.x, ntx * nty * ntz);
+    const int tx = t % ntx;
+    const int tr = t / ntx;
+    const int ty = tr % nty;
+    const int tz = tr / nty;
+    const int lane = threadIdx.x + kTileX * threadIdx.y;
+    i = tx * W + lane % W;
+    j = ty * rows + lane / W;
+    k0 = tz * TZ;
+    k1 = min(k0 + TZ, nz);
+    return i < nx && j < ny;
+}
+
 // Access at a wave-uniform base plus a 32-bit per-lane byte offset, through a
 // global (address space 1) pointer: the base stays in scalar registers and the
 // access takes the "SGPR base + VGPR offset" form.

@@ -29,12 +29,12 @@ namespace {
 // ---------------------------------------------------------------------------
 // H pass (Faraday's law)
 // ---------------------------------------------------------------------------
-template <typename T, int TY, int TZ>
+template <typename T, int TY, int TZ, int W>
 __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void h_pass_kernel(const StepArgs<T> a)
 {
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     int i, j, k0, k1;
-    if (!tile_of<TY, TZ>(nx, ny, nz, i, j, k0, k1)) return;
+    if (!tile_of_w<TY, TZ, W>(nx, ny, nz, i, j, k0, k1)) return;
     const long long sxy = a.g.sxy;
     const int ip = (i + 1 == nx) ? 0 : i + 1;
     const int jp = (j + 1 == ny) ? 0 : j + 1;
@@ -106,12 +106,12 @@ __device__ __forceinline__ EdgeCoef<T> edge_coef(const T e[4], const T s[4], con
     return {(eps - (T(1) - theta) * sdt) * inv, dt * inv, hdt * ell};
 }
 
-template <typename T, int TY, int TZ, bool CLS>
+template <typename T, int TY, int TZ, bool CLS, int W>
 __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const StepArgs<T> a)
 {
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     int i, j, k0, k1;
-    if (!tile_of<TY, TZ>(nx, ny, nz, i, j, k0, k1)) return;
+    if (!tile_of_w<TY, TZ, W>(nx, ny, nz, i, j, k0, k1)) return;
     const long long sxy = a.g.sxy;
     const int im = (i == 0) ? nx - 1 : i - 1;
     const int jm = (j == 0) ? ny - 1 : j - 1;
@@ -751,11 +751,13 @@ __global__ void fill_zero_kernel(uint32_t *p, size_t nwords)
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-// Tile shapes of the forward sweeps per storage type: rows of 64-wide
-// wavefronts per block, the longest z run, and the wavefronts a launch should
-// at least provide (from sweeps of shapes on MI355X: the FP64 H pass is
-// fastest with all its tiles resident in one round, the other sweeps with
-// about two rounds of waves; the fused sweep varies by < 3 % over shapes).
+// Tile shapes of the forward sweeps per storage type: wavefronts per block, the
+// longest z run, and the wavefronts a launch should at least provide (from
+// sweeps of shapes on MI355X: the FP64 H pass is fastest with all its tiles
+// resident in one round, the other sweeps with about two rounds of waves; the
+// fused sweep varies by < 3 % over shapes).  The two passes take rows of 64,
+// 32 or 16 cells (row_width); the FP32 fused sweep rows of 256 or 128 cells
+// when they divide nx.
 template <typename T>
 struct FwdTiles;
 template <>
@@ -769,56 +771,58 @@ struct FwdTiles<float> {
     static constexpr long long h_waves = 8192, e_waves = 8192, f_waves = 16384;
 };
 
-// Launch kernel template K<T, TY, TZ> with TZ in {8, 16, 32, 64} chosen at run time.
-#define TFL_LAUNCH_TZ(K, T, TY, TZ, a, s)                                                                        \
-    do {                                                                                                       \
-        const dim3 blk(kTileX, TY);                                                                            \
-        const dim3 grd(tile_blocks((a).g, TY, TZ));                                                            \
-        switch (TZ) {                                                                                          \
-        case 64: hipLaunchKernelGGL((K<T, TY, 64>), grd, blk, 0, s, a); break;                                 \
-        case 32: hipLaunchKernelGGL((K<T, TY, 32>), grd, blk, 0, s, a); break;                                 \
-        case 16: hipLaunchKernelGGL((K<T, TY, 16>), grd, blk, 0, s, a); break;                                 \
-        default: hipLaunchKernelGGL((K<T, TY, 8>), grd, blk, 0, s, a); break;                                  \
-        }                                                                                                      \
-    } while (0)
+template <typename T, int W>
+static void launch_h_pass_w(const StepArgs<T> &a, hipStream_t s)
+{
+    using C = FwdTiles<T>;
+    const int tz = pick_tile_z_w(a.g, C::hy, C::h_waves, C::hz_max, W);
+    const dim3 blk(kTileX, C::hy), grd((unsigned)(row_tiles(a.g, C::hy, W) * ((a.g.nz + tz - 1) / tz)));
+    switch (tz) {
+    case 64: hipLaunchKernelGGL((h_pass_kernel<T, C::hy, 64, W>), grd, blk, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((h_pass_kernel<T, C::hy, 32, W>), grd, blk, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((h_pass_kernel<T, C::hy, 16, W>), grd, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((h_pass_kernel<T, C::hy, 8, W>), grd, blk, 0, s, a); break;
+    }
+}
 
-// The same for K<T, TY, TZ, CLS>, with the edge-class variant when classes are bound.
-#define TFL_LAUNCH_TZ_CLS(K, T, TY, TZ, a, s)                                                                    \
-    do {                                                                                                       \
-        const dim3 blk(kTileX, TY);                                                                            \
-        const dim3 grd(tile_blocks((a).g, TY, TZ));                                                            \
-        if ((a).cls[0]) {                                                                                      \
-            switch (TZ) {                                                                                      \
-            case 64: hipLaunchKernelGGL((K<T, TY, 64, true>), grd, blk, 0, s, a); break;                       \
-            case 32: hipLaunchKernelGGL((K<T, TY, 32, true>), grd, blk, 0, s, a); break;                       \
-            case 16: hipLaunchKernelGGL((K<T, TY, 16, true>), grd, blk, 0, s, a); break;                       \
-            default: hipLaunchKernelGGL((K<T, TY, 8, true>), grd, blk, 0, s, a); break;                        \
-            }                                                                                                  \
-        } else {                                                                                               \
-            switch (TZ) {                                                                                      \
-            case 64: hipLaunchKernelGGL((K<T, TY, 64, false>), grd, blk, 0, s, a); break;                      \
-            case 32: hipLaunchKernelGGL((K<T, TY, 32, false>), grd, blk, 0, s, a); break;                      \
-            case 16: hipLaunchKernelGGL((K<T, TY, 16, false>), grd, blk, 0, s, a); break;                      \
-            default: hipLaunchKernelGGL((K<T, TY, 8, false>), grd, blk, 0, s, a); break;                       \
-            }                                                                                                  \
-        }                                                                                                      \
-    } while (0)
+template <typename T, int W, bool CLS>
+static void launch_e_pass_w(const StepArgs<T> &a, hipStream_t s)
+{
+    using C = FwdTiles<T>;
+    const int tz = pick_tile_z_w(a.g, C::ey, C::e_waves, C::ez_max, W);
+    const dim3 blk(kTileX, C::ey), grd((unsigned)(row_tiles(a.g, C::ey, W) * ((a.g.nz + tz - 1) / tz)));
+    switch (tz) {
+    case 64: hipLaunchKernelGGL((e_pass_kernel<T, C::ey, 64, CLS, W>), grd, blk, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((e_pass_kernel<T, C::ey, 32, CLS, W>), grd, blk, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((e_pass_kernel<T, C::ey, 16, CLS, W>), grd, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((e_pass_kernel<T, C::ey, 8, CLS, W>), grd, blk, 0, s, a); break;
+    }
+}
 
 template <typename T>
 hipError_t launch_h_pass(const StepArgs<T> &a, hipStream_t s)
 {
-    using C = FwdTiles<T>;
-    const int tz = pick_tile_z(a.g, C::hy, C::h_waves, C::hz_max);
-    TFL_LAUNCH_TZ(h_pass_kernel, T, C::hy, tz, a, s);
+    switch (row_width(a.g.nx, sizeof(T))) {
+    case 16: launch_h_pass_w<T, 16>(a, s); break;
+    case 32: launch_h_pass_w<T, 32>(a, s); break;
+    default: launch_h_pass_w<T, 64>(a, s); break;
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t s)
 {
-    using C = FwdTiles<T>;
-    const int tz = pick_tile_z(a.g, C::ey, C::e_waves, C::ez_max);
-    TFL_LAUNCH_TZ_CLS(e_pass_kernel, T, C::ey, tz, a, s);
+    const int w = row_width(a.g.nx, sizeof(T));
+    if (a.cls[0]) {
+        if (w == 16) launch_e_pass_w<T, 16, true>(a, s);
+        else if (w == 32) launch_e_pass_w<T, 32, true>(a, s);
+        else launch_e_pass_w<T, 64, true>(a, s);
+    } else {
+        if (w == 16) launch_e_pass_w<T, 16, false>(a, s);
+        else if (w == 32) launch_e_pass_w<T, 32, false>(a, s);
+        else launch_e_pass_w<T, 64, false>(a, s);
+    }
     return hipGetLastError();
 }
 

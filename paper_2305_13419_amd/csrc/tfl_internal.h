@@ -133,6 +133,43 @@ inline int pick_tile_z(const GridDims &g, int ty, long long target_waves, int ma
     return tz;
 }
 
+// Column tiles and z length for tiles of 64 TY / W rows of W lanes (tile_of_w).
+inline long long row_tiles(const GridDims &g, int ty, int w)
+{
+    const int rows = kTileX * ty / w;
+    return (long long)((g.nx + w - 1) / w) * ((g.ny + rows - 1) / rows);
+}
+
+inline int pick_tile_z_w(const GridDims &g, int ty, long long target_waves, int max_tz, int w)
+{
+    const long long cols = row_tiles(g, ty, w);
+    int tz = max_tz;
+    while (tz > 8 && cols * ((g.nz + tz - 1) / tz) * ty < target_waves) tz /= 2;
+    return tz;
+}
+
+// Lanes per tile row of the two passes: 64 unless a narrower row (32 or 16 lanes, at least 256 bytes
+// of the storage type: two cache lines) leaves clearly less of the row idle for this nx.  Measured on
+// the paper's CPW (nx = 146): FP64 rows of 32 cells 4 % faster than 64; FP32 rows of 32 cells
+// (128 bytes) 1 % slower.
+inline int row_width(int nx, int esz)
+{
+    auto idle = [nx](int w) {
+        const int padded = (nx + w - 1) / w * w;
+        return double(padded - nx) / padded;
+    };
+    int best = kTileX;
+    double best_idle = idle(kTileX);
+    for (int w = 32; w >= 16; w /= 2) {
+        if (w * esz < 256) break;
+        if (idle(w) + 0.02 < best_idle) {
+            best = w;
+            best_idle = idle(w);
+        }
+    }
+    return best;
+}
+
 inline int tile_blocks(const GridDims &g, int ty, int tz, int tx = kTileX)
 {
     return (int)(((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty) * ((g.nz + tz - 1) / tz));
