@@ -71,6 +71,24 @@ static __device__ __forceinline__ void stp(T *base, uint32_t off, T v)
     *(__attribute__((address_space(1))) T *)(reinterpret_cast<char *>(base) + off) = v;
 }
 
+// ldp / stp with the offset passed through an empty asm at the access: the
+// compiler can then neither hoist its 64-bit extension out of a loop nor keep a
+// 64-bit address per array and neighbour live across it (which had doubled the
+// address registers of the adjoint sweeps).
+template <typename T>
+static __device__ __forceinline__ T ldo(const T *base, uint32_t off)
+{
+    asm volatile("" : "+v"(off));
+    return ldp(base, off);
+}
+
+template <typename T>
+static __device__ __forceinline__ void sto(T *base, uint32_t off, T v)
+{
+    asm volatile("" : "+v"(off));
+    stp(base, off, v);
+}
+
 // stp with a nontemporal hint when NT (the line is not kept in L2 / the infinity cache)
 template <bool NT, typename T>
 static __device__ __forceinline__ void stp_hint(T *base, uint32_t off, T v)

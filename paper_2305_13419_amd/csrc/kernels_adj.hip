@@ -21,54 +21,29 @@
 namespace tfl {
 namespace {
 
-// curl term signs: component c differentiated along axis a enters with +1 when
-// a = c+1 (mod 3) and -1 when a = c+2 (mod 3), for both curls.
-__device__ __forceinline__ int curl_sign(int c, int a) { return ((c + 1) % 3 == a) ? 1 : -1; }
-// compact PML array of axis a that holds component c
-__device__ __forceinline__ int psi_slot(int c, int a) { return ((c - a + 3) % 3) - 1; }
-
-template <typename T>
-__device__ __forceinline__ long long psi_index(const PmlAxis<T> &P, int a, int nx, int ny, int i, int j, int k, int s)
-{
-    if (a == 0) return ((long long)k * ny + j) * P.P + s;
-    if (a == 1) return ((long long)k * P.P + s) * nx + i;
-    return ((long long)s * ny + j) * nx + i;
-}
-
-// W of an E-side term (edge component c, axis a) at edge (i,j,k): the adjoint of
-// the stretched backward difference, sg kn mu + cn tot.
-template <typename T>
-__device__ __forceinline__ T w_edge(const AdjArgs<T> &A, int c, int a, int i, int j, int k, T muv)
-{
-    const PmlAxis<T> &P = A.f.pml[a];
-    const T sg = T(curl_sign(c, a));
-    if (!P.on) return sg * muv;
-    const int pos = a == 0 ? i : (a == 1 ? j : k);
-    const int s = slab_slot(pos, P.lo, P.hi, P.n);
-    if (s < 0) return sg * muv;
-    const T tot = A.lpsiE[a][psi_slot(c, a)][psi_index(P, a, A.f.g.nx, A.f.g.ny, i, j, k, s)];
-    return sg * P.kn[pos] * muv + P.cn[pos] * tot;
-}
-
-// WH of an H-side term (face component h, axis a) at face (i,j,k): the adjoint
-// of the stretched forward difference, -dt/mu0 sg kh lH + ch tot.
-template <typename T>
-__device__ __forceinline__ T w_face(const AdjArgs<T> &A, int h, int a, int i, int j, int k, T lh)
-{
-    const PmlAxis<T> &P = A.f.pml[a];
-    const T sg = T(curl_sign(h, a));
-    const T hdt = A.f.hdt;
-    if (!P.on) return -hdt * sg * lh;
-    const int pos = a == 0 ? i : (a == 1 ? j : k);
-    const int s = slab_slot(pos, P.lo, P.hi, P.n);
-    if (s < 0) return -hdt * sg * lh;
-    const T tot = A.lpsiH[a][psi_slot(h, a)][psi_index(P, a, A.f.g.nx, A.f.g.ny, i, j, k, s)];
-    return -hdt * sg * P.kh[pos] * lh + P.ch[pos] * tot;
-}
+// Conventions written out in both sweeps: a curl term of component c
+// differentiated along axis a enters with +1 when a = c+1 (mod 3) and -1 when
+// a = c+2 (mod 3); the two CPML variables of axis a hold components a+1 and a+2
+// (mod 3) in that order (x: y, z; y: z, x; z: x, y), indexed ((k ny + j) P + s)
+// in x slabs, ((k P + s) nx + i) in y slabs and ((s ny + j) nx + i) in z slabs,
+// with s the slot of the cell in the axis's pair of slabs.
 
 // ---------------------------------------------------------------------------
 // Face sweep: lH'' = lH + curl W (F2^T), then the H-side PML variables (F1^T)
 // ---------------------------------------------------------------------------
+// W of an E-side term inside a CPML slab (the adjoint of the stretched backward
+// difference): sg kn mu + cn tot, with tot the stored E-side adjoint variable.
+template <typename T>
+__device__ __forceinline__ T w_slab(T sg, T kn, T cn, T muv, T tot)
+{
+    return sg * kn * muv + cn * tot;
+}
+
+// Outside the slabs W = sg mu.  Each axis has two terms per face position (the
+// two edge components it differentiates), which share the slab test, the
+// stretching coefficients and the index of their adjoint variables; the slab
+// tests are hoisted (x per lane, y per row, z per plane), so the interior runs
+// the stencil alone and the register count stays close to the H pass.
 template <typename T, int TY, int TZ>
 __global__ __launch_bounds__(kTileX *TY) void adj_face_kernel(const AdjArgs<T> A)
 {
@@ -80,50 +55,107 @@ __global__ __launch_bounds__(kTileX *TY) void adj_face_kernel(const AdjArgs<T> A
     const int jp = (j + 1 == ny) ? 0 : j + 1;
     const uint32_t o00 = uint32_t(j * nx + i) * sizeof(T), oxp = uint32_t(j * nx + ip) * sizeof(T);
     const uint32_t oyp = uint32_t(jp * nx + i) * sizeof(T);
-    const T rdx = A.f.rd[0], rdy = A.f.rd[1], rdz = A.f.rd[2];
+    const uint32_t oi = uint32_t(i) * sizeof(T), oip = uint32_t(ip) * sizeof(T);
+    const T rdx = A.f.rd[0], rdy = A.f.rd[1], rdz = A.f.rd[2], hdt = A.f.hdt;
     const T *mx = A.mu[0], *my = A.mu[1], *mz = A.mu[2];
+    const PmlAxis<T> &px = A.f.pml[0], &py = A.f.pml[1], &pz = A.f.pml[2];
+    // a wavefront is one row (blockDim.x = 64): j is uniform over it, so the y tests, the y
+    // coefficients and the row parts of every adjoint-variable index are scalar
+    const int jw = __builtin_amdgcn_readfirstlane(j), jpw = __builtin_amdgcn_readfirstlane(jp);
+    // slab slots (-1 outside) of the lane's own and +1 positions along x, of the row and the next along y
+    const int sxi = px.on ? slab_slot(i, px.lo, px.hi, nx) : -1;
+    const int sxp = px.on ? slab_slot(ip, px.lo, px.hi, nx) : -1;
+    const int syj = py.on ? slab_slot(jw, py.lo, py.hi, ny) : -1;
+    const int syp = py.on ? slab_slot(jpw, py.lo, py.hi, ny) : -1;
+    const uint32_t osxi = uint32_t(sxi) * sizeof(T), osxp = uint32_t(sxp) * sizeof(T);
     // the z terms W(Ey, z) and W(Ex, z) of plane k are those of plane k+1 one iteration earlier
     T wyz0, wxz0;
     {
         const long long b = (long long)k0 * sxy;
-        wyz0 = w_edge(A, 1, 2, i, j, k0, ldp(my + b, o00));
-        wxz0 = w_edge(A, 0, 2, i, j, k0, ldp(mx + b, o00));
+        const T my0 = ldo(my + b, o00), mx0 = ldo(mx + b, o00);
+        wyz0 = my0;
+        wxz0 = -mx0;
+        const int sz = pz.on ? slab_slot(k0, pz.lo, pz.hi, nz) : -1;
+        if (sz >= 0) {
+            const long long r = ((long long)sz * ny + jw) * nx;
+            const T kn = pz.kn[k0], cn = pz.cn[k0];
+            wyz0 = w_slab(T(1), kn, cn, my0, ldo(A.lpsiE[2][1] + r, oi));
+            wxz0 = w_slab(T(-1), kn, cn, mx0, ldo(A.lpsiE[2][0] + r, oi));
+        }
     }
     for (int k = k0; k < k1; ++k) {
         const int kp = (k + 1 == nz) ? 0 : k + 1;
         const long long b = opaque_offset((long long)k * sxy), bp = opaque_offset((long long)kp * sxy);
-        const T mx0 = ldp(mx + b, o00), my0 = ldp(my + b, o00), mz0 = ldp(mz + b, o00);
-        const T my_kp = ldp(my + bp, o00), mx_kp = ldp(mx + bp, o00);
-        const T mz_yp = ldp(mz + b, oyp), mz_xp = ldp(mz + b, oxp), mx_yp = ldp(mx + b, oyp), my_xp = ldp(my + b, oxp);
-        const T lh0 = ldp(A.lH[0] + b, o00), lh1 = ldp(A.lH[1] + b, o00), lh2 = ldp(A.lH[2] + b, o00);
-        // lHx: terms (Ey, z) and (Ez, y)
-        const T wyz1 = w_edge(A, 1, 2, i, j, kp, my_kp);
-        const T wzy0 = w_edge(A, 2, 1, i, j, k, mz0), wzy1 = w_edge(A, 2, 1, i, jp, k, mz_yp);
-        // lHy: terms (Ex, z) and (Ez, x)
-        const T wxz1 = w_edge(A, 0, 2, i, j, kp, mx_kp);
-        const T wzx0 = w_edge(A, 2, 0, i, j, k, mz0), wzx1 = w_edge(A, 2, 0, ip, j, k, mz_xp);
-        // lHz: terms (Ex, y) and (Ey, x)
-        const T wxy0 = w_edge(A, 0, 1, i, j, k, mx0), wxy1 = w_edge(A, 0, 1, i, jp, k, mx_yp);
-        const T wyx0 = w_edge(A, 1, 0, i, j, k, my0), wyx1 = w_edge(A, 1, 0, ip, j, k, my_xp);
-        const T lh[3] = {lh0 + (wyz0 - wyz1) * rdz + (wzy0 - wzy1) * rdy,
-                         lh1 + (wxz0 - wxz1) * rdz + (wzx0 - wzx1) * rdx,
-                         lh2 + (wxy0 - wxy1) * rdy + (wyx0 - wyx1) * rdx};
-        for (int h = 0; h < 3; ++h) stp(A.lH[h] + b, o00, lh[h]);
+        const T mx0 = ldo(mx + b, o00), my0 = ldo(my + b, o00), mz0 = ldo(mz + b, o00);
+        const T my_kp = ldo(my + bp, o00), mx_kp = ldo(mx + bp, o00);
+        const T mz_yp = ldo(mz + b, oyp), mz_xp = ldo(mz + b, oxp), mx_yp = ldo(mx + b, oyp), my_xp = ldo(my + b, oxp);
+        const T lh0 = ldo(A.lH[0] + b, o00), lh1 = ldo(A.lH[1] + b, o00), lh2 = ldo(A.lH[2] + b, o00);
+        // W outside the slabs: (Ey,z) +, (Ex,z) -, (Ez,y) -, (Ex,y) +, (Ez,x) +, (Ey,x) -
+        T wyz1 = my_kp, wxz1 = -mx_kp;
+        T wzy0 = -mz0, wzy1 = -mz_yp, wxy0 = mx0, wxy1 = mx_yp;
+        T wzx0 = mz0, wzx1 = mz_xp, wyx0 = -my0, wyx1 = -my_xp;
+        const int szk = pz.on ? slab_slot(k, pz.lo, pz.hi, nz) : -1;
+        const int szp = pz.on ? slab_slot(kp, pz.lo, pz.hi, nz) : -1;
+        // row bases of the adjoint variables: x slabs ((k ny + j) P + s), y slabs ((k P + s) nx + i)
+        const long long rx = ((long long)k * ny + jw) * px.P;
+        if (szp >= 0) {
+            const long long r = ((long long)szp * ny + jw) * nx;
+            const T kn = pz.kn[kp], cn = pz.cn[kp];
+            wyz1 = w_slab(T(1), kn, cn, my_kp, ldo(A.lpsiE[2][1] + r, oi));
+            wxz1 = w_slab(T(-1), kn, cn, mx_kp, ldo(A.lpsiE[2][0] + r, oi));
+        }
+        if (syj >= 0) {
+            const long long r = ((long long)k * py.P + syj) * nx;
+            const T kn = py.kn[jw], cn = py.cn[jw];
+            wzy0 = w_slab(T(-1), kn, cn, mz0, ldo(A.lpsiE[1][0] + r, oi));
+            wxy0 = w_slab(T(1), kn, cn, mx0, ldo(A.lpsiE[1][1] + r, oi));
+        }
+        if (syp >= 0) {
+            const long long r = ((long long)k * py.P + syp) * nx;
+            const T kn = py.kn[jpw], cn = py.cn[jpw];
+            wzy1 = w_slab(T(-1), kn, cn, mz_yp, ldo(A.lpsiE[1][0] + r, oi));
+            wxy1 = w_slab(T(1), kn, cn, mx_yp, ldo(A.lpsiE[1][1] + r, oi));
+        }
+        if (sxi >= 0) {
+            const T kn = ldo(px.kn, oi), cn = ldo(px.cn, oi);
+            wzx0 = w_slab(T(1), kn, cn, mz0, ldo(A.lpsiE[0][1] + rx, osxi));
+            wyx0 = w_slab(T(-1), kn, cn, my0, ldo(A.lpsiE[0][0] + rx, osxi));
+        }
+        if (sxp >= 0) {
+            const T kn = ldo(px.kn, oip), cn = ldo(px.cn, oip);
+            wzx1 = w_slab(T(1), kn, cn, mz_xp, ldo(A.lpsiE[0][1] + rx, osxp));
+            wyx1 = w_slab(T(-1), kn, cn, my_xp, ldo(A.lpsiE[0][0] + rx, osxp));
+        }
+        // lHx: terms (Ey, z) and (Ez, y); lHy: (Ex, z) and (Ez, x); lHz: (Ex, y) and (Ey, x)
+        const T nh0 = lh0 + (wyz0 - wyz1) * rdz + (wzy0 - wzy1) * rdy;
+        const T nh1 = lh1 + (wxz0 - wxz1) * rdz + (wzx0 - wzx1) * rdx;
+        const T nh2 = lh2 + (wxy0 - wxy1) * rdy + (wyx0 - wyx1) * rdx;
+        sto(A.lH[0] + b, o00, nh0);
+        sto(A.lH[1] + b, o00, nh1);
+        sto(A.lH[2] + b, o00, nh2);
         wyz0 = wyz1;
         wxz0 = wxz1;
-        // H-side PML adjoint variables: tot = bh * stored + (-dt/mu0) sg lH''
-        const int pos[3] = {i, j, k};
-        for (int a = 0; a < 3; ++a) {
-            const PmlAxis<T> &P = A.f.pml[a];
-            if (!P.on) continue;
-            const int s = slab_slot(pos[a], P.lo, P.hi, P.n);
-            if (s < 0) continue;
-            const long long pi = psi_index(P, a, nx, ny, i, j, k, s);
-            for (int q = 0; q < 2; ++q) {
-                const int h = (a + 1 + q) % 3;
-                T *ps = A.lpsiH[a][q];
-                ps[pi] = P.bh[pos[a]] * ps[pi] - A.f.hdt * T(curl_sign(h, a)) * lh[h];
-            }
+        // H-side PML adjoint variables: tot = bh * stored + (-dt/mu0) sg lH'' for the two face
+        // components each axis differentiates (x: Hy -, Hz +; y: Hz -, Hx +; z: Hx -, Hy +)
+        if (sxi >= 0) {
+            const T bh = ldo(px.bh, oi);
+            T *p0 = A.lpsiH[0][0] + rx, *p1 = A.lpsiH[0][1] + rx;
+            sto(p0, osxi, bh * ldo(p0, osxi) - hdt * T(-1) * nh1);
+            sto(p1, osxi, bh * ldo(p1, osxi) - hdt * T(1) * nh2);
+        }
+        if (syj >= 0) {
+            const long long r = ((long long)k * py.P + syj) * nx;
+            const T bh = py.bh[jw];
+            T *p0 = A.lpsiH[1][0] + r, *p1 = A.lpsiH[1][1] + r;
+            sto(p0, oi, bh * ldo(p0, oi) - hdt * T(-1) * nh2);
+            sto(p1, oi, bh * ldo(p1, oi) - hdt * T(1) * nh0);
+        }
+        if (szk >= 0) {
+            const long long r = ((long long)szk * ny + jw) * nx;
+            const T bh = pz.bh[k];
+            T *p0 = A.lpsiH[2][0] + r, *p1 = A.lpsiH[2][1] + r;
+            sto(p0, oi, bh * ldo(p0, oi) - hdt * T(-1) * nh0);
+            sto(p1, oi, bh * ldo(p1, oi) - hdt * T(1) * nh1);
         }
     }
 }
@@ -163,48 +195,74 @@ __device__ __forceinline__ EdgeCoef<T> adj_coef(const T e4[4], const T s4[4], co
     return {(eps - (T(1) - theta) * sdt) * inv, dt * inv, hdt * ell};
 }
 
-// Edge-local part of F2^T for component q of the edge at plane offset b, lane
+// Slab position of one edge row of the edge sweep: slots (-1 outside the slab)
+// along x (per lane), y (per row) and z (per plane), and the row parts of the
+// adjoint-variable indices (x slabs ((k ny + j) P + s), y slabs ((k P + s) nx + i),
+// z slabs ((s ny + j) nx + i)), so each access is a scalar base plus a lane offset.
+struct EdgeSlabs {
+    int sx, sy, sz;
+    uint32_t osx, oi;  // byte offsets of the x-slab slot and of column i (arrays of T)
+    long long rx, ry, rz;
+    int jw, k;
+};
+
+// Edge-local part of F2^T for component Q of the edge at plane offset b, lane
 // byte offsets ow (arrays of T) and od (FP64 gradient arrays), from values
 // loaded by the caller: lJ and gL (superconducting edges only), gS, E^n, E'_pre.
-template <typename T>
-__device__ __forceinline__ void adj_edge_local(const AdjArgs<T> &A, int q, long long b, uint32_t ow, uint32_t od,
-                                               const int pos[3], T lEq, const EdgeCoef<T> &k, T En, T Ep, T lJ,
+// `wall`: the edge lies on the PEC wall of a CPML axis other than Q (E' = 0
+// there, so its adjoint does not propagate).
+template <int Q, typename T>
+__device__ __forceinline__ void adj_edge_local(const AdjArgs<T> &A, long long b, uint32_t ow, uint32_t od, bool wall,
+                                               const EdgeSlabs &sl, T lEq, const EdgeCoef<T> &k, T En, T Ep, T lJ,
                                                double gL, double gS)
 {
-    const int nx = A.f.g.nx, ny = A.f.g.ny;
     const T theta = A.f.theta, hdt = A.f.hdt;
-    // PEC wall: E' = 0 there, so its adjoint does not propagate
-    bool wall = false;
-    for (int a = 0; a < 3; ++a)
-        if (a != q && A.f.pml[a].on && pos[a] == 0) wall = true;
     const T lEp = wall ? T(0) : lEq;
     const T mu = k.cb * lEp;
     T ljt = T(0);
     if (k.cj > T(0)) {
         ljt = lJ - mu;
-        stp(A.lJ[q] + b, ow, ljt);
-        stp(A.gL[q] + b, od, gL + (double)hdt * (double)ljt * (double)En);
+        sto(A.lJ[Q] + b, ow, ljt);
+        sto(A.gL[Q] + b, od, gL + (double)hdt * (double)ljt * (double)En);
     }
-    stp(A.gS[q] + b, od, gS - (double)lEp * (double)k.cb * ((double)theta * (double)Ep + (1.0 - (double)theta) * (double)En));
-    stp(A.mu[q] + b, ow, mu);
-    stp(A.lE[q] + b, ow, k.ca * lEp + k.cj * ljt);
-    // E-side PML adjoint variables: tot = bn * stored + sg mu
-    for (int a = 0; a < 3; ++a) {
-        if (a == q) continue;
-        const PmlAxis<T> &P = A.f.pml[a];
-        if (!P.on) continue;
-        const int sl = slab_slot(pos[a], P.lo, P.hi, P.n);
-        if (sl < 0) continue;
-        T *ps = A.lpsiE[a][psi_slot(q, a)];
-        const long long pi = psi_index(P, a, nx, ny, pos[0], pos[1], pos[2], sl);
-        ps[pi] = P.bn[pos[a]] * ps[pi] + T(curl_sign(q, a)) * mu;
+    sto(A.gS[Q] + b, od, gS - (double)lEp * (double)k.cb * ((double)theta * (double)Ep + (1.0 - (double)theta) * (double)En));
+    sto(A.mu[Q] + b, ow, mu);
+    sto(A.lE[Q] + b, ow, k.ca * lEp + k.cj * ljt);
+    // E-side PML adjoint variables of the two axes component Q is differentiated along:
+    // tot = bn * stored + sg mu (x: Ey -, Ez +; y: Ez -, Ex +; z: Ex -, Ey +)
+    if constexpr (Q != 0) {
+        if (sl.sx >= 0) {
+            T *ps = A.lpsiE[0][Q == 1 ? 0 : 1] + sl.rx;
+            sto(ps, sl.osx, ldo(A.f.pml[0].bn, sl.oi) * ldo(ps, sl.osx) + T(Q == 1 ? -1 : 1) * mu);
+        }
     }
+    if constexpr (Q != 1) {
+        if (sl.sy >= 0) {
+            T *ps = A.lpsiE[1][Q == 0 ? 1 : 0] + sl.ry;
+            sto(ps, sl.oi, A.f.pml[1].bn[sl.jw] * ldo(ps, sl.oi) + T(Q == 0 ? 1 : -1) * mu);
+        }
+    }
+    if constexpr (Q != 2) {
+        if (sl.sz >= 0) {
+            T *ps = A.lpsiE[2][Q == 0 ? 0 : 1] + sl.rz;
+            sto(ps, sl.oi, A.f.pml[2].bn[sl.k] * ldo(ps, sl.oi) + T(Q == 0 ? -1 : 1) * mu);
+        }
+    }
+}
+
+// WH of an H-side term inside a CPML slab (the adjoint of the stretched forward
+// difference): -dt/mu0 sg kh lH + ch tot; outside the slabs -dt/mu0 sg lH.
+template <typename T>
+__device__ __forceinline__ T wh_slab(T sg, T hdt, T kh, T ch, T lh, T tot)
+{
+    return -hdt * sg * kh * lh + ch * tot;
 }
 
 // z-marching like the forward E pass: the maps of plane k-1 and the z terms of
 // the curl^T at k-1 are carried in registers, and the edge coefficients of a
 // plane are formed one iteration ahead so that all loads of an iteration
 // (including lJ and gL on superconducting edges) are issued before the first wait.
+// Slab tests are hoisted as in the face sweep (x per lane, y per row, z per plane).
 template <typename T, int TY, int TZ, bool CLS>
 __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A)
 {
@@ -219,15 +277,34 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
     const uint32_t o00 = cell * sizeof(T), o10 = uint32_t(j * nx + im) * sizeof(T);
     const uint32_t o01 = uint32_t(jm * nx + i) * sizeof(T), o11 = uint32_t(jm * nx + im) * sizeof(T);
     const uint32_t od = cell * sizeof(double);
+    const uint32_t oi = uint32_t(i) * sizeof(T), oim = uint32_t(im) * sizeof(T);
     const T rdx = A.f.rd[0], rdy = A.f.rd[1], rdz = A.f.rd[2];
     const T dt = A.f.dt, theta = A.f.theta, hdt = A.f.hdt;
     const bool theta_one = (theta == T(1));
+    const PmlAxis<T> &px = A.f.pml[0], &py = A.f.pml[1], &pz = A.f.pml[2];
+    // a wavefront is one row (blockDim.x = 64): j is uniform over it
+    const int jw = __builtin_amdgcn_readfirstlane(j), jmw = __builtin_amdgcn_readfirstlane(jm);
+    const int sxi = px.on ? slab_slot(i, px.lo, px.hi, nx) : -1;
+    const int sxm = px.on ? slab_slot(im, px.lo, px.hi, nx) : -1;
+    const int syj = py.on ? slab_slot(jw, py.lo, py.hi, ny) : -1;
+    const int sym = py.on ? slab_slot(jmw, py.lo, py.hi, ny) : -1;
+    const uint32_t osxi = uint32_t(sxi) * sizeof(T), osxm = uint32_t(sxm) * sizeof(T);
+    // PEC walls: node plane 0 of a CPML axis
+    const bool wx = px.on && i == 0, wy = py.on && jw == 0;
     const int km0 = (k0 == 0) ? nz - 1 : k0 - 1;
     T whyz_m = T(0), whxz_m = T(0);
     if (A.doC) {
         const long long bm = (long long)km0 * sxy;
-        whyz_m = w_face(A, 1, 2, i, j, km0, ldp(A.lH[1] + bm, o00));
-        whxz_m = w_face(A, 0, 2, i, j, km0, ldp(A.lH[0] + bm, o00));
+        const T hy = ldo(A.lH[1] + bm, o00), hx = ldo(A.lH[0] + bm, o00);
+        whyz_m = -hdt * T(1) * hy;
+        whxz_m = -hdt * T(-1) * hx;
+        const int sz = pz.on ? slab_slot(km0, pz.lo, pz.hi, nz) : -1;
+        if (sz >= 0) {
+            const long long r = ((long long)sz * ny + jw) * nx;
+            const T kh = pz.kh[km0], ch = pz.ch[km0];
+            whyz_m = wh_slab(T(1), hdt, kh, ch, hy, ldo(A.lpsiH[2][1] + r, oi));
+            whxz_m = wh_slab(T(-1), hdt, kh, ch, hx, ldo(A.lpsiH[2][0] + r, oi));
+        }
     }
     T pe00 = T(0), pe10 = T(0), pe01 = T(0), ps00 = T(0), ps10 = T(0), ps01 = T(0), pl00 = T(0), pl10 = T(0),
       pl01 = T(0);
@@ -242,12 +319,12 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
     auto load_maps = [&](int kk) {
         const long long b = opaque_offset((long long)kk * sxy);
         if constexpr (CLS) {
-            return Classes{ldp(A.f.cls[0] + b, oc), ldp(A.f.cls[1] + b, oc), ldp(A.f.cls[2] + b, oc)};
+            return Classes{ldo(A.f.cls[0] + b, oc), ldo(A.f.cls[1] + b, oc), ldo(A.f.cls[2] + b, oc)};
         } else {
             const T *me = A.f.eps + b, *ms = A.f.sig + b, *ml = A.f.ell + b;
-            return Maps{ldp(me, o00), ldp(me, o10), ldp(me, o01), ldp(me, o11),
-                        ldp(ms, o00), ldp(ms, o10), ldp(ms, o01), ldp(ms, o11),
-                        ldp(ml, o00), ldp(ml, o10), ldp(ml, o01), ldp(ml, o11)};
+            return Maps{ldo(me, o00), ldo(me, o10), ldo(me, o01), ldo(me, o11),
+                        ldo(ms, o00), ldo(ms, o10), ldo(ms, o01), ldo(ms, o11),
+                        ldo(ml, o00), ldo(ml, o10), ldo(ml, o01), ldo(ml, o11)};
         }
     };
     auto coefs = [&](const auto &m) {
@@ -287,12 +364,12 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
     }
     for (int k = k0; k < k1; ++k) {
         const long long b = opaque_offset((long long)k * sxy);
-        T le[3] = {ldp(A.lE[0] + b, o00), ldp(A.lE[1] + b, o00), ldp(A.lE[2] + b, o00)};
+        T le[3] = {ldo(A.lE[0] + b, o00), ldo(A.lE[1] + b, o00), ldo(A.lE[2] + b, o00)};
         T hx0 = T(0), hy0 = T(0), hz0 = T(0), hz_ym = T(0), hz_xm = T(0), hx_ym = T(0), hy_xm = T(0);
         if (A.doC) {
             const T *Hx = A.lH[0] + b, *Hy = A.lH[1] + b, *Hz = A.lH[2] + b;
-            hx0 = ldp(Hx, o00); hy0 = ldp(Hy, o00); hz0 = ldp(Hz, o00);
-            hz_ym = ldp(Hz, o01); hz_xm = ldp(Hz, o10); hx_ym = ldp(Hx, o01); hy_xm = ldp(Hy, o10);
+            hx0 = ldo(Hx, o00); hy0 = ldo(Hy, o00); hz0 = ldo(Hz, o00);
+            hz_ym = ldo(Hz, o01); hz_xm = ldo(Hz, o10); hx_ym = ldo(Hx, o01); hy_xm = ldo(Hy, o10);
         }
         const EdgeCoef<T> kq[3] = {cq[0], cq[1], cq[2]};
         T En[3] = {}, Ep[3] = {}, lJ[3] = {};
@@ -301,20 +378,20 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
         if (A.doA) {
             for (int q = 0; q < 3; ++q) {
                 if (kq[q].cj > T(0)) {
-                    lJ[q] = ldp(A.lJ[q] + b, o00);
-                    gL[q] = ldp(A.gL[q] + b, od);
+                    lJ[q] = ldo(A.lJ[q] + b, o00);
+                    gL[q] = ldo(A.gL[q] + b, od);
                 }
             }
             for (int q = 0; q < 3; ++q) {
                 // E^n enters the sigma gradient only through (1 - theta) E^n: with theta = 1 it is read
                 // on superconducting edges only (the ell gradient)
-                if (!theta_one || kq[q].cj > T(0)) En[q] = ldp(A.En[q] + b, o00);
-                Ep[q] = ldp(A.Ep[q] + b, o00);
-                gS[q] = ldp(A.gS[q] + b, od);
+                if (!theta_one || kq[q].cj > T(0)) En[q] = ldo(A.En[q] + b, o00);
+                Ep[q] = ldo(A.Ep[q] + b, o00);
+                gS[q] = ldo(A.gS[q] + b, od);
             }
             // E'_pre: the soft sources of this step taken out of the stored E^{m+1}
             for (int sidx = 0; sidx < A.nsrc; ++sidx) {
-                if (k >= A.sbox[sidx][5] && k < A.sbox[sidx][6] && j >= A.sbox[sidx][3] && j < A.sbox[sidx][4] &&
+                if (k >= A.sbox[sidx][5] && k < A.sbox[sidx][6] && jw >= A.sbox[sidx][3] && jw < A.sbox[sidx][4] &&
                     i >= A.sbox[sidx][1] && i < A.sbox[sidx][2]) {
                     const int c = A.sbox[sidx][0];
                     const double g = A.sg[sidx];
@@ -327,25 +404,62 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
             // maps of the next plane (the last iteration re-reads its own plane and discards them)
             mn = load_maps(k + 1 < nz ? k + 1 : k);
         }
+        const int szk = pz.on ? slab_slot(k, pz.lo, pz.hi, nz) : -1;
+        const long long rx = ((long long)k * ny + jw) * px.P;
         if (A.doC) {
-            const T whyz = w_face(A, 1, 2, i, j, k, hy0), whxz = w_face(A, 0, 2, i, j, k, hx0);
+            // WH outside the slabs: (Hy,z) +, (Hx,z) -, (Hz,y) -, (Hx,y) +, (Hz,x) +, (Hy,x) -
+            T whyz = -hdt * T(1) * hy0, whxz = -hdt * T(-1) * hx0;
+            T wzy_m = -hdt * T(-1) * hz_ym, wzy_0 = -hdt * T(-1) * hz0;
+            T wxy_m = -hdt * T(1) * hx_ym, wxy_0 = -hdt * T(1) * hx0;
+            T wzx_m = -hdt * T(1) * hz_xm, wzx_0 = -hdt * T(1) * hz0;
+            T wyx_m = -hdt * T(-1) * hy_xm, wyx_0 = -hdt * T(-1) * hy0;
+            if (szk >= 0) {
+                const long long r = ((long long)szk * ny + jw) * nx;
+                const T kh = pz.kh[k], ch = pz.ch[k];
+                whyz = wh_slab(T(1), hdt, kh, ch, hy0, ldo(A.lpsiH[2][1] + r, oi));
+                whxz = wh_slab(T(-1), hdt, kh, ch, hx0, ldo(A.lpsiH[2][0] + r, oi));
+            }
+            if (sym >= 0) {
+                const long long r = ((long long)k * py.P + sym) * nx;
+                const T kh = py.kh[jmw], ch = py.ch[jmw];
+                wzy_m = wh_slab(T(-1), hdt, kh, ch, hz_ym, ldo(A.lpsiH[1][0] + r, oi));
+                wxy_m = wh_slab(T(1), hdt, kh, ch, hx_ym, ldo(A.lpsiH[1][1] + r, oi));
+            }
+            if (syj >= 0) {
+                const long long r = ((long long)k * py.P + syj) * nx;
+                const T kh = py.kh[jw], ch = py.ch[jw];
+                wzy_0 = wh_slab(T(-1), hdt, kh, ch, hz0, ldo(A.lpsiH[1][0] + r, oi));
+                wxy_0 = wh_slab(T(1), hdt, kh, ch, hx0, ldo(A.lpsiH[1][1] + r, oi));
+            }
+            if (sxm >= 0) {
+                const T kh = ldo(px.kh, oim), ch = ldo(px.ch, oim);
+                wzx_m = wh_slab(T(1), hdt, kh, ch, hz_xm, ldo(A.lpsiH[0][1] + rx, osxm));
+                wyx_m = wh_slab(T(-1), hdt, kh, ch, hy_xm, ldo(A.lpsiH[0][0] + rx, osxm));
+            }
+            if (sxi >= 0) {
+                const T kh = ldo(px.kh, oi), ch = ldo(px.ch, oi);
+                wzx_0 = wh_slab(T(1), hdt, kh, ch, hz0, ldo(A.lpsiH[0][1] + rx, osxi));
+                wyx_0 = wh_slab(T(-1), hdt, kh, ch, hy0, ldo(A.lpsiH[0][0] + rx, osxi));
+            }
             // Ex: terms (Hy, z) and (Hz, y); Ey: (Hx, z) and (Hz, x); Ez: (Hx, y) and (Hy, x)
-            le[0] += (whyz_m - whyz) * rdz + (w_face(A, 2, 1, i, jm, k, hz_ym) - w_face(A, 2, 1, i, j, k, hz0)) * rdy;
-            le[1] += (whxz_m - whxz) * rdz + (w_face(A, 2, 0, im, j, k, hz_xm) - w_face(A, 2, 0, i, j, k, hz0)) * rdx;
-            le[2] += (w_face(A, 0, 1, i, jm, k, hx_ym) - w_face(A, 0, 1, i, j, k, hx0)) * rdy +
-                     (w_face(A, 1, 0, im, j, k, hy_xm) - w_face(A, 1, 0, i, j, k, hy0)) * rdx;
+            le[0] += (whyz_m - whyz) * rdz + (wzy_m - wzy_0) * rdy;
+            le[1] += (whxz_m - whxz) * rdz + (wzx_m - wzx_0) * rdx;
+            le[2] += (wxy_m - wxy_0) * rdy + (wyx_m - wyx_0) * rdx;
             whyz_m = whyz;
             whxz_m = whxz;
         }
-        if (A.obj && i >= A.ob[0] && i < A.ob[1] && j >= A.ob[2] && j < A.ob[3] && k >= A.ob[4] && k < A.ob[5])
+        if (A.obj && i >= A.ob[0] && i < A.ob[1] && jw >= A.ob[2] && jw < A.ob[3] && k >= A.ob[4] && k < A.ob[5])
             le[A.ocomp] += (T)A.og;
         if (!A.doA) {
-            for (int q = 0; q < 3; ++q) stp(A.lE[q] + b, o00, le[q]);
+            for (int q = 0; q < 3; ++q) sto(A.lE[q] + b, o00, le[q]);
             continue;
         }
-        const int pos[3] = {i, j, k};
-        for (int q = 0; q < 3; ++q)
-            adj_edge_local(A, q, b, o00, od, pos, le[q], kq[q], En[q], Ep[q], lJ[q], gL[q], gS[q]);
+        const bool wz = pz.on && k == 0;
+        const EdgeSlabs sl{sxi, syj, szk, osxi, oi, rx, ((long long)k * py.P + syj) * nx,
+                           ((long long)szk * ny + jw) * nx, jw, k};
+        adj_edge_local<0>(A, b, o00, od, wy || wz, sl, le[0], kq[0], En[0], Ep[0], lJ[0], gL[0], gS[0]);
+        adj_edge_local<1>(A, b, o00, od, wx || wz, sl, le[1], kq[1], En[1], Ep[1], lJ[1], gL[1], gS[1]);
+        adj_edge_local<2>(A, b, o00, od, wx || wy, sl, le[2], kq[2], En[2], Ep[2], lJ[2], gL[2], gS[2]);
         coefs(mn);
     }
 }
