@@ -419,21 +419,40 @@ __device__ __forceinline__ double waveform(int wave, double f, double t0, double
     return wave == TFL_WAVE_GAUSS ? g : g * sin(kTwoPi * f * t);
 }
 
+// All soft sources of a step in one launch, a thread per cell of the boxes laid
+// end to end (src[q].offset is the prefix of the counts).  Where boxes of one
+// component overlap, the thread of the first box holding an edge adds every
+// source holding it in source order (the sums one launch per source would
+// form) and the threads of the later boxes leave it.
 template <typename T>
-__global__ void source_kernel(const SrcArgs<T> a, int q)
+__global__ void source_kernel(const SrcArgs<T> a)
 {
-    const SourceDesc &s = a.src[q];
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= s.count) return;
+    if (idx >= a.total) return;
+    int q = 0;
+    while (q + 1 < a.nsrc && idx >= a.src[q + 1].offset) ++q;
+    const SourceDesc &s = a.src[q];
+    const long long loc = idx - s.offset;
     const int wx = s.i1 - s.i0, wy = s.j1 - s.j0;
-    const int i = s.i0 + (int)(idx % wx);
-    const long long r = idx / wx;
+    const int i = s.i0 + (int)(loc % wx);
+    const long long r = loc / wx;
     const int j = s.j0 + (int)(r % wy);
     const int k = s.k0 + (int)(r / wy);
-    const double g = s.amp * waveform(s.wave, s.f, s.t0, s.tw, a.t);
+    auto holds = [&](const SourceDesc &d) {
+        return d.comp == s.comp && i >= d.i0 && i < d.i1 && j >= d.j0 && j < d.j1 && k >= d.k0 && k < d.k1;
+    };
+    for (int p = 0; p < q; ++p)
+        if (holds(a.src[p])) return;
     T *E = a.E[s.comp];
     const long long c = ((long long)k * a.g.ny + j) * a.g.nx + i;
-    E[c] = (T)((double)E[c] + g);
+    T v = E[c];
+    for (int p = q; p < a.nsrc; ++p) {
+        const SourceDesc &d = a.src[p];
+        if (!holds(d)) continue;
+        const double g = d.amp * waveform(d.wave, d.f, d.t0, d.tw, a.t);
+        v = (T)((double)v + g);
+    }
+    E[c] = v;
 }
 
 constexpr int kProbeThreads = 256;
@@ -876,15 +895,16 @@ hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s)
 template <typename T>
 hipError_t launch_sources(const SrcArgs<T> &a, hipStream_t s)
 {
-    for (int q = 0; q < a.nsrc; ++q) {
-        const long long cnt = a.src[q].count;
-        if (cnt <= 0) continue;
-        const int nb = (int)((cnt + 255) / 256);
-        hipLaunchKernelGGL(source_kernel<T>, dim3(nb), dim3(256), 0, s, a, q);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    SrcArgs<T> b = a;
+    long long total = 0;
+    for (int q = 0; q < b.nsrc; ++q) {
+        b.src[q].offset = total;
+        total += b.src[q].count > 0 ? b.src[q].count : 0;
     }
-    return hipSuccess;
+    b.total = total;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(source_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, b);
+    return hipGetLastError();
 }
 
 template <typename T>

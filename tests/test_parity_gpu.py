@@ -58,6 +58,22 @@ def test_cpml_sources_probes(pml, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_overlapping_sources(dtype):
+    """Boxes that overlap on one component add in source order (all sources of a step run in one
+    launch, where the first box holding an edge adds every source there); a second component
+    overlaps them too, and a one-cell box sits inside two others."""
+    wl = workloads.random_medium((40, 18, 22), seed=11, pml=(None, (3, 3), None))
+    wl["sources"] = [
+        dict(comp=1, box=(5, 30, 2, 14, 4, 18), amplitude=1.5, waveform="sin", freq=2e14),
+        dict(comp=1, box=(10, 12, 0, 18, 0, 22), amplitude=-0.7, waveform="mod_gauss", freq=3e14, t0=2e-15, tw=8e-16),
+        dict(comp=2, box=(8, 20, 6, 9, 3, 12), amplitude=0.9, waveform="gauss", t0=1e-15, tw=5e-16),
+        dict(comp=1, box=(11, 12, 5, 6, 10, 11), amplitude=3.0, waveform="sin", freq=1e14),
+    ]
+    wl["probes"] = [dict(comp=1, box=(11, 12, 0, 18, 0, 22), freqs=(2e14,))]
+    check(wl, 20, dtype)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_mid_size_grid(dtype):
     """8.4 M cells: the launch rule picks 16-plane tiles for the FP32 sweeps and the FP64 E pass
     and 32-plane tiles for the FP64 H pass, which the small grids (8 planes) do not reach."""
