@@ -2,9 +2,9 @@
 
 Workload: the 256^3 roofline grid (dx = 20 nm, periodic, random
 superconducting boxes on ~30 % of the cells, E and H ~ N(0, 1)), stepped in
-FP64 and in FP32.  A step is one full time step of Algorithm 1: on this
-all-periodic grid one fused sweep (the product path), and for comparison the
-two passes (H pass, E + Js pass) that grids with CPML use.  Also timed: the adjoint gradient on the half-size CPW
+FP64 and in FP32.  A step is one full time step of Algorithm 1: one fused
+sweep (the product path), and for comparison the two passes (H pass, E + Js
+pass) it replaces.  Also timed: the adjoint gradient on the half-size CPW
 workload (256 x 128 x 64 cells, 4096 steps, 64-step checkpoint segments)
 against its checkpointed forward run.  Prints one JSON line.
 
@@ -300,9 +300,10 @@ def table1_run():
     return rows
 
 
-def paper_cpw_run(steps=200, warmup=10, cases=(1, 2, 3, 4)):
+def paper_cpw_run(steps=200, warmup=10, cases=(1, 2, 3, 4), fused=True):
     """Step rate on the paper's CPW resonator at its own size (196 M cells with the CPML slabs), each
-    film case, FP32 and FP64, against the paper's ~0.05 s per step on 32 A100 GPUs."""
+    film case, FP32 and FP64, against the paper's ~0.05 s per step on 32 A100 GPUs (fused=False: the
+    two passes instead of the fused sweep)."""
     import numpy as np
     import torch
 
@@ -312,7 +313,7 @@ def paper_cpw_run(steps=200, warmup=10, cases=(1, 2, 3, 4)):
     for case in cases:
         wl = workloads.paper_cpw_grid(case)
         for dtype, npdt in ((torch.float32, np.float32), (torch.float64, np.float64)):
-            sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"])
+            sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"], fused=fused)
             sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
             for src in wl["sources"]:
                 sim.add_source(**src)
@@ -327,7 +328,7 @@ def paper_cpw_run(steps=200, warmup=10, cases=(1, 2, 3, 4)):
             series_ok = bool(np.all(np.isfinite(sim.probe(pids[1])[0])))
             sim.close()
             n = int(np.prod(wl["shape"]))
-            rows.append(dict(case=case, dtype=str(dtype)[6:], cells=n, steps=steps, ms_per_step=el / steps * 1e3,
+            rows.append(dict(case=case, dtype=str(dtype)[6:], fused=fused, cells=n, steps=steps, ms_per_step=el / steps * 1e3,
                              Gcells=n * steps / el / 1e9, dt_s=wl["dt"], nonfinite=int(bad), probes_finite=series_ok,
                              paper_s_per_step=0.05, speedup_per_step=0.05 / (el / steps)))
             print(f"# {rows[-1]}", file=sys.stderr, flush=True)

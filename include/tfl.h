@@ -147,19 +147,21 @@ int tfl_bind_state(tfl_sim *sim, void *const E[3], void *const H[3], void *const
  * workspace may be NULL when its size is 0. */
 int tfl_bind_workspace(tfl_sim *sim, void *workspace, void *scratch, void *stream);
 
-/* Optional second set of E and H fields for the fused sweep (grids with
- * periodic boundaries on every axis).  tfl_fused_buffer_bytes reports its size
- * (6 fields, each padded to 256 bytes; 0 when the grid has a CPML axis).
+/* Optional second set of E and H fields for the fused sweep.
+ * tfl_fused_buffer_bytes reports its size: 6 fields, each padded to 256
+ * bytes, then on each CPML axis a second set of its two H-side auxiliary
+ * variables (2 x the slab cells of the axis, padded to 256 bytes).
  * With a buffer bound, tfl_step runs H and E updates of a step in one sweep
- * (Algorithm 1, steps 1-5 of a time step fused): it reads E^n, H^{n-1/2} from
- * one set and writes E^{n+1}, H^{n+1/2} to the other, recomputing the few H
- * values a cell needs from its x-1 and y-1 neighbours, so each cell's fields
- * cross HBM once per step instead of twice; results equal those of the two
- * passes.  Steps run in pairs (bound fields -> buffer -> bound fields), an odd
- * last step with the two passes, so the state is in the bound fields after
- * every call.  The buffer is caller-owned device memory, 256-byte aligned,
- * holding nothing between calls; bind NULL to go back to the two passes.
- * TFL_E_INVAL on a grid with a CPML axis or a misaligned buffer. */
+ * (Algorithm 1, steps 1-5 of a time step fused): it reads E^n, H^{n-1/2} (and
+ * the H-side CPML variables) from one set and writes E^{n+1}, H^{n+1/2} (and
+ * the new variables) to the other, recomputing the few H values a cell needs
+ * from its x-1 and y-1 neighbours, so each cell's fields cross HBM once per
+ * step instead of twice; results equal those of the two passes bit for bit.
+ * Steps run in pairs (bound fields -> buffer -> bound fields), an odd last
+ * step with the two passes, so the state is in the bound fields and the
+ * workspace after every call.  The buffer is caller-owned device memory,
+ * 256-byte aligned, holding nothing between calls; bind NULL to go back to
+ * the two passes.  TFL_E_INVAL on a misaligned buffer. */
 int tfl_fused_buffer_bytes(const tfl_sim *sim, size_t *bytes);
 int tfl_bind_fused_buffer(tfl_sim *sim, void *buffer);
 
@@ -286,10 +288,11 @@ int tfl_forward_checkpointed(tfl_sim *sim, const tfl_objective *obj, int64_t nst
  * seg and ckpt; F as returned by it).  Writes dJ/d inv_lambda2 and
  * dJ/d sigma_n per cell to grad_ell and grad_sigma (device FP64, N each).
  * snap and adj are device buffers of snap_bytes and adj_bytes.  Probes are
- * not sampled during the recomputation.  On return the state arrays hold
- * intermediate values of the recomputation: load a saved state (and set the
- * step index) before stepping again.  TFL_E_STATE if no matching forward run
- * exists. */
+ * not sampled during the recomputation, which runs the fused sweep when a
+ * fused buffer is bound (as tfl_step; same results).  On return the state
+ * arrays (and the fused buffer) hold intermediate values of the
+ * recomputation: load a saved state (and set the step index) before stepping
+ * again.  TFL_E_STATE if no matching forward run exists. */
 int tfl_adjoint(tfl_sim *sim, const tfl_objective *obj, int64_t nsteps, int64_t seg, const void *ckpt,
                 const double F[2], void *snap, void *adj, double *grad_ell, double *grad_sigma, void *stream);
 

@@ -78,6 +78,18 @@ size_t slab_elems(const tfl_config &c, int a)
 
 size_t round256(size_t bytes) { return (bytes + 255) & ~size_t(255); }
 
+size_t fused_layout(const tfl_sim *s, size_t psi_at[3], size_t *total)
+{
+    const size_t fb = round256((size_t)s->N * s->esz);
+    size_t off = 6 * fb;
+    for (int ax = 0; ax < 3; ++ax) {
+        psi_at[ax] = off;
+        if (s->cfg.bc[ax] == TFL_CPML) off += round256(2 * s->psi_count[ax] * s->esz);
+    }
+    if (total) *total = off;
+    return fb;
+}
+
 void layout_workspace(tfl_sim *s)
 {
     const tfl_config &c = s->cfg;
@@ -143,6 +155,7 @@ StepArgs<T> make_args(const tfl_sim *s)
         T *ps = w + s->psi_off[ax];
         const size_t m = s->psi_count[ax];
         p.psiH[0] = ps; p.psiH[1] = ps + m; p.psiE[0] = ps + 2 * m; p.psiE[1] = ps + 3 * m;
+        p.psiHo[0] = p.psiH[0]; p.psiHo[1] = p.psiH[1];
     }
     return a;
 }
@@ -177,8 +190,10 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
     // fields, B the buffer), so the state is back in A after every call; an odd last step runs the
     // two passes in place on A.
     StepArgs<T> ab = a, ba = a;
-    if (s->fused) {
-        const size_t fb = round256((size_t)s->N * s->esz);
+    const bool fused = s->fused != nullptr && fused_step_pays<T>(a);
+    if (fused) {
+        size_t psi_at[3];
+        const size_t fb = fused_layout(s, psi_at);
         for (int q = 0; q < 3; ++q) {
             T *eb = (T *)((char *)s->fused + q * fb), *hb = (T *)((char *)s->fused + (3 + q) * fb);
             ab.Eout[q] = eb;
@@ -186,11 +201,23 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
             ba.E[q] = eb;
             ba.H[q] = hb;
         }
+        // CPML axes: the H-side variables go A -> B -> A with the fields (the E-side ones stay in place)
+        for (int ax = 0; ax < 3; ++ax) {
+            if (!a.pml[ax].on || s->psi_count[ax] == 0) continue;
+            T *pb = (T *)((char *)s->fused + psi_at[ax]);
+            const size_t m = s->psi_count[ax];
+            ab.pml[ax].psiHo[0] = pb;
+            ab.pml[ax].psiHo[1] = pb + m;
+            ba.pml[ax].psiH[0] = pb;
+            ba.pml[ax].psiH[1] = pb + m;
+            ba.pml[ax].psiHo[0] = a.pml[ax].psiH[0];
+            ba.pml[ax].psiHo[1] = a.pml[ax].psiH[1];
+        }
     }
     bool inB = false;
     for (int64_t it = 0; it < nsteps; ++it) {
         if (ev && (e = hipEventRecord(ev[2 * it], st)) != hipSuccess) return hip_fail(s, e, "event");
-        if (s->fused && (inB || it + 1 < nsteps)) {
+        if (fused && (inB || it + 1 < nsteps)) {
             if ((e = launch_fused_step<T>(inB ? ba : ab, st)) != hipSuccess) return hip_fail(s, e, "fused step");
             if (ev && (e = hipEventRecord(ev[2 * it + 1], st)) != hipSuccess) return hip_fail(s, e, "event");
             inB = !inB;
@@ -217,12 +244,7 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
     return TFL_OK;
 }
 
-bool fused_eligible(const tfl_sim *s)
-{
-    for (int a = 0; a < 3; ++a)
-        if (s->cfg.bc[a] != TFL_PERIODIC) return false;
-    return true;
-}
+
 
 int upload_probes(tfl_sim *s, hipStream_t st)
 {
@@ -417,14 +439,14 @@ int tfl_bind_workspace(tfl_sim *s, void *workspace, void *scratch, void *stream)
 int tfl_fused_buffer_bytes(const tfl_sim *s, size_t *bytes)
 {
     if (!s || !bytes) return fail(nullptr, TFL_E_INVAL, "null argument");
-    *bytes = fused_eligible(s) ? 6 * round256((size_t)s->N * s->esz) : 0;
+    size_t psi_at[3];
+    fused_layout(s, psi_at, bytes);
     return TFL_OK;
 }
 
 int tfl_bind_fused_buffer(tfl_sim *s, void *buf)
 {
     if (!s) return fail(nullptr, TFL_E_INVAL, "null handle");
-    if (buf && !fused_eligible(s)) return fail(s, TFL_E_INVAL, "the fused sweep needs periodic boundaries on every axis");
     if (buf && !aligned(buf)) return fail(s, TFL_E_INVAL, "fused buffer must be 256-byte aligned");
     s->fused = buf;
     return TFL_OK;

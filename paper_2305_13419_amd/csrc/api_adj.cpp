@@ -154,14 +154,45 @@ struct Reverse {
         fs.nsrc = (int)s->src.size();
         for (int q = 0; q < fs.nsrc; ++q) fs.src[q] = s->src[q];
         const double dt = s->cfg.dt;
-        for (int64_t t = 0; t < len; ++t) {
+        // With the fused buffer bound (and the fused sweep paying on this grid) the recomputation
+        // runs the fused sweep: E goes from snapshot t to snapshot t + 1 as in the two passes, H and
+        // the H-side CPML variables alternate between the bound set (even t) and the buffer (odd t).
+        const bool fused = s->fused != nullptr && fused_step_pays<T>(f);
+        StepArgs<T> fo = f, fe = f;  // odd t: buffer -> bound set; even t: bound set -> buffer
+        if (fused) {
+            size_t psi_at[3];
+            const size_t fst = fused_layout(s, psi_at);
             for (int q = 0; q < 3; ++q) {
-                f.E[q] = snapE(t, q);
-                f.Eout[q] = snapE(t + 1, q);
+                T *hb = (T *)((char *)s->fused + (3 + q) * fst);
+                fe.Hout[q] = hb;
+                fo.H[q] = hb;
+                fo.Hout[q] = f.H[q];
+            }
+            for (int ax = 0; ax < 3; ++ax) {
+                if (!f.pml[ax].on || s->psi_count[ax] == 0) continue;
+                T *pb = (T *)((char *)s->fused + psi_at[ax]);
+                const size_t m = s->psi_count[ax];
+                fe.pml[ax].psiHo[0] = pb;
+                fe.pml[ax].psiHo[1] = pb + m;
+                fo.pml[ax].psiH[0] = pb;
+                fo.pml[ax].psiH[1] = pb + m;
+                fo.pml[ax].psiHo[0] = f.pml[ax].psiH[0];
+                fo.pml[ax].psiHo[1] = f.pml[ax].psiH[1];
+            }
+        }
+        for (int64_t t = 0; t < len; ++t) {
+            StepArgs<T> &g = fused ? ((t & 1) ? fo : fe) : f;
+            for (int q = 0; q < 3; ++q) {
+                g.E[q] = snapE(t, q);
+                g.Eout[q] = snapE(t + 1, q);
                 fs.E[q] = snapE(t + 1, q);
             }
-            if ((e = launch_h_pass<T>(f, st)) != hipSuccess) return hip_fail(s, e, "recompute h_pass");
-            if ((e = launch_e_pass<T>(f, st)) != hipSuccess) return hip_fail(s, e, "recompute e_pass");
+            if (fused) {
+                if ((e = launch_fused_step<T>(g, st)) != hipSuccess) return hip_fail(s, e, "recompute fused step");
+            } else {
+                if ((e = launch_h_pass<T>(g, st)) != hipSuccess) return hip_fail(s, e, "recompute h_pass");
+                if ((e = launch_e_pass<T>(g, st)) != hipSuccess) return hip_fail(s, e, "recompute e_pass");
+            }
             if (fs.nsrc > 0) {
                 fs.t = (double)(s0 + t + 1) * dt;
                 if ((e = launch_sources<T>(fs, st)) != hipSuccess) return hip_fail(s, e, "recompute sources");

@@ -180,6 +180,51 @@ static __device__ __forceinline__ T stretch(T d, T *psi, long long pidx, T b, T 
     return kinv * d + p;
 }
 
+// The same with the new variable written to psio: the fused sweep reads the
+// H-side variables of one set and writes the other, as it does E and H, since
+// the neighbours it recomputes read their old values.
+template <typename T>
+static __device__ __forceinline__ T stretch_to(T d, const T *psi, T *psio, long long pidx, T b, T c, T kinv)
+{
+    const T p = b * psi[pidx] + c * d;
+    psio[pidx] = p;
+    return kinv * d + p;
+}
+
+// The stretching of d with the stored variable's value already loaded: p is
+// the new variable (for the caller to store, or not).
+template <typename T>
+static __device__ __forceinline__ T stretch_v(T d, T psi, T b, T c, T kinv, T &p)
+{
+    p = b * psi + c * d;
+    return kinv * d + p;
+}
+
+// stretch, stretch_to and stretch_virtual on a variable at a scalar base plus a
+// lane byte offset (ldo / sto)
+template <typename T>
+static __device__ __forceinline__ T stretch_o(T d, T *psi, uint32_t off, T b, T c, T kinv)
+{
+    const T p = b * ldo(psi, off) + c * d;
+    sto(psi, off, p);
+    return kinv * d + p;
+}
+
+template <typename T>
+static __device__ __forceinline__ T stretch_to_o(T d, const T *psi, T *psio, uint32_t off, T b, T c, T kinv)
+{
+    const T p = b * ldo(psi, off) + c * d;
+    sto(psio, off, p);
+    return kinv * d + p;
+}
+
+template <typename T>
+static __device__ __forceinline__ T stretch_virtual_o(T d, const T *psi, uint32_t off, T b, T c, T kinv)
+{
+    const T p = b * ldo(psi, off) + c * d;
+    return kinv * d + p;
+}
+
 template <typename T>
 static __device__ __forceinline__ T stretch_virtual(T d, const T *psi, long long pidx, T b, T c, T kinv)
 {

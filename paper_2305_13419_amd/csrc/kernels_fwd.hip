@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const
 // edge classes).  NT: the new E and H are stored with a
 // nontemporal hint (chosen at launch for grids well beyond the infinity cache,
 // where keeping them would only evict lines the sweep still reads).
-template <typename T, int TY, int TZ, bool CLS, bool NT, int TX>
+template <typename T, int TY, int TZ, bool CLS, bool NT, int TX, bool PML>
 __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const StepArgs<T> a)
 {
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
@@ -279,6 +279,49 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
     const uint32_t oxm_yp = uint32_t(jp * nx + im) * w, oxp_ym = uint32_t(jm * nx + ip) * w;
     const T rdx = a.rd[0], rdy = a.rd[1], rdz = a.rd[2];
     const T dt = a.dt, theta = a.theta, hdt = a.hdt;
+    // loads at a plane base plus a lane offset (ldo on CPML grids, where the longer body would
+    // otherwise keep 64-bit addresses live across the z loop)
+    auto ld = [](const auto *base, uint32_t off) {
+        if constexpr (PML) return ldo(base, off);
+        else return ldp(base, off);
+    };
+    // CPML grids (PML): slab slots (-1 outside) of the lane's column and of column x-1, of the
+    // row and of row y-1 (a wavefront is one row: those are scalar), and the PEC walls; the
+    // auxiliary variables and coefficient tables are addressed as scalar bases plus these lane
+    // byte offsets
+    const PmlAxis<T> &px = a.pml[0], &py = a.pml[1], &pz = a.pml[2];
+    [[maybe_unused]] int sx = -1, sxm = -1, sy = -1, sym = -1, jw = j, jmw = jm;
+    [[maybe_unused]] bool wall_x = false, wall_y = false;
+    [[maybe_unused]] uint32_t osx = 0, osxm = 0;
+    [[maybe_unused]] const uint32_t oi = uint32_t(i) * w, oim = uint32_t(im) * w;
+    if constexpr (PML) {
+        jw = __builtin_amdgcn_readfirstlane(j);
+        jmw = __builtin_amdgcn_readfirstlane(jm);
+        sx = px.on ? slab_slot(i, px.lo, px.hi, nx) : -1;
+        sxm = px.on ? slab_slot(im, px.lo, px.hi, nx) : -1;
+        sy = py.on ? slab_slot(jw, py.lo, py.hi, ny) : -1;
+        sym = py.on ? slab_slot(jmw, py.lo, py.hi, ny) : -1;
+        osx = uint32_t(sx) * w;
+        osxm = uint32_t(sxm) * w;
+        wall_x = px.on && i == 0;
+        wall_y = py.on && jw == 0;
+    }
+    // x slabs cut through the wavefronts of a row: their coefficients (the tables cover the whole
+    // axis) are loaded once, and each plane's x-slab variables are loaded with the plane's other
+    // loads at slots clamped into the slab, so that only arithmetic and stores depend on the lane
+    [[maybe_unused]] const bool xv = PML && px.on && px.P > 0;
+    [[maybe_unused]] T xbh = T(0), xch = T(0), xkh = T(0), xbn = T(0), xcn = T(0), xkn = T(0);
+    [[maybe_unused]] T xbhm = T(0), xchm = T(0), xkhm = T(0);
+    [[maybe_unused]] uint32_t osxc = 0, osxmc = 0;
+    if constexpr (PML) {
+        if (xv) {
+            xbh = ldo(px.bh, oi); xch = ldo(px.ch, oi); xkh = ldo(px.kh, oi);
+            xbn = ldo(px.bn, oi); xcn = ldo(px.cn, oi); xkn = ldo(px.kn, oi);
+            xbhm = ldo(px.bh, oim); xchm = ldo(px.ch, oim); xkhm = ldo(px.kh, oim);
+            osxc = uint32_t(sx >= 0 ? sx : 0) * w;
+            osxmc = uint32_t(sxm >= 0 ? sxm : 0) * w;
+        }
+    }
 
     T pe00, pe10, pe01, ps00, ps10, ps01, pl00, pl10, pl01;
     EdgeCoef<T> cx, cy, cz;
@@ -292,12 +335,12 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
     auto load_maps = [&](int kk) {
         const long long b = opaque_offset((long long)kk * sxy);
         if constexpr (CLS) {
-            return Classes{ldp(a.cls[0] + b, oc), ldp(a.cls[1] + b, oc), ldp(a.cls[2] + b, oc)};
+            return Classes{ld(a.cls[0] + b, oc), ld(a.cls[1] + b, oc), ld(a.cls[2] + b, oc)};
         } else {
             const T *me = a.eps + b, *ms = a.sig + b, *ml = a.ell + b;
-            return Maps{ldp(me, o00), ldp(me, o10), ldp(me, o01), ldp(me, o11),
-                        ldp(ms, o00), ldp(ms, o10), ldp(ms, o01), ldp(ms, o11),
-                        ldp(ml, o00), ldp(ml, o10), ldp(ml, o01), ldp(ml, o11)};
+            return Maps{ld(me, o00), ld(me, o10), ld(me, o01), ld(me, o11),
+                        ld(ms, o00), ld(ms, o10), ld(ms, o01), ld(ms, o11),
+                        ld(ml, o00), ld(ml, o10), ld(ml, o01), ld(ml, o11)};
         }
     };
     auto coefs = [&](const auto &m) {
@@ -333,13 +376,27 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
     {
         const long long bm = (long long)km0 * sxy, b = (long long)k0 * sxy;
         const T *Ex = a.E[0] + bm, *Ey = a.E[1] + bm, *Ez = a.E[2] + bm;
-        const T exk = ldp(Ex, o00), eyk = ldp(Ey, o00), ez = ldp(Ez, o00);
-        const T exk1 = ldp(a.E[0] + b, o00), eyk1 = ldp(a.E[1] + b, o00);
-        const T ez_x = ldp(Ez, oxp), ez_y = ldp(Ez, oyp);
-        const T dyEz = (ez_y - ez) * rdy, dzEy = (eyk1 - eyk) * rdz;
-        const T dzEx = (exk1 - exk) * rdz, dxEz = (ez_x - ez) * rdx;
-        hx_km = ldp(a.H[0] + bm, o00) - hdt * (dyEz - dzEy);
-        hy_km = ldp(a.H[1] + bm, o00) - hdt * (dzEx - dxEz);
+        const T exk = ld(Ex, o00), eyk = ld(Ey, o00), ez = ld(Ez, o00);
+        const T exk1 = ld(a.E[0] + b, o00), eyk1 = ld(a.E[1] + b, o00);
+        const T ez_x = ld(Ez, oxp), ez_y = ld(Ez, oyp);
+        T dyEz = (ez_y - ez) * rdy, dzEy = (eyk1 - eyk) * rdz;
+        T dzEx = (exk1 - exk) * rdz, dxEz = (ez_x - ez) * rdx;
+        if constexpr (PML) {  // the H pass's stretching at plane k0-1, without storing (another tile does)
+            if (sx >= 0)
+                dxEz = stretch_virtual_o(dxEz, px.psiH[0] + ((long long)km0 * ny + jw) * px.P, osx, ldo(px.bh, oi),
+                                         ldo(px.ch, oi), ldo(px.kh, oi));
+            if (sy >= 0)
+                dyEz = stretch_virtual_o(dyEz, py.psiH[1] + ((long long)km0 * py.P + sy) * nx, oi, py.bh[jw], py.ch[jw],
+                                         py.kh[jw]);
+            const int sz = pz.on ? slab_slot(km0, pz.lo, pz.hi, nz) : -1;
+            if (sz >= 0) {
+                const long long r = ((long long)sz * ny + jw) * nx;
+                dzEy = stretch_virtual_o(dzEy, pz.psiH[0] + r, oi, pz.bh[km0], pz.ch[km0], pz.kh[km0]);
+                dzEx = stretch_virtual_o(dzEx, pz.psiH[1] + r, oi, pz.bh[km0], pz.ch[km0], pz.kh[km0]);
+            }
+        }
+        hx_km = ld(a.H[0] + bm, o00) - hdt * (dyEz - dzEy);
+        hy_km = ld(a.H[1] + bm, o00) - hdt * (dzEx - dxEz);
         if constexpr (!CLS) {
             const Maps m = load_maps(km0);
             pe00 = m.e00; pe10 = m.e10; pe01 = m.e01;
@@ -348,8 +405,8 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
         }
         ex0 = exk1;
         ey0 = eyk1;
-        exm = ldp(a.E[0] + b, o10);
-        eym = ldp(a.E[1] + b, o01);
+        exm = ld(a.E[0] + b, o10);
+        eym = ld(a.E[1] + b, o01);
     }
     coefs(load_maps(k0));
 
@@ -359,46 +416,137 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
         T *Jx = a.J[0] + b, *Jy = a.J[1] + b, *Jz = a.J[2] + b;
         const EdgeCoef<T> qx = cx, qy = cy, qz = cz;
         T jx = T(0), jy = T(0), jz = T(0);
-        if (qx.cj > T(0)) jx = ldp(Jx, o00);
-        if (qy.cj > T(0)) jy = ldp(Jy, o00);
-        if (qz.cj > T(0)) jz = ldp(Jz, o00);
+        if (qx.cj > T(0)) jx = ld(Jx, o00);
+        if (qy.cj > T(0)) jy = ld(Jy, o00);
+        if (qz.cj > T(0)) jz = ld(Jz, o00);
         const T *Ex = a.E[0] + b, *Ey = a.E[1] + b, *Ez = a.E[2] + b;
         const T *Hx = a.H[0] + b, *Hy = a.H[1] + b, *Hz = a.H[2] + b;
         // E^n of this plane and the next
-        const T ex_yp = ldp(Ex, oyp), exm_yp = ldp(Ex, oxm_yp), ex_ym = ldp(Ex, o01);
-        const T ey_xp = ldp(Ey, oxp), ey_xm = ldp(Ey, o10), eym_xp = ldp(Ey, oxp_ym);
-        const T ez = ldp(Ez, o00), ez_xp = ldp(Ez, oxp), ez_yp = ldp(Ez, oyp), ez_xm = ldp(Ez, o10), ez_ym = ldp(Ez, o01);
-        const T ex1 = ldp(a.E[0] + bp, o00), exm1 = ldp(a.E[0] + bp, o10);
-        const T ey1 = ldp(a.E[1] + bp, o00), eym1 = ldp(a.E[1] + bp, o01);
+        const T ex_yp = ld(Ex, oyp), exm_yp = ld(Ex, oxm_yp), ex_ym = ld(Ex, o01);
+        const T ey_xp = ld(Ey, oxp), ey_xm = ld(Ey, o10), eym_xp = ld(Ey, oxp_ym);
+        const T ez = ld(Ez, o00), ez_xp = ld(Ez, oxp), ez_yp = ld(Ez, oyp), ez_xm = ld(Ez, o10), ez_ym = ld(Ez, o01);
+        const T ex1 = ld(a.E[0] + bp, o00), exm1 = ld(a.E[0] + bp, o10);
+        const T ey1 = ld(a.E[1] + bp, o00), eym1 = ld(a.E[1] + bp, o01);
         // H^{n-1/2}: own faces, Hz and Hy at x-1, Hz and Hx at y-1
-        const T hx = ldp(Hx, o00), hy = ldp(Hy, o00), hz = ldp(Hz, o00);
-        const T hz_xm = ldp(Hz, o10), hy_xm = ldp(Hy, o10), hz_ym = ldp(Hz, o01), hx_ym = ldp(Hx, o01);
+        const T hx = ld(Hx, o00), hy = ld(Hy, o00), hz = ld(Hz, o00);
+        const T hz_xm = ld(Hz, o10), hy_xm = ld(Hy, o10), hz_ym = ld(Hz, o01), hx_ym = ld(Hx, o01);
         const auto mn = load_maps(k + 1 < nz ? k + 1 : k);
 
-        // H^{n+1/2} with the H pass's arithmetic
-        const T nhx = hx - hdt * ((ez_yp - ez) * rdy - (ey1 - ey0) * rdz);
-        const T nhy = hy - hdt * ((ex1 - ex0) * rdz - (ez_xp - ez) * rdx);
-        const T nhz = hz - hdt * ((ey_xp - ey0) * rdx - (ex_yp - ex0) * rdy);
-        const T nhz_xm = hz_xm - hdt * ((ey0 - ey_xm) * rdx - (exm_yp - exm) * rdy);
-        const T nhy_xm = hy_xm - hdt * ((exm1 - exm) * rdz - (ez - ez_xm) * rdx);
-        const T nhz_ym = hz_ym - hdt * ((eym_xp - eym) * rdx - (ex0 - ex_ym) * rdy);
-        const T nhx_ym = hx_ym - hdt * ((ez - ez_ym) * rdy - (eym1 - eym) * rdz);
+        [[maybe_unused]] T qh0 = T(0), qh1 = T(0), qh1ym = T(0), qm0 = T(0), qm1 = T(0), qe0 = T(0), qe1 = T(0);
+        if constexpr (PML) {
+            if (xv) {
+                const long long r = ((long long)k * ny + jw) * px.P, rym = ((long long)k * ny + jmw) * px.P;
+                qh0 = ldo(px.psiH[0] + r, osxc);
+                qh1 = ldo(px.psiH[1] + r, osxc);
+                qh1ym = ldo(px.psiH[1] + rym, osxc);
+                qm0 = ldo(px.psiH[0] + r, osxmc);
+                qm1 = ldo(px.psiH[1] + r, osxmc);
+                qe0 = ldo(px.psiE[0] + r, osxc);
+                qe1 = ldo(px.psiE[1] + r, osxc);
+            }
+        }
+
+        // H^{n+1/2} with the H pass's arithmetic: own faces, Hz and Hy at x-1, Hz and Hx at y-1
+        T dyEz = (ez_yp - ez) * rdy, dzEy = (ey1 - ey0) * rdz;              // Hx
+        T dzEx = (ex1 - ex0) * rdz, dxEz = (ez_xp - ez) * rdx;              // Hy
+        T dxEy = (ey_xp - ey0) * rdx, dyEx = (ex_yp - ex0) * rdy;           // Hz
+        T dxEy_xm = (ey0 - ey_xm) * rdx, dyEx_xm = (exm_yp - exm) * rdy;    // Hz at x-1
+        T dzEx_xm = (exm1 - exm) * rdz, dxEz_xm = (ez - ez_xm) * rdx;       // Hy at x-1
+        T dxEy_ym = (eym_xp - eym) * rdx, dyEx_ym = (ex0 - ex_ym) * rdy;    // Hz at y-1
+        T dyEz_ym = (ez - ez_ym) * rdy, dzEy_ym = (eym1 - eym) * rdz;       // Hx at y-1
+        [[maybe_unused]] int sz = -1;
+        if constexpr (PML) {
+            // stretched differences: the lane's own faces update their variables (old set in,
+            // new set out); the faces at x-1 and y-1 belong to other lanes and only read them
+            sz = pz.on ? slab_slot(k, pz.lo, pz.hi, nz) : -1;
+            if (sx >= 0) {
+                const long long r = ((long long)k * ny + jw) * px.P;
+                T p0, p1, pv;
+                dxEz = stretch_v(dxEz, qh0, xbh, xch, xkh, p0);
+                dxEy = stretch_v(dxEy, qh1, xbh, xch, xkh, p1);
+                dxEy_ym = stretch_v(dxEy_ym, qh1ym, xbh, xch, xkh, pv);
+                sto(px.psiHo[0] + r, osx, p0);
+                sto(px.psiHo[1] + r, osx, p1);
+            }
+            if (sxm >= 0) {
+                T pv;
+                dxEy_xm = stretch_v(dxEy_xm, qm1, xbhm, xchm, xkhm, pv);
+                dxEz_xm = stretch_v(dxEz_xm, qm0, xbhm, xchm, xkhm, pv);
+            }
+            if (sy >= 0) {
+                const long long r = ((long long)k * py.P + sy) * nx;
+                const T bh = py.bh[jw], ch = py.ch[jw], kh = py.kh[jw];
+                dyEx = stretch_to_o(dyEx, py.psiH[0] + r, py.psiHo[0] + r, oi, bh, ch, kh);
+                dyEz = stretch_to_o(dyEz, py.psiH[1] + r, py.psiHo[1] + r, oi, bh, ch, kh);
+                dyEx_xm = stretch_virtual_o(dyEx_xm, py.psiH[0] + r, oim, bh, ch, kh);
+            }
+            if (sym >= 0) {
+                const long long r = ((long long)k * py.P + sym) * nx;
+                const T bh = py.bh[jmw], ch = py.ch[jmw], kh = py.kh[jmw];
+                dyEx_ym = stretch_virtual_o(dyEx_ym, py.psiH[0] + r, oi, bh, ch, kh);
+                dyEz_ym = stretch_virtual_o(dyEz_ym, py.psiH[1] + r, oi, bh, ch, kh);
+            }
+            if (sz >= 0) {
+                const long long r = ((long long)sz * ny + jw) * nx, rym = ((long long)sz * ny + jmw) * nx;
+                const T bh = pz.bh[k], ch = pz.ch[k], kh = pz.kh[k];
+                dzEy = stretch_to_o(dzEy, pz.psiH[0] + r, pz.psiHo[0] + r, oi, bh, ch, kh);
+                dzEx = stretch_to_o(dzEx, pz.psiH[1] + r, pz.psiHo[1] + r, oi, bh, ch, kh);
+                dzEx_xm = stretch_virtual_o(dzEx_xm, pz.psiH[1] + r, oim, bh, ch, kh);
+                dzEy_ym = stretch_virtual_o(dzEy_ym, pz.psiH[0] + rym, oi, bh, ch, kh);
+            }
+        }
+        const T nhx = hx - hdt * (dyEz - dzEy);
+        const T nhy = hy - hdt * (dzEx - dxEz);
+        const T nhz = hz - hdt * (dxEy - dyEx);
+        const T nhz_xm = hz_xm - hdt * (dxEy_xm - dyEx_xm);
+        const T nhy_xm = hy_xm - hdt * (dzEx_xm - dxEz_xm);
+        const T nhz_ym = hz_ym - hdt * (dxEy_ym - dyEx_ym);
+        const T nhx_ym = hx_ym - hdt * (dyEz_ym - dzEy_ym);
         T *Hxo = a.Hout[0] + b, *Hyo = a.Hout[1] + b, *Hzo = a.Hout[2] + b;
         stp_hint<NT>(Hxo, o00, nhx);
         stp_hint<NT>(Hyo, o00, nhy);
         stp_hint<NT>(Hzo, o00, nhz);
 
         // E^{n+1} with the E pass's arithmetic
-        const T dyHz = (nhz - nhz_ym) * rdy, dzHy = (nhy - hy_km) * rdz;  // Ex
-        const T dzHx = (nhx - hx_km) * rdz, dxHz = (nhz - nhz_xm) * rdx;  // Ey
-        const T dxHy = (nhy - nhy_xm) * rdx, dyHx = (nhx - nhx_ym) * rdy;  // Ez
+        T dyHz = (nhz - nhz_ym) * rdy, dzHy = (nhy - hy_km) * rdz;  // Ex
+        T dzHx = (nhx - hx_km) * rdz, dxHz = (nhz - nhz_xm) * rdx;  // Ey
+        T dxHy = (nhy - nhy_xm) * rdx, dyHx = (nhx - nhx_ym) * rdy;  // Ez
+        if constexpr (PML) {  // E-side variables: only this lane touches them, in place
+            if (sx >= 0) {
+                const long long r = ((long long)k * ny + jw) * px.P;
+                T p0, p1;
+                dxHz = stretch_v(dxHz, qe0, xbn, xcn, xkn, p0);  // Ey
+                dxHy = stretch_v(dxHy, qe1, xbn, xcn, xkn, p1);  // Ez
+                sto(px.psiE[0] + r, osx, p0);
+                sto(px.psiE[1] + r, osx, p1);
+            }
+            if (sy >= 0) {
+                const long long r = ((long long)k * py.P + sy) * nx;
+                dyHx = stretch_o(dyHx, py.psiE[0] + r, oi, py.bn[jw], py.cn[jw], py.kn[jw]);  // Ez
+                dyHz = stretch_o(dyHz, py.psiE[1] + r, oi, py.bn[jw], py.cn[jw], py.kn[jw]);  // Ex
+            }
+            if (sz >= 0) {
+                const long long r = ((long long)sz * ny + jw) * nx;
+                dzHy = stretch_o(dzHy, pz.psiE[0] + r, oi, pz.bn[k], pz.cn[k], pz.kn[k]);  // Ex
+                dzHx = stretch_o(dzHx, pz.psiE[1] + r, oi, pz.bn[k], pz.cn[k], pz.kn[k]);  // Ey
+            }
+        }
         if (qx.cj > T(0)) { jx = jx + qx.cj * ex0; stp(Jx, o00, jx); }
         if (qy.cj > T(0)) { jy = jy + qy.cj * ey0; stp(Jy, o00, jy); }
         if (qz.cj > T(0)) { jz = jz + qz.cj * ez; stp(Jz, o00, jz); }
+        T nex = qx.ca * ex0 + qx.cb * ((dyHz - dzHy) - jx);
+        T ney = qy.ca * ey0 + qy.cb * ((dzHx - dxHz) - jy);
+        T nez = qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz);
+        if constexpr (PML) {  // tangential E on the PEC walls
+            const bool wall_z = pz.on && k == 0;
+            nex = (wall_y || wall_z) ? T(0) : nex;
+            ney = (wall_z || wall_x) ? T(0) : ney;
+            nez = (wall_x || wall_y) ? T(0) : nez;
+        }
         T *Exo = a.Eout[0] + b, *Eyo = a.Eout[1] + b, *Ezo = a.Eout[2] + b;
-        stp_hint<NT>(Exo, o00, qx.ca * ex0 + qx.cb * ((dyHz - dzHy) - jx));
-        stp_hint<NT>(Eyo, o00, qy.ca * ey0 + qy.cb * ((dzHx - dxHz) - jy));
-        stp_hint<NT>(Ezo, o00, qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz));
+        stp_hint<NT>(Exo, o00, nex);
+        stp_hint<NT>(Eyo, o00, ney);
+        stp_hint<NT>(Ezo, o00, nez);
         hx_km = nhx;
         hy_km = nhy;
         ex0 = ex1;
@@ -845,25 +993,29 @@ hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T, int TX, int TY, bool NT, bool CLS, bool PML>
+static void launch_fused_cls(const StepArgs<T> &a, int tz, hipStream_t s)
+{
+    const dim3 blk(TX, TY), grd(tile_blocks(a.g, TY, tz, TX));
+    switch (tz) {
+    case 64: hipLaunchKernelGGL((fused_step_kernel<T, TY, 64, CLS, NT, TX, PML>), grd, blk, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((fused_step_kernel<T, TY, 32, CLS, NT, TX, PML>), grd, blk, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((fused_step_kernel<T, TY, 16, CLS, NT, TX, PML>), grd, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((fused_step_kernel<T, TY, 8, CLS, NT, TX, PML>), grd, blk, 0, s, a); break;
+    }
+}
+
 template <typename T, int TX, int TY, bool NT>
 static void launch_fused_tx(const StepArgs<T> &a, long long waves, int max_tz, hipStream_t s)
 {
     const int tz = pick_tile_z(a.g, TY, waves, max_tz, TX);
-    const dim3 blk(TX, TY), grd(tile_blocks(a.g, TY, tz, TX));
+    const bool pml = a.pml[0].on || a.pml[1].on || a.pml[2].on;
     if (a.cls[0]) {
-        switch (tz) {
-        case 64: hipLaunchKernelGGL((fused_step_kernel<T, TY, 64, true, NT, TX>), grd, blk, 0, s, a); break;
-        case 32: hipLaunchKernelGGL((fused_step_kernel<T, TY, 32, true, NT, TX>), grd, blk, 0, s, a); break;
-        case 16: hipLaunchKernelGGL((fused_step_kernel<T, TY, 16, true, NT, TX>), grd, blk, 0, s, a); break;
-        default: hipLaunchKernelGGL((fused_step_kernel<T, TY, 8, true, NT, TX>), grd, blk, 0, s, a); break;
-        }
+        if (pml) launch_fused_cls<T, TX, TY, NT, true, true>(a, tz, s);
+        else launch_fused_cls<T, TX, TY, NT, true, false>(a, tz, s);
     } else {
-        switch (tz) {
-        case 64: hipLaunchKernelGGL((fused_step_kernel<T, TY, 64, false, NT, TX>), grd, blk, 0, s, a); break;
-        case 32: hipLaunchKernelGGL((fused_step_kernel<T, TY, 32, false, NT, TX>), grd, blk, 0, s, a); break;
-        case 16: hipLaunchKernelGGL((fused_step_kernel<T, TY, 16, false, NT, TX>), grd, blk, 0, s, a); break;
-        default: hipLaunchKernelGGL((fused_step_kernel<T, TY, 8, false, NT, TX>), grd, blk, 0, s, a); break;
-        }
+        if (pml) launch_fused_cls<T, TX, TY, NT, false, true>(a, tz, s);
+        else launch_fused_cls<T, TX, TY, NT, false, false>(a, tz, s);
     }
 }
 
@@ -890,6 +1042,21 @@ hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s)
         else launch_fused_tx<T, 64, C::fy, false>(a, C::f_waves, C::fz_max, s);
     }
     return hipGetLastError();
+}
+
+// With its CPML code the FP64 fused sweep holds ~154 VGPRs (3 waves per SIMD, 3072 on the GPU);
+// below two rounds of such waves the two passes are faster.  Measured: 256 x 128 x 64 with CPML
+// on x and z (4096 waves) 94 us fused vs 85 us; 256^3 with the same slabs (8192 waves) 0.70 vs
+// 0.82 ms; the paper's CPW (64512 waves) 8.76 vs 9.12 ms.  FP32 (5 waves per SIMD) gained on
+// every CPML grid measured but one (512 x 256 x 128, within 4 %).
+template <typename T>
+bool fused_step_pays(const StepArgs<T> &a)
+{
+    if (sizeof(T) != 8 || !(a.pml[0].on || a.pml[1].on || a.pml[2].on)) return true;
+    using C = FwdTiles<T>;
+    const int tz = pick_tile_z(a.g, C::fy, C::f_waves, C::fz_max, kTileX);
+    const long long waves = (long long)tile_blocks(a.g, C::fy, tz, kTileX) * C::fy;
+    return waves >= 2LL * 3 * 4 * 256;
 }
 
 template <typename T>
@@ -971,6 +1138,7 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
     template hipError_t launch_h_pass<T>(const StepArgs<T> &, hipStream_t);                                 \
     template hipError_t launch_e_pass<T>(const StepArgs<T> &, hipStream_t);                                 \
     template hipError_t launch_fused_step<T>(const StepArgs<T> &, hipStream_t);                             \
+    template bool fused_step_pays<T>(const StepArgs<T> &);                                                 \
     template hipError_t launch_class_table<T>(const StepArgs<T> &, const T *, const uint64_t *, int, T *,     \
                                               hipStream_t);                                                 \
     template hipError_t launch_sources<T>(const SrcArgs<T> &, hipStream_t);                                 \

@@ -57,7 +57,10 @@ template <typename T> int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hi
                                   bool probes = true);
 int copy_state(tfl_sim *s, void *dst, const void *src, bool save, hipStream_t st);
 // The fused sweep needs periodic boundaries on every axis.
-bool fused_eligible(const tfl_sim *s);
+// Layout of the fused sweep's buffer: six field arrays (the second E, H set) of
+// the returned stride, then on each CPML axis the second set of its two H-side
+// variables at byte offset psi_at[axis]; *total (if given) is the size.
+size_t fused_layout(const tfl_sim *s, size_t psi_at[3], size_t *total = nullptr);
 // Device pointers of the bound edge classes (x, y, z) and class table; all null when none are bound.
 void class_pointers(const tfl_sim *s, const uint16_t *cls[3], const void **table);
 

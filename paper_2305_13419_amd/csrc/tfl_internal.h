@@ -39,6 +39,7 @@ struct PmlAxis {
     const T *bh, *ch, *kh;  // half-node tables
     T *psiH[2];             // H-side variables (two components)
     T *psiE[2];             // E-side variables (two components)
+    T *psiHo[2];            // where the fused sweep writes the new H-side variables (psiH elsewhere)
 };
 
 template <typename T>
@@ -181,6 +182,9 @@ template <typename T> hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t
 // One whole step in one sweep on grids without CPML: reads E^n (E) and H^{n-1/2} (H), writes
 // E^{n+1} (Eout) and H^{n+1/2} (Hout); Js in place.  E, Eout and H, Hout must not overlap.
 template <typename T> hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s);
+// Whether the fused sweep beats the two passes on this grid (false only for FP64 CPML grids too
+// small to fill the GPU at the fused sweep's occupancy).
+template <typename T> bool fused_step_pays(const StepArgs<T> &a);
 // Class table of the edge-coefficient path: entry c = coefficients of the four cells
 // mat[(tuple[c] >> 16 q) & 0xffff], q = 0..3 (mat: eps_r, sigma, ell per cell material).
 template <typename T>

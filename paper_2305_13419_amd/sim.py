@@ -32,7 +32,7 @@ class Simulation:
     pml : per axis None (periodic) or (lo, hi) absorbing cells (CPML backed by a PEC wall)
     pml_order, pml_scale, kappa_max, alpha_max : CPML grading (tfl_config)
     device : the GPU holding every buffer
-    fused : on grids periodic on every axis, bind a second E, H set so that a step runs as one sweep
+    fused : bind a second E, H set (and H-side CPML variables) so that a step runs as one sweep
     edge_classes : after each set_materials, replace the maps read by the E update with one 16-bit
         class per edge and a coefficient table when the grid has few enough distinct materials
         (the number bound is in ``edge_classes`` afterwards, 0 on the map path); results are
@@ -82,7 +82,7 @@ class Simulation:
         self._call("tfl_bind_state", e3, h3, j3)
         self._call("tfl_bind_workspace", ctypes.c_void_p(self.workspace.data_ptr() if ws.value else 0),
                    ctypes.c_void_p(self.scratch.data_ptr()), _stream())
-        # second E, H set for the one-sweep step on all-periodic grids (fused=False keeps two passes)
+        # second E, H set for the one-sweep step (fused=False keeps two passes)
         fb = ctypes.c_size_t()
         self._call("tfl_fused_buffer_bytes", ctypes.byref(fb))
         self.fused_buffer = None

@@ -134,24 +134,27 @@ def test_buffer_sizes_and_call_order(L):
     assert L.lib().tfl_destroy(h) == 0
 
 
-def test_fused_buffer_only_on_periodic_grids(L):
-    """6 padded fields on an all-periodic grid; none (and binding refused) with a CPML axis."""
+def test_fused_buffer_layout(L):
+    """6 padded fields; with a CPML axis also a second set of that axis's two H-side variables
+    (y slabs: nz x (lo + hi) x nx each), padded to 256 bytes."""
     c = good_config(L)
     rc, h = create(L, c)
     assert rc == 0
     b = ctypes.c_size_t()
+    field = (20 * 10 * 8 * 8 + 255) // 256 * 256
     assert L.lib().tfl_fused_buffer_bytes(h, ctypes.byref(b)) == 0
-    assert b.value == 6 * ((20 * 10 * 8 * 8 + 255) // 256 * 256)
+    assert b.value == 6 * field
     assert L.lib().tfl_bind_fused_buffer(h, ctypes.c_void_p(0x1001)) == L.TFL_E_INVAL  # misaligned
     assert L.lib().tfl_bind_fused_buffer(h, None) == 0
     L.lib().tfl_destroy(h)
     c.bc[1] = L.TFL_CPML
-    c.pml_lo[1], c.pml_hi[1] = 2, 2
+    c.pml_lo[1], c.pml_hi[1] = 2, 3
     rc, h = create(L, c)
     assert rc == 0
-    assert L.lib().tfl_fused_buffer_bytes(h, ctypes.byref(b)) == 0 and b.value == 0
-    assert L.lib().tfl_bind_fused_buffer(h, ctypes.c_void_p(0x1000)) == L.TFL_E_INVAL
-    assert b"periodic" in L.lib().tfl_last_error(h)
+    assert L.lib().tfl_fused_buffer_bytes(h, ctypes.byref(b)) == 0
+    assert b.value == 6 * field + (2 * 8 * 5 * 20 * 8 + 255) // 256 * 256
+    assert L.lib().tfl_bind_fused_buffer(h, ctypes.c_void_p(0x1010)) == L.TFL_E_INVAL
+    assert L.lib().tfl_bind_fused_buffer(h, None) == 0
     L.lib().tfl_destroy(h)
 
 

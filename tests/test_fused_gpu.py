@@ -1,5 +1,7 @@
-"""The fused sweep (H and E updates of a step in one kernel, periodic grids) gives the same
-fields, currents and probe series as the two passes, bit for bit, for odd and even step counts."""
+"""The fused sweep (H and E updates of a step in one kernel) gives the same fields, currents and
+probe series as the two passes, bit for bit, for odd and even step counts, on periodic grids and
+on grids with CPML slabs and PEC walls (where it also carries the H-side auxiliary variables from
+one set to the other)."""
 import numpy as np
 import pytest
 
@@ -68,5 +70,35 @@ def test_fused_row_tiles_and_large_grids_equal_two_pass(shape, dtype):
     print(f"case: fused vs two-pass, roofline boxes {shape}, {dtype}, 3 steps", flush=True)
     a = run_plain(wl, 3, dtype, True)
     b = run_plain(wl, 3, dtype, False)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+CPML_CASES = [((6, 5), None, (4, 7)), ((5, 5), (4, 3), (6, 4)), (None, (3, 4), None), ((0, 0), None, (0, 0))]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("pml", CPML_CASES)
+def test_fused_equals_two_pass_cpml(pml, dtype):
+    # FP64 on CPML grids takes the fused sweep only when its launch has at least 6144 wavefronts
+    # (64 x 4 column tiles, z runs of 8 planes here): 256 x 192 x 64 gives 4 * 48 * 8 * 4 = 6144
+    shape = (256, 192, 64) if dtype == torch.float64 else (66, 21, 40)
+    wl = workloads.random_medium(shape, seed=5, pml=pml)
+    print(f"case: fused vs two-pass, {shape} CPML {pml}, 9 steps in chunks [4, 5], {dtype}", flush=True)
+    a = run(wl, 9, dtype, True, [4, 5])
+    b = run(wl, 9, dtype, False, [4, 5])
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", [(256, 9, 12), (128, 10, 9)])
+def test_fused_row_tiles_cpml_equal_two_pass(shape, dtype):
+    """FP32 rows of 256 or 128 cells with CPML slabs on x and z."""
+    wl = workloads.roofline_grid(shape)
+    wl["pml"] = ((8, 7), None, (3, 2))
+    print(f"case: fused vs two-pass, roofline boxes {shape} with CPML {wl['pml']}, {dtype}, 5 steps", flush=True)
+    a = run_plain(wl, 5, dtype, True)
+    b = run_plain(wl, 5, dtype, False)
     for x, y in zip(a, b):
         assert torch.equal(x, y)
