@@ -447,15 +447,24 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
         }
 
         // H^{n+1/2} with the H pass's arithmetic: own faces, Hz and Hy at x-1, Hz and Hx at y-1
-        T dyEz = (ez_yp - ez) * rdy, dzEy = (ey1 - ey0) * rdz;              // Hx
-        T dzEx = (ex1 - ex0) * rdz, dxEz = (ez_xp - ez) * rdx;              // Hy
-        T dxEy = (ey_xp - ey0) * rdx, dyEx = (ex_yp - ex0) * rdy;           // Hz
-        T dxEy_xm = (ey0 - ey_xm) * rdx, dyEx_xm = (exm_yp - exm) * rdy;    // Hz at x-1
-        T dzEx_xm = (exm1 - exm) * rdz, dxEz_xm = (ez - ez_xm) * rdx;       // Hy at x-1
-        T dxEy_ym = (eym_xp - eym) * rdx, dyEx_ym = (ex0 - ex_ym) * rdy;    // Hz at y-1
-        T dyEz_ym = (ez - ez_ym) * rdy, dzEy_ym = (eym1 - eym) * rdz;       // Hx at y-1
+        T nhx, nhy, nhz, nhz_xm, nhy_xm, nhz_ym, nhx_ym;
         [[maybe_unused]] int sz = -1;
-        if constexpr (PML) {
+        if constexpr (!PML) {
+            nhx = hx - hdt * ((ez_yp - ez) * rdy - (ey1 - ey0) * rdz);
+            nhy = hy - hdt * ((ex1 - ex0) * rdz - (ez_xp - ez) * rdx);
+            nhz = hz - hdt * ((ey_xp - ey0) * rdx - (ex_yp - ex0) * rdy);
+            nhz_xm = hz_xm - hdt * ((ey0 - ey_xm) * rdx - (exm_yp - exm) * rdy);
+            nhy_xm = hy_xm - hdt * ((exm1 - exm) * rdz - (ez - ez_xm) * rdx);
+            nhz_ym = hz_ym - hdt * ((eym_xp - eym) * rdx - (ex0 - ex_ym) * rdy);
+            nhx_ym = hx_ym - hdt * ((ez - ez_ym) * rdy - (eym1 - eym) * rdz);
+        } else {
+            T dyEz = (ez_yp - ez) * rdy, dzEy = (ey1 - ey0) * rdz;              // Hx
+            T dzEx = (ex1 - ex0) * rdz, dxEz = (ez_xp - ez) * rdx;              // Hy
+            T dxEy = (ey_xp - ey0) * rdx, dyEx = (ex_yp - ex0) * rdy;           // Hz
+            T dxEy_xm = (ey0 - ey_xm) * rdx, dyEx_xm = (exm_yp - exm) * rdy;    // Hz at x-1
+            T dzEx_xm = (exm1 - exm) * rdz, dxEz_xm = (ez - ez_xm) * rdx;       // Hy at x-1
+            T dxEy_ym = (eym_xp - eym) * rdx, dyEx_ym = (ex0 - ex_ym) * rdy;    // Hz at y-1
+            T dyEz_ym = (ez - ez_ym) * rdy, dzEy_ym = (eym1 - eym) * rdz;       // Hx at y-1
             // stretched differences: the lane's own faces update their variables (old set in,
             // new set out); the faces at x-1 and y-1 belong to other lanes and only read them
             sz = pz.on ? slab_slot(k, pz.lo, pz.hi, nz) : -1;
@@ -494,59 +503,72 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
                 dzEx_xm = stretch_virtual_o(dzEx_xm, pz.psiH[1] + r, oim, bh, ch, kh);
                 dzEy_ym = stretch_virtual_o(dzEy_ym, pz.psiH[0] + rym, oi, bh, ch, kh);
             }
+            nhx = hx - hdt * (dyEz - dzEy);
+            nhy = hy - hdt * (dzEx - dxEz);
+            nhz = hz - hdt * (dxEy - dyEx);
+            nhz_xm = hz_xm - hdt * (dxEy_xm - dyEx_xm);
+            nhy_xm = hy_xm - hdt * (dzEx_xm - dxEz_xm);
+            nhz_ym = hz_ym - hdt * (dxEy_ym - dyEx_ym);
+            nhx_ym = hx_ym - hdt * (dyEz_ym - dzEy_ym);
         }
-        const T nhx = hx - hdt * (dyEz - dzEy);
-        const T nhy = hy - hdt * (dzEx - dxEz);
-        const T nhz = hz - hdt * (dxEy - dyEx);
-        const T nhz_xm = hz_xm - hdt * (dxEy_xm - dyEx_xm);
-        const T nhy_xm = hy_xm - hdt * (dzEx_xm - dxEz_xm);
-        const T nhz_ym = hz_ym - hdt * (dxEy_ym - dyEx_ym);
-        const T nhx_ym = hx_ym - hdt * (dyEz_ym - dzEy_ym);
         T *Hxo = a.Hout[0] + b, *Hyo = a.Hout[1] + b, *Hzo = a.Hout[2] + b;
         stp_hint<NT>(Hxo, o00, nhx);
         stp_hint<NT>(Hyo, o00, nhy);
         stp_hint<NT>(Hzo, o00, nhz);
 
         // E^{n+1} with the E pass's arithmetic
-        T dyHz = (nhz - nhz_ym) * rdy, dzHy = (nhy - hy_km) * rdz;  // Ex
-        T dzHx = (nhx - hx_km) * rdz, dxHz = (nhz - nhz_xm) * rdx;  // Ey
-        T dxHy = (nhy - nhy_xm) * rdx, dyHx = (nhx - nhx_ym) * rdy;  // Ez
-        if constexpr (PML) {  // E-side variables: only this lane touches them, in place
-            if (sx >= 0) {
-                const long long r = ((long long)k * ny + jw) * px.P;
-                T p0, p1;
-                dxHz = stretch_v(dxHz, qe0, xbn, xcn, xkn, p0);  // Ey
-                dxHy = stretch_v(dxHy, qe1, xbn, xcn, xkn, p1);  // Ez
-                sto(px.psiE[0] + r, osx, p0);
-                sto(px.psiE[1] + r, osx, p1);
+        if constexpr (!PML) {
+            const T dyHz = (nhz - nhz_ym) * rdy, dzHy = (nhy - hy_km) * rdz;  // Ex
+            const T dzHx = (nhx - hx_km) * rdz, dxHz = (nhz - nhz_xm) * rdx;  // Ey
+            const T dxHy = (nhy - nhy_xm) * rdx, dyHx = (nhx - nhx_ym) * rdy;  // Ez
+            if (qx.cj > T(0)) { jx = jx + qx.cj * ex0; stp(Jx, o00, jx); }
+            if (qy.cj > T(0)) { jy = jy + qy.cj * ey0; stp(Jy, o00, jy); }
+            if (qz.cj > T(0)) { jz = jz + qz.cj * ez; stp(Jz, o00, jz); }
+            T *Exo = a.Eout[0] + b, *Eyo = a.Eout[1] + b, *Ezo = a.Eout[2] + b;
+            stp_hint<NT>(Exo, o00, qx.ca * ex0 + qx.cb * ((dyHz - dzHy) - jx));
+            stp_hint<NT>(Eyo, o00, qy.ca * ey0 + qy.cb * ((dzHx - dxHz) - jy));
+            stp_hint<NT>(Ezo, o00, qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz));
+        } else {
+            T dyHz = (nhz - nhz_ym) * rdy, dzHy = (nhy - hy_km) * rdz;  // Ex
+            T dzHx = (nhx - hx_km) * rdz, dxHz = (nhz - nhz_xm) * rdx;  // Ey
+            T dxHy = (nhy - nhy_xm) * rdx, dyHx = (nhx - nhx_ym) * rdy;  // Ez
+            {  // E-side variables: only this lane touches them, in place
+                if (sx >= 0) {
+                    const long long r = ((long long)k * ny + jw) * px.P;
+                    T p0, p1;
+                    dxHz = stretch_v(dxHz, qe0, xbn, xcn, xkn, p0);  // Ey
+                    dxHy = stretch_v(dxHy, qe1, xbn, xcn, xkn, p1);  // Ez
+                    sto(px.psiE[0] + r, osx, p0);
+                    sto(px.psiE[1] + r, osx, p1);
+                }
+                if (sy >= 0) {
+                    const long long r = ((long long)k * py.P + sy) * nx;
+                    dyHx = stretch_o(dyHx, py.psiE[0] + r, oi, py.bn[jw], py.cn[jw], py.kn[jw]);  // Ez
+                    dyHz = stretch_o(dyHz, py.psiE[1] + r, oi, py.bn[jw], py.cn[jw], py.kn[jw]);  // Ex
+                }
+                if (sz >= 0) {
+                    const long long r = ((long long)sz * ny + jw) * nx;
+                    dzHy = stretch_o(dzHy, pz.psiE[0] + r, oi, pz.bn[k], pz.cn[k], pz.kn[k]);  // Ex
+                    dzHx = stretch_o(dzHx, pz.psiE[1] + r, oi, pz.bn[k], pz.cn[k], pz.kn[k]);  // Ey
+                }
             }
-            if (sy >= 0) {
-                const long long r = ((long long)k * py.P + sy) * nx;
-                dyHx = stretch_o(dyHx, py.psiE[0] + r, oi, py.bn[jw], py.cn[jw], py.kn[jw]);  // Ez
-                dyHz = stretch_o(dyHz, py.psiE[1] + r, oi, py.bn[jw], py.cn[jw], py.kn[jw]);  // Ex
+            if (qx.cj > T(0)) { jx = jx + qx.cj * ex0; stp(Jx, o00, jx); }
+            if (qy.cj > T(0)) { jy = jy + qy.cj * ey0; stp(Jy, o00, jy); }
+            if (qz.cj > T(0)) { jz = jz + qz.cj * ez; stp(Jz, o00, jz); }
+            T nex = qx.ca * ex0 + qx.cb * ((dyHz - dzHy) - jx);
+            T ney = qy.ca * ey0 + qy.cb * ((dzHx - dxHz) - jy);
+            T nez = qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz);
+            {  // tangential E on the PEC walls
+                const bool wall_z = pz.on && k == 0;
+                nex = (wall_y || wall_z) ? T(0) : nex;
+                ney = (wall_z || wall_x) ? T(0) : ney;
+                nez = (wall_x || wall_y) ? T(0) : nez;
             }
-            if (sz >= 0) {
-                const long long r = ((long long)sz * ny + jw) * nx;
-                dzHy = stretch_o(dzHy, pz.psiE[0] + r, oi, pz.bn[k], pz.cn[k], pz.kn[k]);  // Ex
-                dzHx = stretch_o(dzHx, pz.psiE[1] + r, oi, pz.bn[k], pz.cn[k], pz.kn[k]);  // Ey
-            }
+            T *Exo = a.Eout[0] + b, *Eyo = a.Eout[1] + b, *Ezo = a.Eout[2] + b;
+            stp_hint<NT>(Exo, o00, nex);
+            stp_hint<NT>(Eyo, o00, ney);
+            stp_hint<NT>(Ezo, o00, nez);
         }
-        if (qx.cj > T(0)) { jx = jx + qx.cj * ex0; stp(Jx, o00, jx); }
-        if (qy.cj > T(0)) { jy = jy + qy.cj * ey0; stp(Jy, o00, jy); }
-        if (qz.cj > T(0)) { jz = jz + qz.cj * ez; stp(Jz, o00, jz); }
-        T nex = qx.ca * ex0 + qx.cb * ((dyHz - dzHy) - jx);
-        T ney = qy.ca * ey0 + qy.cb * ((dzHx - dxHz) - jy);
-        T nez = qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz);
-        if constexpr (PML) {  // tangential E on the PEC walls
-            const bool wall_z = pz.on && k == 0;
-            nex = (wall_y || wall_z) ? T(0) : nex;
-            ney = (wall_z || wall_x) ? T(0) : ney;
-            nez = (wall_x || wall_y) ? T(0) : nez;
-        }
-        T *Exo = a.Eout[0] + b, *Eyo = a.Eout[1] + b, *Ezo = a.Eout[2] + b;
-        stp_hint<NT>(Exo, o00, nex);
-        stp_hint<NT>(Eyo, o00, ney);
-        stp_hint<NT>(Ezo, o00, nez);
         hx_km = nhx;
         hy_km = nhy;
         ex0 = ex1;
