@@ -11,10 +11,11 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def gpu_adjoint(wl, objective, N, seg, dtype, maps=None, edge_classes=True):
+def gpu_adjoint(wl, objective, N, seg, dtype, maps=None, edge_classes=True, fused=True):
     from paper_2305_13419_amd import Simulation
     npdt = np.float64 if dtype == torch.float64 else np.float32
-    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"], edge_classes=edge_classes)
+    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"], edge_classes=edge_classes,
+                     fused=fused)
     sim.set_materials(*[np.asarray(m, dtype=npdt) for m in (maps or wl["maps"])])
     if wl["fields"] is None:
         z = [np.zeros(sim.shape3, dtype=npdt)] * 3

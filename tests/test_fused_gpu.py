@@ -102,3 +102,22 @@ def test_fused_row_tiles_cpml_equal_two_pass(shape, dtype):
     b = run_plain(wl, 5, dtype, False)
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_adjoint_recomputation_fused_equals_two_pass(dtype):
+    """The adjoint's recomputation through the fused sweep (H and the H-side CPML variables
+    alternating between the bound set and the buffer, segments of odd length) gives the gradients
+    of the two-pass recomputation bit for bit; FP64 on a grid large enough for the launch rule."""
+    from tests.test_adjoint_gpu import gpu_adjoint
+    shape = (256, 192, 64) if dtype == torch.float64 else (66, 21, 40)
+    wl = workloads.random_medium(shape, seed=7, pml=((5, 5), (4, 3), (6, 4)), theta=0.8)
+    nx, ny, nz = shape
+    wl["sources"] = [dict(comp=1, box=(nx // 3, nx // 3 + 1, 0, ny, nz // 4, nz // 2), amplitude=2.0,
+                          waveform="mod_gauss", freq=3e14, t0=1.5e-15, tw=6e-16)]
+    obj = (1, (2 * nx // 3, 2 * nx // 3 + 1, 0, ny, 0, nz), 2.5e14)
+    print(f"case: adjoint recomputation fused vs two passes, {shape}, {dtype}, 13 steps, seg 5", flush=True)
+    F1, gl1, gs1 = gpu_adjoint(wl, obj, 13, 5, dtype, fused=True)
+    F0, gl0, gs0 = gpu_adjoint(wl, obj, 13, 5, dtype, fused=False)
+    assert F1 == F0
+    assert np.array_equal(gl1, gl0) and np.array_equal(gs1, gs0)
