@@ -103,18 +103,32 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return gbs
 
 
+KERNEL_SOURCES = ("kernels_fwd.hip", "fdtd_common.h", "tfl_internal.h")
+
+
+def kernel_code_hash():
+    """Hash of the forward kernels' code: their source and the headers they include, with comments,
+    indentation and blank lines removed (a change of comments leaves the kernels as measured)."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        text = open(os.path.join(ROOT, "paper_2305_13419_amd", "csrc", name)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(ln.strip() for ln in text.splitlines() if ln.strip()).encode())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(dtype_name, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when the
-    kernel source changed after the counters were taken."""
+    kernels' code changed after the counters were taken."""
     path = os.path.join(ROOT, "profiles", "forward_kernels_roofline_256cube.md")
-    src = os.path.join(ROOT, "paper_2305_13419_amd", "csrc", "kernels_fwd.hip")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    code = kernel_code_hash()
     for line in open(path):
-        m = re.match(r"TRAFFIC (\w+) (\w+) bytes_per_launch=(\S+) kernels_fwd_sha=(\w+)", line.strip())
+        m = re.match(r"TRAFFIC (\w+) (\w+) bytes_per_launch=(\S+) kernel_code=(\w+)", line.strip())
         if m and m.group(1) == dtype_name and m.group(2) == kernel:
-            return float(m.group(3)) if m.group(4) == sha else None
+            return float(m.group(3)) if m.group(4) == code else None
     return None
 
 

@@ -9,10 +9,9 @@
 // b_e = dt/(eps_e + theta sigma_e dt), i.e. Algorithm 1 step 3 multiplied out.
 // Per-edge materials are formed on the fly from the per-cell maps, or read as
 // one 16-bit class per edge and a coefficient table when classes are bound
-// (the CLS template argument).  On grids
-// without CPML the two sweeps can be replaced by one (fused_step_kernel), which
-// reads the old fields from one set of buffers and writes the new ones to
-// another.
+// (the CLS template argument).  The two sweeps can be replaced by one
+// (fused_step_kernel), which reads the old fields from one set of buffers and
+// writes the new ones to another.
 //
 // Each block owns a column tile of the x-y plane (rows of 64 cells, one
 // wavefront each, 4 or 8 rows; the FP32 fused sweep takes rows of 256 or 128
@@ -250,7 +249,7 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const
 }
 
 // ---------------------------------------------------------------------------
-// Fused step (H and E pass in one sweep, grids without CPML)
+// Fused step (H and E pass in one sweep)
 // ---------------------------------------------------------------------------
 // Each lane updates E at its own edges and H at its own faces.  The E update
 // needs H^{n+1/2} also at the faces x-1 (Hz, Hy) and y-1 (Hz, Hx) of its cell,
@@ -262,7 +261,12 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const
 // 21 + 6 f_J of the two passes (12 + 6 f_J words and three 16-bit classes with
 // edge classes).  NT: the new E and H are stored with a
 // nontemporal hint (chosen at launch for grids well beyond the infinity cache,
-// where keeping them would only evict lines the sweep still reads).
+// where keeping them would only evict lines the sweep still reads).  PML: the
+// CPML variant (an instantiation of its own, so periodic grids run the code
+// without it): the H-side auxiliary variables go from psiH to psiHo (the faces
+// recomputed at x-1 and y-1 read the old values), the E-side ones are updated
+// in place, and tangential E is zeroed on the PEC walls, all with the
+// arithmetic of the two passes.
 template <typename T, int TY, int TZ, bool CLS, bool NT, int TX, bool PML>
 __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const StepArgs<T> a)
 {

@@ -179,8 +179,9 @@ inline int tile_blocks(const GridDims &g, int ty, int tz, int tx = kTileX)
 // Host-side launchers (kernels_fwd.hip).
 template <typename T> hipError_t launch_h_pass(const StepArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t s);
-// One whole step in one sweep on grids without CPML: reads E^n (E) and H^{n-1/2} (H), writes
-// E^{n+1} (Eout) and H^{n+1/2} (Hout); Js in place.  E, Eout and H, Hout must not overlap.
+// One whole step in one sweep: reads E^n (E) and H^{n-1/2} (H), writes E^{n+1} (Eout) and
+// H^{n+1/2} (Hout), and on CPML axes the H-side variables from psiH to psiHo; Js and the E-side
+// variables in place.  E, Eout, H, Hout and psiH, psiHo must not overlap.
 template <typename T> hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s);
 // Whether the fused sweep beats the two passes on this grid (false only for FP64 CPML grids too
 // small to fill the GPU at the fused sweep's occupancy).
