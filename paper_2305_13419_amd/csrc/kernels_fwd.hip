@@ -1036,13 +1036,15 @@ static void launch_fused_tx(const StepArgs<T> &a, long long waves, int max_tz, h
 {
     const int tz = pick_tile_z(a.g, TY, waves, max_tz, TX);
     const bool pml = a.pml[0].on || a.pml[1].on || a.pml[2].on;
-    if (a.cls[0]) {
-        if (pml) launch_fused_cls<T, TX, TY, NT, true, true>(a, tz, s);
-        else launch_fused_cls<T, TX, TY, NT, true, false>(a, tz, s);
-    } else {
-        if (pml) launch_fused_cls<T, TX, TY, NT, false, true>(a, tz, s);
-        else launch_fused_cls<T, TX, TY, NT, false, false>(a, tz, s);
+    if constexpr (TX == kTileX) {  // CPML grids run rows of 64 cells (launch_fused_step)
+        if (pml) {
+            if (a.cls[0]) launch_fused_cls<T, TX, TY, NT, true, true>(a, tz, s);
+            else launch_fused_cls<T, TX, TY, NT, false, true>(a, tz, s);
+            return;
+        }
     }
+    if (a.cls[0]) launch_fused_cls<T, TX, TY, NT, true, false>(a, tz, s);
+    else launch_fused_cls<T, TX, TY, NT, false, false>(a, tz, s);
 }
 
 template <typename T>
@@ -1054,19 +1056,26 @@ hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s)
     // step finds them there (128^3 runs 1.5x faster with ordinary stores)
     const double touched = (double)a.g.sxy * a.g.nz * (15.0 * sizeof(T) + 6.0);
     const bool nt = touched > 512.0 * 1024 * 1024;
-    // FP32: rows of 256 (or 128) cells per block when they tile the x extent exactly (4 or 2
-    // wavefronts per row, no x halo between them; 256^3: 282 -> 267 us); FP64 gains nothing from it
-    const int tx = (sizeof(T) == 4 && a.g.nx % 256 == 0) ? 256 : (sizeof(T) == 4 && a.g.nx % 128 == 0) ? 128 : 64;
-    if (tx == 256) {
-        if (nt) launch_fused_tx<T, 256, 2, true>(a, C::f_waves, C::fz_max, s);
-        else launch_fused_tx<T, 256, 2, false>(a, C::f_waves, C::fz_max, s);
-    } else if (tx == 128) {
-        if (nt) launch_fused_tx<T, 128, 2, true>(a, C::f_waves, C::fz_max, s);
-        else launch_fused_tx<T, 128, 2, false>(a, C::f_waves, C::fz_max, s);
-    } else {
-        if (nt) launch_fused_tx<T, 64, C::fy, true>(a, C::f_waves, C::fz_max, s);
-        else launch_fused_tx<T, 64, C::fy, false>(a, C::f_waves, C::fz_max, s);
+    // FP32 on periodic grids: rows of 256 (or 128) cells per block when they tile the x extent
+    // exactly (4 or 2 wavefronts per row, no x halo between them; 256^3: 282 -> 267 us).  FP64
+    // gains nothing from it, and with CPML slabs rows of 64 cells were as fast or faster (512 x 256
+    // x 128 CPW: 0.414 vs 0.431 ms; 256^3 with slabs 0.343 vs 0.349 ms).
+    const bool pml = a.pml[0].on || a.pml[1].on || a.pml[2].on;
+    if constexpr (sizeof(T) == 4) {
+        const int tx = pml ? kTileX : (a.g.nx % 256 == 0) ? 256 : (a.g.nx % 128 == 0) ? 128 : kTileX;
+        if (tx == 256) {
+            if (nt) launch_fused_tx<T, 256, 2, true>(a, C::f_waves, C::fz_max, s);
+            else launch_fused_tx<T, 256, 2, false>(a, C::f_waves, C::fz_max, s);
+            return hipGetLastError();
+        }
+        if (tx == 128) {
+            if (nt) launch_fused_tx<T, 128, 2, true>(a, C::f_waves, C::fz_max, s);
+            else launch_fused_tx<T, 128, 2, false>(a, C::f_waves, C::fz_max, s);
+            return hipGetLastError();
+        }
     }
+    if (nt) launch_fused_tx<T, kTileX, C::fy, true>(a, C::f_waves, C::fz_max, s);
+    else launch_fused_tx<T, kTileX, C::fy, false>(a, C::f_waves, C::fz_max, s);
     return hipGetLastError();
 }
 

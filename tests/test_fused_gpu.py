@@ -94,7 +94,8 @@ def test_fused_equals_two_pass_cpml(pml, dtype):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("shape", [(256, 9, 12), (128, 10, 9)])
 def test_fused_row_tiles_cpml_equal_two_pass(shape, dtype):
-    """FP32 rows of 256 or 128 cells with CPML slabs on x and z."""
+    """Grids whose FP32 rows would be 256 or 128 cells wide on periodic grids, with CPML slabs on x
+    and z (where the fused sweep takes rows of 64 cells)."""
     wl = workloads.roofline_grid(shape)
     wl["pml"] = ((8, 7), None, (3, 2))
     print(f"case: fused vs two-pass, roofline boxes {shape} with CPML {wl['pml']}, {dtype}, 5 steps", flush=True)
