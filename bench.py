@@ -14,7 +14,7 @@ against its checkpointed forward run.  Prints one JSON line.
                                  # gradient over 512 steps (several minutes)
     python bench.py --table1     # the paper's skin-depth sweep, 12 rows (about 8 minutes)
     python bench.py --paper-cpw  # step rate on the paper's CPW resonator at its own size, 4 film cases
-    python bench.py --paper-cpw-q 1,2   # Q and f of film cases 1 and 2 at dz = 200 nm (~8 min per case)
+    python bench.py --paper-cpw-q 1,2   # Q and f of film cases 1 and 2 at dz = 200 nm (~7 min per case)
 """
 import argparse
 import hashlib
