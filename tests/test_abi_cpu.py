@@ -156,6 +156,16 @@ def test_fused_buffer_layout(L):
     assert L.lib().tfl_bind_fused_buffer(h, ctypes.c_void_p(0x1010)) == L.TFL_E_INVAL
     assert L.lib().tfl_bind_fused_buffer(h, None) == 0
     L.lib().tfl_destroy(h)
+    # all three axes: x slabs nz x ny x P, y slabs nz x P x nx, z slabs P x ny x nx (P = lo + hi)
+    c.bc[0], c.bc[2] = L.TFL_CPML, L.TFL_CPML
+    c.pml_lo[0], c.pml_hi[0] = 3, 2
+    c.pml_lo[2], c.pml_hi[2] = 1, 2
+    rc, h = create(L, c)
+    assert rc == 0
+    assert L.lib().tfl_fused_buffer_bytes(h, ctypes.byref(b)) == 0
+    r256 = lambda n: (n + 255) // 256 * 256
+    assert b.value == 6 * field + r256(2 * 8 * 10 * 5 * 8) + r256(2 * 8 * 5 * 20 * 8) + r256(2 * 3 * 10 * 20 * 8)
+    L.lib().tfl_destroy(h)
 
 
 def test_edge_class_buffer_size_and_call_order(L):
