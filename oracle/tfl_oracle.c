@@ -38,7 +38,10 @@
  *     sample 0 is the state passed to oracle_set_fields.
  *
  * The code favours plain loops over speed: every array is a full grid and
- * every neighbour index is wrapped explicitly.
+ * every neighbour index is wrapped explicitly.  The grid sweeps are split over
+ * z-planes (or elements) with OpenMP when there are several; each element is
+ * written by one thread from values no thread writes in the same loop, so the
+ * results do not depend on the thread count.
  */
 #include <math.h>
 #include <stdint.h>
@@ -94,7 +97,16 @@ typedef struct {
     o_probe probe[O_MAXPROBE];
 } oracle_sim;
 
-static long o_wrap(long i, long n) { long r = i % n; return r < 0 ? r + n : r; }
+/* Index wrap onto [0, n): the stencils step at most one cell past an end, so
+ * those cases are tested first; any other index takes the general modulo. */
+static long o_wrap(long i, long n)
+{
+    if (i >= 0 && i < n) return i;
+    if (i == -1) return n - 1;
+    if (i == n) return 0;
+    long r = i % n;
+    return r < 0 ? r + n : r;
+}
 
 static long o_idx(const oracle_sim *s, long i, long j, long k)
 {
@@ -260,7 +272,7 @@ static void o_half_B(oracle_sim *s, int advance_psi)
 {
     double h = 0.5 * s->dt;
     for (int c = 0; c < 3; ++c) {
-#pragma omp parallel for
+#pragma omp parallel for if (s->n[2] > 1)
         for (long k = 0; k < s->n[2]; ++k)
             for (long j = 0; j < s->n[1]; ++j)
                 for (long i = 0; i < s->n[0]; ++i) {
@@ -276,7 +288,7 @@ static void o_half_B(oracle_sim *s, int advance_psi)
 static void o_advance_psiB(oracle_sim *s)
 {
     for (int c = 0; c < 3; ++c) {
-#pragma omp parallel for
+#pragma omp parallel for if (s->n[2] > 1)
         for (long k = 0; k < s->n[2]; ++k)
             for (long j = 0; j < s->n[1]; ++j)
                 for (long i = 0; i < s->n[0]; ++i) {
@@ -291,6 +303,7 @@ static void o_half_J(oracle_sim *s)
 {
     for (int c = 0; c < 3; ++c) {
         long N = o_cells(s);
+#pragma omp parallel for if (N > 65536)
         for (long e = 0; e < N; ++e) {
             if (s->ell[c][e] > 0.0) /* superconducting edges only */
                 s->J[c][e] += 0.5 * s->dt * s->E[c][e] * s->ell[c][e] / O_MU0;
@@ -330,11 +343,12 @@ static void o_full_E(oracle_sim *s)
     double *H[3];
     for (int c = 0; c < 3; ++c) {
         H[c] = (double *)malloc((size_t)N * sizeof(double));
+#pragma omp parallel for if (N > 65536)
         for (long e = 0; e < N; ++e) H[c][e] = s->B[c][e] / O_MU0;
     }
     for (int c = 0; c < 3; ++c) {
         int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-#pragma omp parallel for
+#pragma omp parallel for if (s->n[2] > 1)
         for (long k = 0; k < s->n[2]; ++k)
             for (long j = 0; j < s->n[1]; ++j)
                 for (long i = 0; i < s->n[0]; ++i) {
