@@ -535,3 +535,79 @@ def test_table1_row_100THz_sigma1e4_reproduced_by_the_oracle():
     delta = wl["z0"] / np.log(a0 / a1)
     assert abs(delta / cf.discrete_skin_depth(1e14, 10e-9, wl["dt"], 1.0, 1.0, 1e4, ell) - 1) < 1e-4
     assert abs(delta * 1e9 - 450) < 0.5 and abs(theory * 1e9 - 447.92) < 0.01
+
+
+# ---------------------------------------------------------------------------
+# Reflection coefficient versus frequency (Sec. 4.2, Eqs. beta, Ref, beta_cases)
+# ---------------------------------------------------------------------------
+def _reflection_runs():
+    """The paper's 1-D reflection experiment on the oracle: 4480 cells of 20 nm (z in [0, 89.6] um, here
+    along x), vacuum below 7 um, a superconductor (lambda_L = 100 nm, sigma = 0 or 1e4 S/m) above, CPML
+    of 32 cells outside both ends, dt = 0.95 dz / c, 15 800 steps, a soft Ey Gaussian pulse at 100 nm,
+    Ey recorded at 6.8 um in each run and in an all-vacuum run.  Reading: the printed pulse width
+    t_w = 1/(2f) with f = 100 THz (5 fs) carries no energy near the sigma = 0 cutoff (~477 THz) that the
+    paper reports measuring, so the width is taken as 0.5 fs (t0 = 4 t_w), which covers 0-1000 THz."""
+    d, ndom, npml, steps = 20e-9, 4480, 32, 15800
+    n = ndom + 2 * npml
+    dt = 0.95 * d / cf.C0
+    tw = 0.5e-15
+    i_src, i_obs, i_sc = npml + 5, npml + 340, npml + 350
+    ell = 1 / (100e-9) ** 2
+
+    def run(sig, sc):
+        shp = (1, 1, n)
+        s, l = np.zeros(shp), np.zeros(shp)
+        if sc:
+            s[..., i_sc:] = sig
+            l[..., i_sc:] = ell
+        o = OracleSim((n, 1, 1), (d, 1.0, 1.0), dt, 1.0, pml=(1, 0, 0), npml=((npml, npml), (0, 0), (0, 0)))
+        o.set_materials(np.ones(shp), s, l)
+        o.set_fields(zeros(shp), zeros(shp), zeros(shp))
+        o.add_source(1, (i_src, i_src + 1, 0, 1, 0, 1), 1.0, 1, 0.0, 4 * tw, tw)
+        p = o.add_probe(1, (i_obs, i_obs + 1, 0, 1, 0, 1), steps + 1, [])
+        o.step(steps)
+        return o.probe(p)[0]
+
+    vac = run(0.0, False)
+    f = np.fft.rfftfreq(vac.size, dt)
+    Fi = np.fft.rfft(vac)
+    out = {}
+    for sig in (0.0, 1e4):
+        Fr = np.fft.rfft(run(sig, True) - vac)  # reflected = total - incident (the paper's method)
+        out[sig] = np.abs(Fr) ** 2 / np.abs(Fi) ** 2
+    band = np.abs(Fi) > 1e-3 * np.abs(Fi).max()
+    band[0] = False
+    return f, out, band, dict(d=d, dt=dt, ell=ell)
+
+
+def test_reflection_versus_frequency():
+    """R(f) = |E_r / E_i|^2 from the time series matches the discrete scheme's own normal-incidence
+    reflection (frequency-domain recurrence, closed_forms.discrete_reflection, an independent formula)
+    bin by bin, and the continuum Eq. Ref within the paper's 10 % wherever R > 0.4, except within 1 THz
+    of the sigma = 0 cutoff, where the continuum (477.13 THz) and discrete (477.85 THz) cutoffs differ
+    and R falls steeply between them.  For sigma = 0, R = 1 below the cutoff and drops at the first
+    frequency bin above the discrete cutoff (the paper prints 478.75 THz; Eq. beta_cases gives 477.13)."""
+    f, R, band, p = _reflection_runs()
+    fc_cont = cf.cutoff_frequency(p["ell"])
+    # discrete cutoff: K^2 = mu0 eps0 Omega^2 - ell = 0 with Omega = (2/dt) sin(omega dt / 2)
+    fc_disc = np.arcsin(cf.C0 * p["dt"] * np.sqrt(p["ell"]) / 2) / (np.pi * p["dt"])
+    assert abs(fc_disc - 477.85e12) < 0.01e12
+    for sig, tol_disc in ((1e4, 1e-4), (0.0, 1e-2)):
+        sc = (1.0, sig, p["ell"])
+        fb = f[band]
+        Rd = np.array([abs(cf.discrete_reflection(x, p["d"], p["dt"], 1.0, (1.0, 0.0, 0.0), sc, m0=sc)) ** 2
+                       for x in fb])
+        Rm = R[sig][band]
+        assert np.max(np.abs(Rm - Rd)) <= tol_disc, (sig, np.max(np.abs(Rm - Rd)))
+        Rc = cf.reflection(fb, 1.0, 1.0, sig, p["ell"])
+        sel = (Rc > 0.4) & ~((fb > fc_cont - 1e12) & (fb < fc_disc + 1e12))
+        assert np.max(np.abs(Rm[sel] / Rc[sel] - 1)) <= 0.10, (sig, np.max(np.abs(Rm[sel] / Rc[sel] - 1)))
+        assert fb[sel].max() > 400e12  # the comparison reaches the high-R band's upper end
+    R0 = R[0.0][band]
+    fb = f[band]
+    assert np.all(R0[fb < fc_cont - 2e12] > 0.995)
+    first_low = fb[np.argmax(R0 < 0.95)]
+    assert fc_disc < first_low < fc_disc + (f[1] - f[0])
+    # sigma > 0: R falls smoothly from ~1 (Sec. 4.2): no cutoff
+    R4 = R[1e4][band]
+    assert R4[fb < 60e12].min() > 0.98 and np.all(np.diff(R4[(fb > 10e12) & (fb < 1e15)]) < 1e-3)
