@@ -177,7 +177,7 @@ int tfl_bind_fused_buffer(tfl_sim *sim, void *buffer);
  * otherwise it takes the mean of (eps_r, sigma) over all four. */
 int tfl_bind_materials(tfl_sim *sim, const void *eps_r, const void *sigma_n, const void *inv_lambda2, void *stream);
 
-/* Edge-coefficient classes (optional; forward sweeps only).  The E update of
+/* Edge-coefficient classes (optional; forward and adjoint sweeps).  The E update of
  * an edge uses three coefficients fixed by the four cells sharing it (Sec. 3
  * edge rule, Algorithm 1 step 3): E^{n+1} = ca E^n + cb (curl H - Js^{n+1/2}),
  * Js^{n+1/2} = Js^{n-1/2} + cj E^n.  When the grid holds few distinct
@@ -198,8 +198,10 @@ int tfl_bind_materials(tfl_sim *sim, const void *eps_r, const void *sigma_n, con
  * *nclasses (may be NULL) receives the number of classes.  TFL_E_RANGE, with
  * the simulation left on the map path, when the grid has more than 65536
  * distinct cell materials or more than TFL_MAX_EDGE_CLASSES distinct edge
- * materials; TFL_E_STATE without bound maps.  A NULL buffer unbinds.  The
- * adjoint sweeps always read the maps. */
+ * materials; TFL_E_STATE without bound maps.  A NULL buffer unbinds.  With
+ * classes bound, the adjoint's edge sweep reads them as well (the same
+ * coefficients); the adjoint's gather of per-edge gradients onto cells and the
+ * integer-time half kicks read the maps. */
 #define TFL_MAX_EDGE_CLASSES 65535
 int tfl_edge_class_bytes(const tfl_sim *sim, size_t *bytes);
 int tfl_bind_edge_classes(tfl_sim *sim, void *buffer, int *nclasses, void *stream);
@@ -218,6 +220,18 @@ int tfl_clear_sources_probes(tfl_sim *sim);
 
 /* Advance nsteps >= 0 time steps (Algorithm 1), with sources and probes. */
 int tfl_step(tfl_sim *sim, int64_t nsteps, void *stream);
+
+/* Optional non-finite check (a guard for long runs; off by default).  With
+ * every > 0, each step of tfl_step and tfl_forward_checkpointed whose new step
+ * index is a multiple of `every` is followed by a device count of the NaN and
+ * Inf values in E, H and Js.  A call during which a check ran reads the counts
+ * back at its end, synchronising `stream`, and returns TFL_E_NONFINITE (the
+ * message gives the count and the first step index where one was seen) if any
+ * was found; all nsteps steps are still taken, and a checkpointed run that
+ * fails the check leaves no run for tfl_adjoint.  every = 0 turns the check
+ * off.  TFL_E_INVAL when every < 0.  The counters live in the scratch buffer.
+ * (Stability is otherwise guarded by the dt bound of tfl_bind_materials.) */
+int tfl_set_nonfinite_check(tfl_sim *sim, int64_t every);
 
 /* tfl_step with HIP events recorded on `stream` around each pass of every
  * step; returns the summed device time of the H passes and of the E passes
@@ -292,7 +306,10 @@ int tfl_forward_checkpointed(tfl_sim *sim, const tfl_objective *obj, int64_t nst
  * fused buffer is bound (as tfl_step; same results).  On return the state
  * arrays (and the fused buffer) hold intermediate values of the
  * recomputation: load a saved state (and set the step index) before stepping
- * again.  TFL_E_STATE if no matching forward run exists. */
+ * again.  TFL_E_STATE if no matching forward run exists: none was made, it had
+ * another nsteps, seg or objective, or the maps (tfl_bind_materials) or the
+ * sources (tfl_add_source, tfl_clear_sources_probes) changed after it, since the
+ * recomputation would then not reproduce the run whose checkpoints are stored. */
 int tfl_adjoint(tfl_sim *sim, const tfl_objective *obj, int64_t nsteps, int64_t seg, const void *ckpt,
                 const double F[2], void *snap, void *adj, double *grad_ell, double *grad_sigma, void *stream);
 

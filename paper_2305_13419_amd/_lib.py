@@ -112,6 +112,7 @@ SIGNATURES = {
     "tfl_add_probe": [P, ctypes.POINTER(tfl_probe), ctypes.POINTER(ctypes.c_int)],
     "tfl_clear_sources_probes": [P],
     "tfl_step": [P, ctypes.c_int64, P],
+    "tfl_set_nonfinite_check": [P, ctypes.c_int64],
     "tfl_profile_step": [P, ctypes.c_int64, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "tfl_sync_integer_time": [P, PP, PP, P],
     "tfl_energy": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), P],

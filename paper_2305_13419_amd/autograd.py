@@ -42,6 +42,9 @@ class AdjointProblem:
         else:
             self.ckpt, self.snap, self.work = self.sim.adjoint_buffers(self.nsteps, self.seg)
         self.F = None
+        # forward runs made so far: a backward must belong to the latest one, since the checkpoints,
+        # F and the maps of the problem are those of its last forward run
+        self.generation = 0
 
     def _reset(self, inv_lambda2, sigma):
         sim = self.sim
@@ -55,6 +58,7 @@ class AdjointProblem:
     def forward(self, inv_lambda2, sigma):
         self._reset(inv_lambda2, sigma)
         self.F = self.sim.forward_checkpointed(self.objective, self.nsteps, self.seg, self.ckpt)
+        self.generation += 1
         return abs(self.F) ** 2
 
     def gradient(self):
@@ -69,11 +73,15 @@ class TwoFluidObjective(torch.autograd.Function):
     def forward(ctx, inv_lambda2, sigma, problem):
         J = problem.forward(inv_lambda2.detach(), sigma.detach())
         ctx.problem = problem
+        ctx.generation = problem.generation
         ctx.dtypes = (inv_lambda2.dtype, sigma.dtype)
         return torch.tensor(J, dtype=torch.float64, device=inv_lambda2.device)
 
     @staticmethod
     def backward(ctx, grad_out):
+        if ctx.problem.generation != ctx.generation:
+            raise RuntimeError("the AdjointProblem ran another forward pass after this one; its checkpoints and "
+                               "maps now belong to that run, so this graph's gradient can no longer be formed")
         gl, gs = ctx.problem.gradient()
         g = grad_out.to(torch.float64)
         return (g * gl).to(ctx.dtypes[0]), (g * gs).to(ctx.dtypes[1]), None

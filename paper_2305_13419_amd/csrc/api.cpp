@@ -239,6 +239,18 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
             pa.n = s->step;
             if ((e = launch_probes<T>(pa, np, st)) != hipSuccess) return hip_fail(s, e, "probe");
         }
+        if (s->checking && s->check_every > 0 && s->step % s->check_every == 0) {
+            NonfiniteArgs<T> na{};
+            for (int q = 0; q < 3; ++q) {
+                na.f[q] = sa.E[q];
+                na.f[3 + q] = inB ? ab.Hout[q] : a.H[q];
+                na.f[6 + q] = a.J[q];
+            }
+            na.n = a.g.sxy * a.g.nz;
+            auto *ctr = (unsigned long long *)((char *)s->scratch + kNonfiniteOffset);
+            if ((e = launch_nonfinite<T>(na, ctr, s->step, st)) != hipSuccess) return hip_fail(s, e, "non-finite check");
+            s->checked = true;
+        }
     }
     if (ev && nsteps > 0 && (e = hipEventRecord(ev[2 * nsteps], st)) != hipSuccess) return hip_fail(s, e, "event");
     return TFL_OK;
@@ -254,6 +266,35 @@ int upload_probes(tfl_sim *s, hipStream_t st)
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host vector may change after return
     if (e != hipSuccess) return hip_fail(s, e, "probe descriptor upload");
     s->probes_dirty = false;
+    return TFL_OK;
+}
+
+int nonfinite_begin(tfl_sim *s, hipStream_t st)
+{
+    s->checking = s->check_every > 0;
+    s->checked = false;
+    if (!s->checking) return TFL_OK;
+    hipError_t e = launch_nonfinite_reset((unsigned long long *)((char *)s->scratch + kNonfiniteOffset), st);
+    if (e != hipSuccess) {
+        s->checking = false;
+        return hip_fail(s, e, "non-finite check reset");
+    }
+    return TFL_OK;
+}
+
+int nonfinite_end(tfl_sim *s, hipStream_t st)
+{
+    const bool ran = s->checking && s->checked;
+    s->checking = false;
+    s->checked = false;
+    if (!ran) return TFL_OK;
+    unsigned long long r[2];
+    hipError_t e = hipMemcpyAsync(r, (char *)s->scratch + kNonfiniteOffset, sizeof(r), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(s, e, "non-finite check readback");
+    if (r[0] != 0)
+        return fail(s, TFL_E_NONFINITE, "%llu non-finite values in E, H and Js, first seen after step %llu", r[0],
+                    r[1]);
     return TFL_OK;
 }
 
@@ -458,6 +499,7 @@ int tfl_bind_materials(tfl_sim *s, const void *eps_r, const void *sigma_n, const
     if (!s->work_bound) return fail(s, TFL_E_STATE, "bind the workspace (scratch) before the materials");
     s->cls = nullptr;  // edge classes are a snapshot of the previous maps
     s->ncls = 0;
+    s->ckpt_valid = false;  // a checkpointed run of the previous maps no longer matches a recomputation
     if (!eps_r || !sigma_n || !inv_lambda2) return fail(s, TFL_E_INVAL, "null map pointer");
     if (!aligned(eps_r) || !aligned(sigma_n) || !aligned(inv_lambda2))
         return fail(s, TFL_E_INVAL, "map pointers must be 256-byte aligned");
@@ -536,6 +578,7 @@ int tfl_add_source(tfl_sim *s, const tfl_source *src, int *id)
     d.t0 = src->t0;
     d.tw = src->tw;
     s->src.push_back(d);
+    s->ckpt_valid = false;  // the recomputation of a checkpointed run would add this source
     if (id) *id = (int)s->src.size() - 1;
     return TFL_OK;
 }
@@ -572,6 +615,7 @@ int tfl_clear_sources_probes(tfl_sim *s)
     s->src.clear();
     s->probe.clear();
     s->probes_dirty = true;
+    s->ckpt_valid = false;
     return TFL_OK;
 }
 
@@ -581,7 +625,18 @@ int tfl_step(tfl_sim *s, int64_t nsteps, void *stream)
     if (rc != TFL_OK) return rc;
     if (nsteps < 0) return fail(s, TFL_E_INVAL, "nsteps must be >= 0");
     hipStream_t st = (hipStream_t)stream;
-    return s->esz == 8 ? do_step<double>(s, nsteps, st) : do_step<float>(s, nsteps, st);
+    if ((rc = nonfinite_begin(s, st)) != TFL_OK) return rc;
+    rc = s->esz == 8 ? do_step<double>(s, nsteps, st) : do_step<float>(s, nsteps, st);
+    const int rc2 = nonfinite_end(s, st);
+    return rc != TFL_OK ? rc : rc2;
+}
+
+int tfl_set_nonfinite_check(tfl_sim *s, int64_t every)
+{
+    if (!s) return fail(nullptr, TFL_E_INVAL, "null handle");
+    if (every < 0) return fail(s, TFL_E_INVAL, "the check interval must be >= 0");
+    s->check_every = every;
+    return TFL_OK;
 }
 
 int tfl_profile_step(tfl_sim *s, int64_t nsteps, void *stream, double *h_ms, double *e_ms)

@@ -38,6 +38,15 @@ int check_obj(tfl_sim *s, const tfl_objective *o)
     return TFL_OK;
 }
 
+// The objective of the reverse sweep must be the one the checkpointed run accumulated F for.
+bool same_objective(const tfl_objective &a, const tfl_objective &b)
+{
+    if (a.comp != b.comp || a.f0 != b.f0) return false;
+    for (int q = 0; q < 6; ++q)
+        if (a.box[q] != b.box[q]) return false;
+    return true;
+}
+
 ProbeDesc objective_probe(const tfl_objective *o, double *dft)
 {
     ProbeDesc d{};
@@ -101,6 +110,7 @@ int forward_ckpt(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(s, e, "objective readback");
     s->ckpt_valid = true;
+    s->ckpt_obj = *o;
     s->ckpt_n0 = n0;
     s->ckpt_nsteps = nsteps;
     s->ckpt_seg = seg;
@@ -352,8 +362,12 @@ int tfl_forward_checkpointed(tfl_sim *s, const tfl_objective *obj, int64_t nstep
     if (!ckpt || !aligned(ckpt) || !F) return fail(s, TFL_E_INVAL, "checkpoint buffer must be aligned, F non-null");
     s->ckpt_valid = false;
     hipStream_t st = (hipStream_t)stream;
-    return s->esz == 8 ? forward_ckpt<double>(s, obj, nsteps, seg, ckpt, F, st)
-                       : forward_ckpt<float>(s, obj, nsteps, seg, ckpt, F, st);
+    if ((rc = nonfinite_begin(s, st)) != TFL_OK) return rc;
+    rc = s->esz == 8 ? forward_ckpt<double>(s, obj, nsteps, seg, ckpt, F, st)
+                     : forward_ckpt<float>(s, obj, nsteps, seg, ckpt, F, st);
+    const int rc2 = nonfinite_end(s, st);
+    if (rc2 != TFL_OK) s->ckpt_valid = false;  // no gradient of a run that went non-finite
+    return rc != TFL_OK ? rc : rc2;
 }
 
 int tfl_adjoint_nested_sizes(const tfl_sim *s, int64_t nsteps, int64_t seg, int64_t seg2, size_t *ckpt_bytes,
@@ -378,7 +392,10 @@ int tfl_adjoint_nested(tfl_sim *s, const tfl_objective *obj, int64_t nsteps, int
     if (rc != TFL_OK) return rc;
     if ((rc = check_obj(s, obj)) != TFL_OK) return rc;
     if (!s->ckpt_valid || s->ckpt_nsteps != nsteps || s->ckpt_seg != seg)
-        return fail(s, TFL_E_STATE, "no checkpointed forward run with these nsteps and seg");
+        return fail(s, TFL_E_STATE,
+                    "no checkpointed forward run with these nsteps and seg since the maps or sources last changed");
+    if (!same_objective(s->ckpt_obj, *obj))
+        return fail(s, TFL_E_STATE, "objective differs from the one of the checkpointed forward run");
     if (seg2 < 1 || seg2 > seg) return fail(s, TFL_E_INVAL, "seg2 must lie in [1, seg]");
     if (!ckpt || !ckpt2 || !snap || !adj || !grad_ell || !grad_sigma || !F)
         return fail(s, TFL_E_INVAL, "null buffer");
@@ -398,7 +415,10 @@ int tfl_adjoint(tfl_sim *s, const tfl_objective *obj, int64_t nsteps, int64_t se
     if (rc != TFL_OK) return rc;
     if ((rc = check_obj(s, obj)) != TFL_OK) return rc;
     if (!s->ckpt_valid || s->ckpt_nsteps != nsteps || s->ckpt_seg != seg)
-        return fail(s, TFL_E_STATE, "no checkpointed forward run with these nsteps and seg");
+        return fail(s, TFL_E_STATE,
+                    "no checkpointed forward run with these nsteps and seg since the maps or sources last changed");
+    if (!same_objective(s->ckpt_obj, *obj))
+        return fail(s, TFL_E_STATE, "objective differs from the one of the checkpointed forward run");
     if (!ckpt || !snap || !adj || !grad_ell || !grad_sigma || !F)
         return fail(s, TFL_E_INVAL, "null buffer");
     if (!aligned(ckpt) || !aligned(snap) || !aligned(adj) || !aligned(grad_ell) || !aligned(grad_sigma))

@@ -933,6 +933,35 @@ __global__ void class_table_kernel(const StepArgs<T> a, const T *mat, const uint
     tab[4 * c + 3] = T(0);
 }
 
+// Non-finite check of the state: counts the NaN and Inf values of the nine arrays (E, H, Js);
+// blocks add their counts to counter[0] and, when they found any, lower counter[1] to `step`
+// (counter[1] starts at the largest value: the first step index where the check saw one).
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void nonfinite_kernel(const NonfiniteArgs<T> a, unsigned long long *counter,
+                                                               unsigned long long step)
+{
+    unsigned long long bad = 0;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < a.n;
+         c += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) bad += isfinite(a.f[q][c]) ? 0u : 1u;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) bad += __shfl_down(bad, off, 64);
+    if ((threadIdx.x & 63) == 0 && bad != 0) {
+        atomicAdd(&counter[0], bad);
+        atomicMin(&counter[1], step);
+    }
+}
+
+__global__ void nonfinite_reset_kernel(unsigned long long *counter)
+{
+    if (threadIdx.x == 0) {
+        counter[0] = 0ull;
+        counter[1] = ~0ull;
+    }
+}
+
 __global__ void fill_zero_kernel(uint32_t *p, size_t nwords)
 {
     for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += (size_t)gridDim.x * blockDim.x)
@@ -1159,6 +1188,22 @@ hipError_t launch_map_stats(const T *eps, const T *sig, const T *ell, long long 
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_nonfinite(const NonfiniteArgs<T> &a, unsigned long long *counter, long long step, hipStream_t s)
+{
+    const long long nbl = (a.n + kRedThreads - 1) / kRedThreads;
+    const int nb = (int)(nbl < 4096 ? nbl : 4096);
+    hipLaunchKernelGGL(nonfinite_kernel<T>, dim3(nb), dim3(kRedThreads), 0, s, a, counter,
+                       (unsigned long long)step);
+    return hipGetLastError();
+}
+
+hipError_t launch_nonfinite_reset(unsigned long long *counter, hipStream_t s)
+{
+    hipLaunchKernelGGL(nonfinite_reset_kernel, dim3(1), dim3(64), 0, s, counter);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
 {
     if (bytes == 0) return hipSuccess;
@@ -1180,6 +1225,8 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
     template hipError_t launch_probes<T>(const ProbeArgs<T> &, int, hipStream_t);                           \
     template hipError_t launch_half_kick<T>(const StepArgs<T> &, T, T *const[3], T *const[3], hipStream_t); \
     template hipError_t launch_energy<T>(const StepArgs<T> &, double *, int, hipStream_t);                  \
+    template hipError_t launch_nonfinite<T>(const NonfiniteArgs<T> &, unsigned long long *, long long,       \
+                                            hipStream_t);                                                   \
     template hipError_t launch_map_stats<T>(const T *, const T *, const T *, long long, double *, int, hipStream_t);
 
 TFL_INSTANTIATE(double)

@@ -34,9 +34,15 @@ struct tfl_sim {
     std::vector<tfl::SourceDesc> src;
     std::vector<tfl::ProbeDesc> probe;
     double max_ell = 0.0;
-    // last tfl_forward_checkpointed run
+    // last tfl_forward_checkpointed run; invalidated by anything that changes what a recomputation
+    // of it would produce (maps, sources)
     bool ckpt_valid = false;
     int64_t ckpt_n0 = 0, ckpt_nsteps = 0, ckpt_seg = 0;
+    tfl_objective ckpt_obj{};
+    // non-finite check every check_every steps (0: off); `checking` while an entry point that
+    // reports it runs (tfl_step, tfl_forward_checkpointed), `checked` once a check was launched
+    int64_t check_every = 0;
+    bool checking = false, checked = false;
     std::string err;
 };
 
@@ -68,10 +74,18 @@ void class_pointers(const tfl_sim *s, const uint16_t *cls[3], const void **table
 constexpr size_t kScratchBytes = 1 << 17;
 constexpr int kRedBlocks = 1024;            // reductions use doubles [0, 5 * kRedBlocks)
 constexpr size_t kObjectiveSlot = 6144;     // doubles [6144, 6146): objective DFT
+constexpr size_t kNonfiniteOffset = 49408;  // bytes: two uint64 counters of the non-finite check
 constexpr size_t kProbeDescOffset = 65536;  // bytes: TFL_MAX_PROBES + 1 ProbeDesc
+static_assert(kNonfiniteOffset >= (kObjectiveSlot + 2) * sizeof(double) && kNonfiniteOffset + 16 <= kProbeDescOffset,
+              "non-finite counters overlap the objective or the probe descriptors");
 static_assert(kProbeDescOffset + (TFL_MAX_PROBES + 1) * sizeof(ProbeDesc) <= kScratchBytes, "scratch too small");
 // Upload the probe descriptors to scratch when they changed (synchronises).
 int upload_probes(tfl_sim *s, hipStream_t st);
+// Non-finite check around an entry point's steps: begin clears the counters when the check is on;
+// end (after the steps) reads them back when a check ran, synchronising, and fails with
+// TFL_E_NONFINITE when any value was found.
+int nonfinite_begin(tfl_sim *s, hipStream_t st);
+int nonfinite_end(tfl_sim *s, hipStream_t st);
 
 }  // namespace detail
 }  // namespace tfl

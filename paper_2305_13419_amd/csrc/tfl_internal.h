@@ -102,6 +102,13 @@ struct ProbeArgs {
     int first;
 };
 
+// The nine state arrays (Ex, Ey, Ez, Hx, Hy, Hz, Jx, Jy, Jz) of the non-finite check.
+template <typename T>
+struct NonfiniteArgs {
+    const T *f[9];
+    long long n;
+};
+
 // Reverse-mode (adjoint) sweep arguments.  Adjoint fields are stored in the
 // field precision; gradient accumulators are FP64.  lpsiH/lpsiE follow the
 // compact slab layout of the forward auxiliary variables.
@@ -205,6 +212,11 @@ hipError_t launch_energy(const StepArgs<T> &a, double *scratch, int nblocks, hip
 template <typename T>
 hipError_t launch_map_stats(const T *eps, const T *sig, const T *ell, long long n, double *scratch, int nblocks,
                             hipStream_t s);
+// Non-finite check: counter[0] += NaN / Inf values of the nine arrays, counter[1] = min(counter[1], step)
+// when any; the reset sets counter[0] = 0 and counter[1] to the largest value (a kernel, no memset).
+template <typename T>
+hipError_t launch_nonfinite(const NonfiniteArgs<T> &a, unsigned long long *counter, long long step, hipStream_t s);
+hipError_t launch_nonfinite_reset(unsigned long long *counter, hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 
 // Gram matrix of the lagged decimated series (fit.hip): for every pair

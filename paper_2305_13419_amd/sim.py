@@ -190,6 +190,11 @@ class Simulation:
     def step(self, n=1):
         self._call("tfl_step", ctypes.c_int64(int(n)), _stream())
 
+    def set_nonfinite_check(self, every):
+        """Count NaN / Inf values of E, H and Js on the device after every `every`-th step (0: off);
+        a step() or forward_checkpointed() that saw any raises TflError with code TFL_E_NONFINITE."""
+        self._call("tfl_set_nonfinite_check", ctypes.c_int64(int(every)))
+
     def profile_step(self, n):
         """Run n steps with HIP events around each pass; returns (H-pass ms, E-pass ms) summed."""
         h, e = ctypes.c_double(), ctypes.c_double()

@@ -162,25 +162,28 @@ def cpw_grid(scale=1, steps=None, dtype_note="FP32 fields + FP64 probes"):
                 objective=(1, probes[1]["box"], 1.7453e12 if s == 2 else None), note=dtype_note)
 
 
-def large_mixed_grid(seed=5, steps=8192):
+def large_mixed_grid(seed=5, steps=8192, shape=(1024, 512, 256)):
     """Large mixed-precision workload: 1024 x 512 x 256 cells of 20 nm, periodic, eps_r = 11.7 in the
     bottom quarter, random superconducting boxes as in the roofline grid (seed 5), zero fields driven by
-    a soft Ey sheet source; objective: Ey summed along y at x = 512, z = 128."""
+    a soft Ey sheet source at x = nx/4 over the middle quarter of z; objective: Ey summed along y at
+    x = nx/2, z = nz/2.  `shape` gives the same construction on another grid (parity tests at the
+    full step count on a grid the oracle can step)."""
     rng = np.random.default_rng(seed)
-    shape = (1024, 512, 256)
-    eps0 = np.ones((256, 512, 1024))
-    eps0[:64] = 11.7
-    maps = random_boxes(shape, rng, eps_r=eps0)
+    nx, ny, nz = (int(v) for v in shape)
+    eps0 = np.ones((nz, ny, nx))
+    eps0[:nz // 4] = 11.7
+    maps = random_boxes((nx, ny, nz), rng, eps_r=eps0)
     d = 20e-9
     f = 2e14
     tw = 1.0 / (2 * f)
-    return dict(name="large 1024x512x256", shape=shape, spacing=(d, d, d),
+    obj_box = (nx // 2, nx // 2 + 1, 0, ny, nz // 2, nz // 2 + 1)
+    return dict(name=f"large {nx}x{ny}x{nz}", shape=(nx, ny, nz), spacing=(d, d, d),
                 dt=courant_dt((d, d, d), 1.0 / (50e-9) ** 2, 0.95), theta=1.0, pml=(None, None, None),
                 maps=maps, fields=None,
-                sources=[dict(comp=1, box=(256, 257, 0, 512, 96, 160), amplitude=1.0, waveform="mod_gauss", freq=f,
-                              t0=4 * tw, tw=tw)],
-                probes=[dict(comp=1, box=(512, 513, 0, 512, 128, 129))], freq=f, steps=steps,
-                objective=(1, (512, 513, 0, 512, 128, 129), None))
+                sources=[dict(comp=1, box=(nx // 4, nx // 4 + 1, 0, ny, 3 * nz // 8, 5 * nz // 8), amplitude=1.0,
+                              waveform="mod_gauss", freq=f, t0=4 * tw, tw=tw)],
+                probes=[dict(comp=1, box=obj_box)], freq=f, steps=steps,
+                objective=(1, obj_box, None))
 
 
 # Rows of the paper's skin-depth sweep (Sec. 4.1, Table 1): (sigma S/m, f Hz, paper's computed delta nm).

@@ -31,8 +31,9 @@ def maps_of(wl, dtype=np.float64):
     return [np.asarray(m, dtype=dtype).astype(np.float64) for m in wl["maps"]]
 
 
-def run_oracle(wl, steps, dtype=np.float64, probe_cap=None):
-    """Oracle run from the inputs rounded to `dtype`.  Returns (E, H, J, probes)."""
+def run_oracle(wl, steps, dtype=np.float64, probe_cap=None, chunk=None):
+    """Oracle run from the inputs rounded to `dtype`.  Returns (E, H, J, probes).  With `chunk`, the
+    steps run in chunks of that many with a progress line after each (long runs)."""
     pml = wl["pml"]
     o = OracleSim(wl["shape"], wl["spacing"], wl["dt"], wl["theta"],
                   pml=[0 if p is None else 1 for p in pml], npml=[(0, 0) if p is None else p for p in pml],
@@ -44,7 +45,17 @@ def run_oracle(wl, steps, dtype=np.float64, probe_cap=None):
         o.add_source(s["comp"], s["box"], s["amplitude"], WAVE_KIND[s.get("waveform", "sin")], s.get("freq", 0.0),
                      s.get("t0", 0.0), s.get("tw", 1.0))
     pids = [o.add_probe(p["comp"], p["box"], probe_cap or steps + 1, p.get("freqs", ())) for p in wl["probes"]]
-    o.step(steps)
+    if chunk:
+        import time
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            n = min(chunk, steps - done)
+            o.step(n)
+            done += n
+            print(f"    oracle {done}/{steps} steps, {time.perf_counter() - t0:.0f} s", flush=True)
+    else:
+        o.step(steps)
     Eo, Bo, Jo = o.get_fields()
     return Eo, [b / MU0 for b in Bo], Jo, [o.probe(p) for p in pids]
 
@@ -90,3 +101,34 @@ def compare(g, o):
         if len(po[1]):
             res[f"dft{q}"] = rel_l2(pg[1], po[1])
     return res
+
+
+def max_abs_rel(a, b):
+    """max |a - b| over the elements divided by max |b|: an error confined to a few cells (a CPML slab,
+    a film) that the relative L2 over a large grid would average away shows here."""
+    mb = float(np.max(np.abs(b))) if np.size(b) else 0.0
+    d = float(np.max(np.abs(np.asarray(a) - np.asarray(b)))) if np.size(b) else 0.0
+    return d / mb if mb > 0 else d
+
+
+def compare_full(g, o):
+    """compare() plus the element-wise max-abs error (max_abs_rel) of every field group and probe."""
+    res = compare(g, o)
+    for name, a, b in (("E", g[0], o[0]), ("H", g[1], o[1]), ("J", g[2], o[2])):
+        res[f"maxabs_{name}"] = max_abs_rel(np.stack(a), np.stack(b))
+    for q, (pg, po) in enumerate(zip(g[3], o[3])):
+        res[f"maxabs_probe{q}"] = max_abs_rel(pg[0], po[0])
+    return res
+
+
+def rounded_inputs(wl, dtype=np.float32):
+    """The workload with its maps and initial fields rounded to `dtype` (kept as float64 arrays), so that
+    an FP64 run, an FP32 run and the oracle all start from the same values and one oracle run serves
+    both comparisons (rounding to FP32 twice changes nothing)."""
+    out = dict(wl)
+    out["maps"] = tuple(np.asarray(m, dtype=dtype).astype(np.float64) for m in wl["maps"])
+    if wl.get("fields") is not None:
+        E, H, J = wl["fields"]
+        r = lambda grp: None if grp is None else [np.asarray(a, dtype=dtype).astype(np.float64) for a in grp]  # noqa
+        out["fields"] = (r(E), r(H), r(J))
+    return out

@@ -131,6 +131,9 @@ def test_buffer_sizes_and_call_order(L):
     n = ctypes.c_int64()
     assert L.lib().tfl_set_step(h, 5) == 0
     assert L.lib().tfl_get_step(h, ctypes.byref(n)) == 0 and n.value == 5
+    assert L.lib().tfl_set_nonfinite_check(h, -1) == L.TFL_E_INVAL
+    assert L.lib().tfl_set_nonfinite_check(h, 16) == 0 and L.lib().tfl_set_nonfinite_check(h, 0) == 0
+    assert L.lib().tfl_set_nonfinite_check(None, 1) == L.TFL_E_INVAL
     assert L.lib().tfl_destroy(h) == 0
 
 

@@ -158,3 +158,74 @@ def test_nested_schedule_equals_two_level(seg, seg2):
     assert np.array_equal(gl2, gl) and np.array_equal(gs2, gs)
     Jo, Fo, glo, gso = oracle_adjoint(wl, obj, N)
     assert rel_l2(gl2, glo) <= 1e-10 and rel_l2(gs2, gso) <= 1e-10
+
+
+def test_adjoint_rejects_stale_checkpoints():
+    """A checkpointed run is invalidated by new maps or sources, and its reverse sweep needs the same
+    objective: each mismatch returns TFL_E_STATE instead of a gradient of another run."""
+    from paper_2305_13419_amd import Simulation, _lib as L
+    c = CASES[0]
+    wl, obj = make_case(c)
+    N, seg = 12, 4
+    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], torch.float64, wl["pml"])
+
+    def fresh_run():
+        sim.set_materials(*wl["maps"])
+        sim.set_fields(*wl["fields"])
+        return sim.forward_checkpointed(obj, N, seg, ckpt)
+
+    for s in wl["sources"]:
+        sim.add_source(**s)
+    ckpt, snap, work = sim.adjoint_buffers(N, seg)
+    F = fresh_run()
+    gl, gs = sim.adjoint(obj, N, seg, ckpt, F, snap, work)  # the matching call works
+    assert np.isfinite(gl.cpu().numpy()).all()
+
+    def expect_state(fn):
+        with pytest.raises(L.TflError) as err:
+            fn()
+        assert err.value.code == L.TFL_E_STATE, err.value
+
+    # another objective frequency, box or component
+    for other in ((obj[0], obj[1], obj[2] * 1.01), (obj[0], (0, 1) + tuple(obj[1][2:]), obj[2]),
+                  ((obj[0] + 1) % 3, obj[1], obj[2])):
+        expect_state(lambda: sim.adjoint(other, N, seg, ckpt, F, snap, work))
+    # new maps after the run
+    F = fresh_run()
+    sim.set_materials(*wl["maps"])
+    expect_state(lambda: sim.adjoint(obj, N, seg, ckpt, F, snap, work))
+    # a new source after the run
+    F = fresh_run()
+    sim.add_source(**wl["sources"][0])
+    expect_state(lambda: sim.adjoint(obj, N, seg, ckpt, F, snap, work))
+    # sources cleared after the run
+    F = fresh_run()
+    sim._call("tfl_clear_sources_probes")
+    expect_state(lambda: sim.adjoint(obj, N, seg, ckpt, F, snap, work))
+    sim.close()
+
+
+def test_autograd_rejects_backward_after_a_later_forward():
+    """Two applies on one AdjointProblem: the later graph's backward gives the oracle gradient of its
+    own maps; the earlier graph's backward raises instead of returning the later run's gradient."""
+    from paper_2305_13419_amd import AdjointProblem, TwoFluidObjective
+    c = CASES[1]
+    wl, obj = make_case(c)
+    eps, sig, ell = wl["maps"]
+    prob = AdjointProblem(wl["shape"], wl["spacing"], wl["dt"], eps, obj, c["N"], seg=10, theta=c["theta"],
+                          pml=c["pml"], sources=wl["sources"])
+    L1 = torch.tensor(ell, device="cuda", requires_grad=True)
+    S1 = torch.tensor(sig, device="cuda", requires_grad=True)
+    J1 = TwoFluidObjective.apply(L1, S1, prob)
+    ell2 = ell * 1.1
+    L2 = torch.tensor(ell2, device="cuda", requires_grad=True)
+    S2 = torch.tensor(sig, device="cuda", requires_grad=True)
+    J2 = TwoFluidObjective.apply(L2, S2, prob)
+    J2.backward()
+    wl2 = dict(wl)
+    wl2["maps"] = (eps, sig, ell2)
+    Jo, Fo, glo, gso = oracle_adjoint(wl2, obj, c["N"])
+    assert abs(J2.item() / Jo - 1) < 1e-12
+    assert rel_l2(L2.grad.cpu().numpy(), glo) <= 1e-10 and rel_l2(S2.grad.cpu().numpy(), gso) <= 1e-10
+    with pytest.raises(RuntimeError, match="another forward pass"):
+        J1.backward()

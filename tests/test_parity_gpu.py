@@ -169,3 +169,50 @@ def test_unstable_dt_rejected():
     bad[0][0, 0, 0] = np.nan
     with pytest.raises(TflError):
         sim2.set_materials(*bad)
+
+
+@pytest.mark.parametrize("dtype,pml,fused,every,plant", [
+    (torch.float64, (None, None, None), True, 1, "E"),
+    (torch.float32, ((4, 4), None, (3, 3)), False, 4, "H"),
+    (torch.float64, ((4, 4), (2, 2), None), True, 3, "J"),
+])
+def test_nonfinite_check_reports_planted_value(dtype, pml, fused, every, plant):
+    """A NaN or Inf written into the state is counted by tfl_energy and, with the step check on, makes
+    tfl_step fail with TFL_E_NONFINITE naming the first checked step; a clean run with the check on
+    passes and equals the run without it bit for bit."""
+    import math
+
+    from paper_2305_13419_amd import Simulation, _lib as L
+    wl = workloads.random_medium((40, 12, 14), seed=5, pml=pml)
+
+    def make():
+        sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"], fused=fused)
+        sim.set_materials(*wl["maps"])
+        sim.set_fields(*wl["fields"])
+        return sim
+
+    clean, checked = make(), make()
+    checked.set_nonfinite_check(1)
+    clean.step(7)
+    checked.step(7)
+    for a, b in zip(clean.E + clean.H + clean.J, checked.E + checked.H + checked.J):
+        assert torch.equal(a, b)
+    assert checked.energy()[1] == 0
+
+    sim = make()
+    grp = {"E": sim.E, "H": sim.H, "J": sim.J}[plant]
+    if plant == "J":  # Js is read only on superconducting edges: plant where one is
+        ell = np.asarray(wl["maps"][2])
+        k, j, i = np.argwhere(ell > 0)[0]
+        grp[2][k, j, i] = math.inf
+    else:
+        grp[1][5, 6, 20] = math.nan
+    assert sim.energy()[1] >= 1
+    sim.set_nonfinite_check(every)
+    with pytest.raises(L.TflError) as err:
+        sim.step(2 * every)
+    assert err.value.code == L.TFL_E_NONFINITE
+    assert f"first seen after step {every}" in str(err.value), str(err.value)
+    assert sim.step_index == 2 * every  # every step of the call was taken
+    sim.set_nonfinite_check(0)
+    sim.step(1)  # off again: no error
