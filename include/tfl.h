@@ -254,6 +254,23 @@ int tfl_sync_integer_time(tfl_sim *sim, void *const Hn[3], void *const Jn[3], vo
  * number of non-finite values in E, H and Js.  Synchronises `stream`. */
 int tfl_energy(tfl_sim *sim, double *energy, int64_t *nonfinite, void *stream);
 
+/* Allocation-free variant of tfl_energy, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same two results, written to the caller's device buffer
+ * out (FP64 [2]: out[0] = W^n, out[1] = the non-finite count as a double),
+ * asynchronously on `stream` (no host copy, no synchronisation).  The block
+ * partials of the reduction live in a fixed device array of the library
+ * (2 x 1024 doubles, 16 KiB, one copy per GPU, held until the process ends)
+ * instead of the bound scratch buffer; the call allocates nothing.  Every
+ * block writes its partial before the final fold reads it, so nothing of a
+ * previous call is read.  All calls on one GPU share that array: calls that
+ * overlap in time on one GPU (two streams, or two host threads) race and may
+ * return wrong values.  Results are bitwise those of tfl_energy.  Needs bound
+ * state and materials (no bound workspace is read).  TFL_E_INVAL on a null or
+ * misaligned out, TFL_E_NOMEM if a reduction would need more partials than
+ * the array holds (no grid does: the count is fixed). */
+int tfl_energy_noalloc(tfl_sim *sim, double *out, void *stream);
+
 /* Step index n (the state is at E^n) and its override (for restarts). */
 int tfl_get_step(const tfl_sim *sim, int64_t *step);
 int tfl_set_step(tfl_sim *sim, int64_t step);

@@ -116,6 +116,7 @@ SIGNATURES = {
     "tfl_profile_step": [P, ctypes.c_int64, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "tfl_sync_integer_time": [P, PP, PP, P],
     "tfl_energy": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), P],
+    "tfl_energy_noalloc": [P, P, P],
     "tfl_get_step": [P, ctypes.POINTER(ctypes.c_int64)],
     "tfl_set_step": [P, ctypes.c_int64],
     "tfl_save_state": [P, P, P],

@@ -720,6 +720,29 @@ int tfl_energy(tfl_sim *s, double *energy, int64_t *nonfinite, void *stream)
     return TFL_OK;
 }
 
+int tfl_energy_noalloc(tfl_sim *s, double *out, void *stream)
+{
+    if (!s) return fail(nullptr, TFL_E_INVAL, "null handle");
+    if (!s->state_bound) return fail(s, TFL_E_STATE, "state arrays not bound (tfl_bind_state)");
+    if (!s->maps_bound) return fail(s, TFL_E_STATE, "materials not bound (tfl_bind_materials)");
+    if (!out || (reinterpret_cast<uintptr_t>(out) & 7u) != 0)
+        return fail(s, TFL_E_INVAL, "out must be an 8-byte aligned device pointer of 2 doubles");
+    // the reduction uses kRedBlocks partial pairs, the same as tfl_energy (so the results are the same
+    // bits); the fixed scratch holds kStaticScratchBlocks of them
+    const int nblocks = kRedBlocks;
+    if (nblocks > kStaticScratchBlocks)
+        return fail(s, TFL_E_NOMEM, "the energy reduction needs %d block partials, the fixed scratch holds %d",
+                    nblocks, kStaticScratchBlocks);
+    double *part = nullptr;
+    hipError_t e = static_scratch(&part);
+    if (e != hipSuccess) return hip_fail(s, e, "fixed scratch address");
+    hipStream_t st = (hipStream_t)stream;
+    e = s->esz == 8 ? launch_energy<double>(make_args<double>(s), part, nblocks, st, out)
+                    : launch_energy<float>(make_args<float>(s), part, nblocks, st, out);
+    if (e != hipSuccess) return hip_fail(s, e, "energy");
+    return TFL_OK;
+}
+
 int tfl_get_step(const tfl_sim *s, int64_t *step)
 {
     if (!s || !step) return fail(nullptr, TFL_E_INVAL, "null argument");

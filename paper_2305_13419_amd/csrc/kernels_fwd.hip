@@ -20,6 +20,8 @@
 // registers; x and y neighbours come from L1/L2.  Blocks are renumbered so that each XCD
 // (blocks are dealt to the 8 XCDs round robin) receives a contiguous range of
 // tiles, keeping the halo rows of neighbouring tiles in the same L2.
+#include <mutex>
+
 #include "fdtd_common.h"
 
 namespace tfl {
@@ -832,11 +834,10 @@ __global__ __launch_bounds__(kRedThreads) void energy_kernel(const StepArgs<T> a
     }
 }
 
-// Second stage: one block folds nblocks pairs into scratch[0..1] in a fixed order.
-__global__ __launch_bounds__(kRedThreads) void fold_pairs_kernel(double *part, int nblocks, int op_min_max)
+// Second stage: one block folds nblocks pairs into dst[0..1] in a fixed order (dst may be part).
+__global__ __launch_bounds__(kRedThreads) void fold_pairs_kernel(double *part, int nblocks, double *dst)
 {
     __shared__ double lds[kRedThreads / 64];
-    (void)op_min_max;
     double a0 = 0.0, a1 = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += kRedThreads) {
         a0 += part[2 * b];
@@ -846,8 +847,8 @@ __global__ __launch_bounds__(kRedThreads) void fold_pairs_kernel(double *part, i
     const double s1 = block_sum(a1, lds);
     __syncthreads();
     if (threadIdx.x == 0) {
-        part[0] = s0;
-        part[1] = s1;
+        dst[0] = s0;
+        dst[1] = s1;
     }
 }
 
@@ -969,6 +970,35 @@ __global__ void fill_zero_kernel(uint32_t *p, size_t nwords)
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free entry points
+// ---------------------------------------------------------------------------
+// One copy per GPU, held until the process ends: the block partials (two FP64 values per block) of
+// the energy reduction of tfl_energy_noalloc.  In host code `scratch` names a host-side stand-in,
+// not device memory: kernels receive the device address from static_scratch() instead.
+static __device__ __align__(256) double scratch[2 * kStaticScratchBlocks];
+
+hipError_t static_scratch(double **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex lock;
+    static double *ptr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(lock);
+    if (!ptr[dev]) {  // first call on this device (the current one): its copy's address
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        ptr[dev] = (double *)p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // Launchers
@@ -1168,12 +1198,12 @@ hipError_t launch_class_table(const StepArgs<T> &a, const T *mat, const uint64_t
 }
 
 template <typename T>
-hipError_t launch_energy(const StepArgs<T> &a, double *scratch, int nblocks, hipStream_t s)
+hipError_t launch_energy(const StepArgs<T> &a, double *part, int nblocks, hipStream_t s, double *dst)
 {
-    hipLaunchKernelGGL(energy_kernel<T>, dim3(nblocks), dim3(kRedThreads), 0, s, a, scratch);
+    hipLaunchKernelGGL(energy_kernel<T>, dim3(nblocks), dim3(kRedThreads), 0, s, a, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fold_pairs_kernel, dim3(1), dim3(kRedThreads), 0, s, scratch, nblocks, 0);
+    hipLaunchKernelGGL(fold_pairs_kernel, dim3(1), dim3(kRedThreads), 0, s, part, nblocks, dst ? dst : part);
     return hipGetLastError();
 }
 
@@ -1224,7 +1254,7 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
     template hipError_t launch_sources<T>(const SrcArgs<T> &, hipStream_t);                                 \
     template hipError_t launch_probes<T>(const ProbeArgs<T> &, int, hipStream_t);                           \
     template hipError_t launch_half_kick<T>(const StepArgs<T> &, T, T *const[3], T *const[3], hipStream_t); \
-    template hipError_t launch_energy<T>(const StepArgs<T> &, double *, int, hipStream_t);                  \
+    template hipError_t launch_energy<T>(const StepArgs<T> &, double *, int, hipStream_t, double *);        \
     template hipError_t launch_nonfinite<T>(const NonfiniteArgs<T> &, unsigned long long *, long long,       \
                                             hipStream_t);                                                   \
     template hipError_t launch_map_stats<T>(const T *, const T *, const T *, long long, double *, int, hipStream_t);

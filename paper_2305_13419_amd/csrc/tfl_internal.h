@@ -205,9 +205,14 @@ template <typename T> hipError_t launch_probes(const ProbeArgs<T> &a, int nprobe
 // SC edges (0 on other edges).  sgn = +1 goes back half a step, -1 forward.
 template <typename T>
 hipError_t launch_half_kick(const StepArgs<T> &a, T sgn, T *const Hout[3], T *const Jout[3], hipStream_t s);
-// Energy partials into scratch (FP64), second stage reduces to scratch[0..1].
+// Energy partials into part (FP64, 2 nblocks values), second stage reduces to dst[0..1] (part[0..1]
+// when dst is null).
 template <typename T>
-hipError_t launch_energy(const StepArgs<T> &a, double *scratch, int nblocks, hipStream_t s);
+hipError_t launch_energy(const StepArgs<T> &a, double *part, int nblocks, hipStream_t s, double *dst = nullptr);
+// Blocks of the energy reduction in the fixed device scratch of the allocation-free entry point, and
+// that scratch's device address on the current device (looked up on the first call per device).
+constexpr int kStaticScratchBlocks = 1024;
+hipError_t static_scratch(double **out);
 // Map statistics: min eps, min sigma, min ell, max ell, nonfinite count.
 template <typename T>
 hipError_t launch_map_stats(const T *eps, const T *sig, const T *ell, long long n, double *scratch, int nblocks,
