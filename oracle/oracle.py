@@ -63,13 +63,23 @@ def lib():
         L.oracle_step.argtypes = [P, Lg]
         L.oracle_step_index.restype = Lg
         L.oracle_step_index.argtypes = [P]
+        L.oracle_threads.restype = I
+        L.oracle_threads.argtypes = []
         L.oracle_energy.restype = D
         L.oracle_energy.argtypes = [P]
         if hasattr(L, "oracle_adjoint"):
             L.oracle_adjoint.restype = I
             L.oracle_adjoint.argtypes = [P, Lg, I, D, pd, pd, pd]
+            L.oracle_adjoint_state.restype = I
+            L.oracle_adjoint_state.argtypes = [P, Lg, I, D, pd, pd, pd, ctypes.POINTER(pd), ctypes.POINTER(pd),
+                                               ctypes.POINTER(pd)]
         _lib = L
     return _lib
+
+
+def threads():
+    """OpenMP threads of the oracle's grid sweeps."""
+    return int(lib().oracle_threads())
 
 
 def _pd(a):
@@ -179,3 +189,16 @@ class OracleSim:
         if rc != 0:
             raise ValueError("oracle_adjoint: bad arguments")
         return out[0], out[1] + 1j * out[2], gl, gs
+
+    def adjoint_state(self, nsteps, pid, f0):
+        """adjoint() plus the adjoint of the state the run started from: (J, F, dJ/d ell, dJ/d sigma,
+        dJ/dE^0, dJ/dB^0, dJ/dJs^0), the last three as lists of three arrays (PML variables held fixed)."""
+        gl = np.zeros(self.shape3)
+        gs = np.zeros(self.shape3)
+        out = np.zeros(3)
+        aE, aB, aJ = ([np.zeros(self.shape3) for _ in range(3)] for _ in range(3))
+        rc = lib().oracle_adjoint_state(self._h, int(nsteps), int(pid), float(f0), _pd(gl), _pd(gs), _pd(out),
+                                        _arr3(aE), _arr3(aB), _arr3(aJ))
+        if rc != 0:
+            raise ValueError("oracle_adjoint: bad arguments")
+        return out[0], out[1] + 1j * out[2], gl, gs, aE, aB, aJ

@@ -44,6 +44,9 @@
  * results do not depend on the thread count.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -492,6 +495,16 @@ void oracle_step(oracle_sim *s, long nsteps)
 
 long oracle_step_index(const oracle_sim *s) { return s->step; }
 
+/* Threads the grid sweeps run on (1 without OpenMP). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* Discrete energy at integer time n, written with the integer-time state:
  *   W^n = dV [ sum_e eps_e E_e^2 / 2
  *            + sum_f (B_f^2 - (dt/2 curlE_f)^2) / (2 mu0)
@@ -642,7 +655,10 @@ static void o_adj_half_B(oracle_sim *s, double **aE, double **aB, double *(*apsi
     }
 }
 
-int oracle_adjoint(oracle_sim *s, long nsteps, int pid, double f0, double *grad_ell, double *grad_sig, double *out)
+/* The reverse sweep; when aE0, aB0, aJ0 are not NULL they receive the adjoint of the initial state
+ * (dJ/dE^0, dJ/dB^0, dJ/dJs^0 at the state passed to the run, with the PML variables held fixed). */
+static int o_adjoint(oracle_sim *s, long nsteps, int pid, double f0, double *grad_ell, double *grad_sig, double *out,
+                     double *const *aE0, double *const *aB0, double *const *aJ0)
 {
     const double twopi = 2.0 * 3.14159265358979323846;
     if (pid < 0 || pid >= s->nprobe || nsteps < 1) return -1;
@@ -766,6 +782,12 @@ int oracle_adjoint(oracle_sim *s, long nsteps, int pid, double f0, double *grad_
         /* 1^T */
         o_adj_half_B(s, aE, aB, apsiB, 0);
     }
+    if (aE0 && aB0 && aJ0)
+        for (int c = 0; c < 3; ++c) {
+            memcpy(aE0[c], aE[c], (size_t)N * sizeof(double));
+            memcpy(aB0[c], aB[c], (size_t)N * sizeof(double));
+            memcpy(aJ0[c], aJ[c], (size_t)N * sizeof(double));
+        }
     /* restore the forward end state */
     o_state_load(s, &traj[nsteps]);
     s->step = step0 + nsteps;
@@ -814,4 +836,15 @@ int oracle_adjoint(oracle_sim *s, long nsteps, int pid, double f0, double *grad_
         for (int a = 0; a < 3; ++a) { free(apsiB[c][a]); free(apsiE[c][a]); }
     }
     return 0;
+}
+
+int oracle_adjoint(oracle_sim *s, long nsteps, int pid, double f0, double *grad_ell, double *grad_sig, double *out)
+{
+    return o_adjoint(s, nsteps, pid, f0, grad_ell, grad_sig, out, NULL, NULL, NULL);
+}
+
+int oracle_adjoint_state(oracle_sim *s, long nsteps, int pid, double f0, double *grad_ell, double *grad_sig,
+                         double *out, double *const *aE0, double *const *aB0, double *const *aJ0)
+{
+    return o_adjoint(s, nsteps, pid, f0, grad_ell, grad_sig, out, aE0, aB0, aJ0);
 }

@@ -49,3 +49,37 @@ def test_oracle_adjoint_matches_central_differences(pml, theta):
             assert abs(g[c] - fd) <= 1e-5 * abs(fd), (mi, c, g[c], fd)
     # cells without superconductivity get no inv_lambda2 gradient (fixed classification)
     assert np.all(gl[wl["maps"][2] == 0] == 0.0)
+
+
+@pytest.mark.parametrize("pml,theta,N", [((None, None, None), 1.0, 1), ((None, None, None), 0.5, 1),
+                                         ((None, None, None), 0.7, 23), (((0, 0), None, (0, 0)), 1.0, 17)])
+def test_oracle_adjoint_dot_product(pml, theta, N):
+    """Dot-product test of the reverse sweep over one step and over N steps: without sources F is linear
+    in the initial state x = (E^0, B^0, Js^0), so the adjoint g = dJ/dx at x0 must satisfy
+    <g, d> = 2 Re(conj(F(x0)) F(d)) for any direction d, F(d) being a forward run started from d.  This
+    is the transpose identity <M^T y, d> = <y, M d> of the whole linear map, exact up to rounding (no
+    finite-difference error); periodic grids and PEC walls (the CPML transpose is covered by the
+    finite-difference test above)."""
+    f0 = 2.5e14
+    wl = workloads.random_medium((11, 6, 9), seed=37, pml=pml, theta=theta)
+    o, pid = build(wl, wl["maps"], f0, src=False)
+    J, F0, gl, gs, aE, aB, aJ = o.adjoint_state(N, pid, f0)
+    assert abs(J - abs(F0) ** 2) <= 1e-14 * J
+    rng = np.random.default_rng(9)
+    sc = [np.asarray(e) > 0 for e in o.edge_materials()[2]]
+    for trial in range(3):
+        dE = [rng.standard_normal(o.shape3) for _ in range(3)]
+        dB = [rng.standard_normal(o.shape3) * MU0 / 377.0 for _ in range(3)]
+        dJ = [np.where(sc[c], 1e3 * rng.standard_normal(o.shape3), 0.0) for c in range(3)]
+        o2 = OracleSim(wl["shape"], wl["spacing"], wl["dt"], wl["theta"],
+                       pml=[0 if p is None else 1 for p in pml], npml=[(0, 0) if p is None else p for p in pml])
+        o2.set_materials(*wl["maps"])
+        o2.set_fields(dE, dB, dJ)
+        p2 = o2.add_probe(1, (8, 9, 0, wl["shape"][1], 0, wl["shape"][2]), 1, [f0])
+        o2.step(N)
+        Fd = o2.probe(p2)[1][0]
+        lhs = sum(float(np.sum(a * b)) for a, b in zip(aE + aB + aJ, dE + dB + dJ))
+        rhs = 2.0 * (np.conj(F0) * Fd).real
+        terms = sum(float(np.sum(np.abs(a * b))) for a, b in zip(aE + aB + aJ, dE + dB + dJ))
+        assert abs(lhs - rhs) <= 1e-13 * terms, (trial, lhs, rhs, terms)
+        assert abs(rhs) > 1e-6 * terms  # the identity is not trivially 0 = 0

@@ -611,3 +611,124 @@ def test_reflection_versus_frequency():
     # sigma > 0: R falls smoothly from ~1 (Sec. 4.2): no cutoff
     R4 = R[1e4][band]
     assert R4[fb < 60e12].min() > 0.98 and np.all(np.diff(R4[(fb > 10e12) & (fb < 1e15)]) < 1e-3)
+
+
+def test_cpml_matches_free_space_reference():
+    """Open boundaries (Sec. 3, CPML backed by a PEC wall): a 36^3 vacuum grid with 10-cell CPML slabs on
+    all six faces (corners where slabs overlap included) against a 128^3 periodic grid holding the same
+    initial field at its centre, whose wrap-around cannot reach the compared region in the run.  Over 120
+    steps (the radiated part of the pulse crosses the slabs and what they reflect comes back), E in the
+    16^3 interior agrees with the free-space run to 1e-4 of the initial peak at every sample, while the
+    same slabs with no absorption (a bare PEC box) are off by 1e-2: the absorber, not the sampling, makes
+    the agreement."""
+    d = 10e-9
+    dt = 0.95 * cf.stable_dt([d, d, d], 0.0)
+
+    def blob(n):
+        x = (np.arange(n) - n // 2) * d
+        X, Y, Z = x[None, None, :], x[None, :, None], x[:, None, None]
+        g = lambda ox, oy, oz, w: np.exp(-(((X + ox * d) / w) ** 2 + ((Y + oy * d) / w) ** 2  # noqa: E731
+                                           + ((Z + oz * d) / w) ** 2))
+        # E on its edges: Ex at (i + 1/2, j, k), Ey at (i, j + 1/2, k), Ez at (i, j, k + 1/2)
+        return [g(0.5, 0, 0, 25e-9), 0.7 * g(0, 0.5, 0, 20e-9), -0.5 * g(0, 0, 0.5, 30e-9)]
+
+    def series(n, npml, scale):
+        pml = (1, 1, 1) if npml else (0, 0, 0)
+        o = OracleSim((n, n, n), (d, d, d), dt, 1.0, pml=pml, npml=[(npml, npml)] * 3, pml_scale=scale)
+        shp = (n, n, n)
+        o.set_materials(np.ones(shp), np.zeros(shp), np.zeros(shp))
+        o.set_fields(blob(n), zeros(shp), zeros(shp))
+        out = []
+        for _ in range(6):
+            o.step(20)
+            out.append(o.get_fields()[0])
+        return out
+
+    ns, npml, nb = 36, 10, 128
+    ref = series(nb, 0, 1.0)
+    off = (nb - ns) // 2
+    si, sb = slice(npml, ns - npml), slice(off + npml, off + ns - npml)
+    peak = max(np.abs(b).max() for b in blob(ns))
+
+    def worst(scale):
+        run = series(ns, npml, scale)
+        return max(max(np.abs(a[c][si, si, si] - b[c][sb, sb, sb]).max() for c in range(3)) / peak
+                   for a, b in zip(run, ref))
+
+    assert worst(1.0) < 1e-4
+    assert worst(0.0) > 1e-2
+
+
+# ---------------------------------------------------------------------------
+# Cube of superconductor: three-dimensional interface convergence (Sec. 4.3.3, Table 6)
+# ---------------------------------------------------------------------------
+# Components on half nodes along these array axes (z, y, x); node axes are subsampled when a fine
+# solution is restricted to the coarse grid, half-node axes averaged over the two fine samples.
+_HALF_AXES = {("E", 0): (2,), ("E", 1): (1,), ("E", 2): (0,), ("B", 0): (0, 1), ("B", 1): (0, 2), ("B", 2): (1, 2)}
+
+
+def _cube_run(n, steps, half):
+    """The paper's cube problem (lambda_L = 40 nm, sigma = 1e4 S/m, cube [-40, 40]^3 nm in a periodic
+    [-640, 640]^3 nm vacuum, plane Ex / By Gaussian pulse from z0 = -320 nm, theta = 0.5, dt of 2.5 nm
+    cells at CFL 0.9) on n cells per axis.  half=True steps only x in [0, 640] nm with PEC walls at x = 0
+    and x = 640 nm: the problem is mirror symmetric about x = 0 with Ey, Ez odd (a PEC plane), and
+    periodic, so also about x = 640 nm, and the half domain holds the same solution."""
+    d = 1280e-9 / n
+    dt = 0.9 * 2.5e-9 / (cf.C0 * np.sqrt(3))
+    nx = n // 2 if half else n
+    shp = (n, n, nx)
+    xc = (np.arange(nx) + 0.5) * d + (0.0 if half else -640e-9)
+    yc = -640e-9 + (np.arange(n) + 0.5) * d
+    inside = lambda c: (c > -40e-9) & (c < 40e-9)  # noqa: E731
+    cube = inside(yc)[:, None, None] & inside(yc)[None, :, None] & inside(xc)[None, None, :]
+    o = OracleSim((nx, n, n), (d, d, d), dt, 0.5, pml=(1 if half else 0, 0, 0), npml=[(0, 0)] * 3)
+    o.set_materials(np.ones(shp), np.where(cube, 1e4, 0.0), np.where(cube, 1 / (40e-9) ** 2, 0.0))
+    zn = -640e-9 + np.arange(n) * d
+    ex = np.broadcast_to(np.exp(-((zn + 320e-9) ** 2) / (80e-9) ** 2)[:, None, None], shp).copy()
+    by = np.broadcast_to((np.exp(-((zn + d / 2 + 320e-9) ** 2) / (80e-9) ** 2) / cf.C0)[:, None, None], shp).copy()
+    z = np.zeros(shp)
+    o.set_fields([ex, z, z], [z, by, z], [z, z, z])
+    o.step(steps)
+    E, B, _ = o.get_fields()
+    return E, B
+
+
+def test_cube_half_domain_is_exact():
+    """The PEC-walled half domain gives the x >= 0 half of the full periodic cube problem bit for bit."""
+    fullE, fullB = _cube_run(32, 60, False)
+    halfE, halfB = _cube_run(32, 60, True)
+    for full, half in ((fullE, halfE), (fullB, halfB)):
+        for c in range(3):
+            assert np.array_equal(full[c][:, :, 16:], half[c])
+    assert np.abs(fullE[1]).max() > 1e-6  # the cube scatters into every component
+
+
+def _restrict3(F, axes):
+    for ax in range(3):
+        m = F.shape[ax] // 2 * 2
+        a = np.take(F, np.arange(m), axis=ax)
+        even = np.take(a, np.arange(0, m, 2), axis=ax)
+        F = 0.5 * (even + np.take(a, np.arange(1, m, 2), axis=ax)) if ax in axes else even
+    return F
+
+
+@pytest.mark.slow
+def test_table6_cube_space_first_column():
+    """Table 6, first error column (128^3 against 256^3, 400 steps at the time step of 512^3, restricted
+    and compared in the L1 mean) for all six components, within 3 % of the printed values: the
+    three-dimensional test of the interface-edge rule at the cube's faces, edges and corners (run on
+    the half domain, test_cube_half_domain_is_exact; the mean over the half equals the mean over the
+    whole by the mirror symmetry)."""
+    ref = {}
+    with open(os.path.join(GOLDEN, "convergence_tables.txt")) as f:
+        for line in f:
+            if line.startswith("table6"):
+                t, fld, a, b, r = line.split()
+                ref[fld] = float(a)
+    coarse = _cube_run(128, 400, True)
+    fine = _cube_run(256, 400, True)
+    for g, key in ((0, "E"), (1, "B")):
+        for c in range(3):
+            e = np.abs(_restrict3(fine[g][c], _HALF_AXES[(key, c)]) - coarse[g][c]).mean()
+            name = key + "xyz"[c]
+            assert abs(e / ref[name] - 1) < 0.03, (name, e, ref[name])
