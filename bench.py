@@ -48,7 +48,7 @@ def sc_edge_fraction(ell):
     return float(np.mean(fr))
 
 
-def run_gpu(wl, dtype, steps, warmup, fused=True, classes=True):
+def run_gpu(wl, dtype, steps, warmup, fused=True, classes=True, sweep="auto"):
     import numpy as np
     import torch
 
@@ -68,6 +68,7 @@ def run_gpu(wl, dtype, steps, warmup, fused=True, classes=True):
         raise RuntimeError("edge classes requested but the grid has too many distinct materials")
     E, H, _ = wl["fields"]
     sim.set_fields([np.asarray(a, dtype=npdt) for a in E], [np.asarray(a, dtype=npdt) for a in H])
+    sim.set_sweep(sweep)
     sim.step(warmup)
     torch.cuda.synchronize()
     # timed region: K steps, HIP events around every kernel on the launch stream (fused sweep: the
@@ -76,10 +77,12 @@ def run_gpu(wl, dtype, steps, warmup, fused=True, classes=True):
     h_ms, e_ms = sim.profile_step(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    counts = sim.sweep_counts()
     W, bad = sim.energy()
     sim.close()
     return dict(h_ms=h_ms / steps, e_ms=e_ms / steps, step_ms=(h_ms + e_ms) / steps, wall_s=wall,
-                nonfinite=int(bad), energy=W, edge_classes=ncls, bind_materials_s=bind_s)
+                nonfinite=int(bad), energy=W, edge_classes=ncls, bind_materials_s=bind_s,
+                sweep_counts=dict(zip(("two_pass", "fused", "two_step"), counts)))
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=10):
@@ -175,8 +178,27 @@ def large_run(steps=8192, seg=512, seg2=32, fd_steps=512, fd_cells=4):
 
     wl = workloads.large_mixed_grid(steps=steps)
     n = int(np.prod(wl["shape"]))
-    obj = (wl["objective"][0], wl["objective"][1], wl["freq"])
-    out = {"workload": wl["name"], "steps": steps, "seg": seg, "seg2": seg2, "objective_f0": wl["freq"]}
+    # the objective's frequency, frozen once: the peak of |DFT| of the objective line over an unperturbed
+    # FP64 run of the same length (as for the half-size CPW)
+    print("# large: FP64 run for the objective frequency", file=sys.stderr, flush=True)
+    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], torch.float64, wl["pml"])
+    sim.set_materials(*wl["maps"])
+    for s in wl["sources"]:
+        sim.add_source(**s)
+    z = [torch.zeros(sim.shape3, dtype=torch.float64, device="cuda")] * 3
+    sim.set_fields(z, z, z)
+    pid = sim.add_probe(wl["objective"][0], wl["objective"][1], steps + 1)
+    sim.step(steps)
+    series = np.asarray(sim.probe(pid)[0])
+    sim.close()
+    del sim, z
+    torch.cuda.empty_cache()
+    freqs = np.linspace(0.25 * wl["freq"], 2.0 * wl["freq"], 3501)
+    t = np.arange(series.size) * wl["dt"]
+    f0 = float(freqs[np.argmax(np.abs(np.exp(-2j * np.pi * np.outer(freqs, t)) @ series))])
+    obj = (wl["objective"][0], wl["objective"][1], f0)
+    out = {"workload": wl["name"], "steps": steps, "seg": seg, "seg2": seg2, "objective_f0": f0,
+           "source_f": wl["freq"]}
 
     def make(dtype, npdt):
         sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"])
@@ -266,9 +288,45 @@ def cpu_baseline(wl, steps):
     o.step(steps)
     dt = time.perf_counter() - t0
     n = wl["shape"][0] * wl["shape"][1] * wl["shape"][2]
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    from oracle import oracle as oracle_mod
+    cores = oracle_mod.threads()  # the OpenMP threads the oracle's grid sweeps run on
     return dict(value=n * steps / dt / 1e9, unit="Gcell-updates/s", cores=cores, kind="oracle",
                 sample=f"{steps} FP64 steps of the same {wl['shape'][0]}^3 grid ({dt:.1f} s)")
+
+
+def cpw_rate(steps=200, warmup=20):
+    """Step rate on the CPW-resonator-shaped grid (512 x 256 x 128, CPML on x and z, soft sources and two
+    FP64 probes every step): FP32 fields (the workload's precision) and FP64, with the kernels' own
+    HIP-event times (sweep, then sources and probes) and the wall time of the timed steps."""
+    import numpy as np
+    import torch
+
+    from paper_2305_13419_amd import Simulation, workloads
+
+    wl = workloads.cpw_grid(1)
+    n = int(np.prod(wl["shape"]))
+    out = {"workload": wl["name"] + " (CPML x, z; 2 soft sources, 2 FP64 probes)", "cells": n, "steps": steps}
+    for name, dt in (("f32", torch.float32), ("f64", torch.float64)):
+        npdt = np.float64 if dt == torch.float64 else np.float32
+        sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dt, wl["pml"])
+        sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
+        z = [np.zeros(sim.shape3, dtype=npdt)] * 3
+        sim.set_fields(z, z, z)
+        for s in wl["sources"]:
+            sim.add_source(**s)
+        for p in wl["probes"]:
+            sim.add_probe(p["comp"], p["box"], steps + warmup + 1)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h_ms, e_ms = sim.profile_step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sim.close()
+        ms = (h_ms + e_ms) / steps
+        out[name] = dict(value=n / (ms * 1e-3) / 1e9, unit="Gcell-updates/s", ms_per_step=ms,
+                         sweep_ms=h_ms / steps, sources_probes_ms=e_ms / steps, wall_ms_per_step=wall / steps * 1e3)
+    return out
 
 
 def table1_run():
@@ -411,7 +469,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--no-cpw", action="store_true", help="skip the CPW-shaped grid's step rate")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--large", action="store_true")
@@ -447,14 +506,16 @@ def main():
     ncell = args.n**3
     fJ = sc_edge_fraction(wl["maps"][2])
     res = {}
-    # product path: the fused sweep with edge classes; beside it the fused sweep on the per-cell maps
-    # and the two passes (the path of grids with CPML) with edge classes
-    modes = {"fused": (True, True), "fused_maps": (True, False), "two_pass": (False, True)}
+    # product path: the automatic sweep choice, i.e. two time steps per sweep with edge classes on this
+    # periodic grid; beside it one step per sweep (the fused sweep) with classes and on the per-cell
+    # maps, and the two passes (H pass, E pass) with classes
+    modes = {"auto": (True, True, "auto"), "fused": (True, True, "fused"), "fused_maps": (True, False, "fused"),
+             "two_pass": (False, True, "two_pass")}
     for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
-        for mode, (fused, classes) in modes.items():
+        for mode, (fused, classes, sweep) in modes.items():
             print(f"# {name} {mode}: {args.warmup} warm-up + {args.steps} timed steps on {wl['name']}",
                   file=sys.stderr, flush=True)
-            res[name, mode] = run_gpu(wl, dt, args.steps, args.warmup, fused, classes)
+            res[name, mode] = run_gpu(wl, dt, args.steps, args.warmup, fused, classes, sweep)
     copy_gbs = copy_bandwidth()
     out = {}
     for name, w in (("f64", 8), ("f32", 4)):
@@ -466,29 +527,50 @@ def main():
         e_cell = w * (9 + 6 * fJ) + 6
         h_cell = w * 9                             # H pass: E, H read; H written
 
-        def roof(kernel, ms, cell, traffic_key):
-            gbs = cell * ncell / (ms * 1e-3) / 1e9
+        # the method's minimum bytes per cell-update (E and H read and written once, Js read and written
+        # on the superconducting edges, three per-cell map words): the per-unit figure `achieved` uses
+        method_cell = w * (15 + 6 * fJ)
+
+        def roof(kernel, ms, cell, traffic_key, steps_per_launch=1):
+            """achieved = the method's minimum bytes per cell-update x the cell-updates of one launch / the
+            launch's average duration; kernel_* = the same with the bytes this kernel itself must move
+            (edge classes instead of maps: fewer than the method's minimum).  A launch that is part of a
+            step (steps_per_launch=0: the E pass) is measured by its own bytes."""
+            per_launch = method_cell * ncell * steps_per_launch if steps_per_launch else cell * ncell
+            gbs = per_launch / (ms * 1e-3) / 1e9
+            kgbs = cell * ncell / (ms * 1e-3) / 1e9
             traffic = measured_traffic(name, traffic_key)
             return dict(bound="hbm", kernel=kernel, achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=gbs / HBM_PEAK_GBS, traffic=traffic, bytes_per_cell=cell,
-                        algorithmic_bytes_per_launch=cell * ncell,
-                        # measured HBM bytes per launch over the launch time, and the algorithmic rate
+                        frac=gbs / HBM_PEAK_GBS, traffic=traffic,
+                        bytes_per_cell_update=method_cell if steps_per_launch else None,
+                        algorithmic_bytes_per_launch=per_launch,
+                        kernel_bytes_per_cell=cell, kernel_achieved=kgbs, kernel_frac=kgbs / HBM_PEAK_GBS,
+                        # measured HBM bytes per launch over the launch time, and the kernel's own rate
                         # against the runtime's device-to-device copy on this GPU
                         traffic_GBs=None if traffic is None else traffic / (ms * 1e-3) / 1e9,
-                        runtime_copy_GBs=copy_gbs, frac_of_runtime_copy=gbs / copy_gbs)
+                        runtime_copy_GBs=copy_gbs, frac_of_runtime_copy=kgbs / copy_gbs)
 
-        r, m, t = res[name, "fused"], res[name, "fused_maps"], res[name, "two_pass"]
+        a_, r, m, t = res[name, "auto"], res[name, "fused"], res[name, "fused_maps"], res[name, "two_pass"]
+        # the two-step sweep: one launch per two steps, reading and writing E, H, Js and the classes once
+        two = a_["sweep_counts"]["two_step"] == args.steps
+        spl = 2 if two else 1
         out[name] = dict(
-            value=ncell / (r["step_ms"] * 1e-3) / 1e9, ms_per_step=r["step_ms"], fused_step_ms=r["h_ms"],
-            nonfinite=r["nonfinite"], edge_classes=r["edge_classes"], bind_materials_s=r["bind_materials_s"],
-            roofline=roof("fused_step_kernel (edge classes)", r["h_ms"], f_cell, "fused_step_kernel"),
+            value=ncell / (a_["step_ms"] * 1e-3) / 1e9, ms_per_step=a_["step_ms"], sweep_counts=a_["sweep_counts"],
+            nonfinite=a_["nonfinite"], edge_classes=a_["edge_classes"], bind_materials_s=a_["bind_materials_s"],
+            roofline=dict(roof("two_step_kernel (edge classes)" if two else "fused_step_kernel (edge classes)",
+                               a_["h_ms"] * spl, f_cell, "two_step_kernel" if two else "fused_step_kernel", spl),
+                          steps_per_launch=spl, launch_ms=a_["h_ms"] * spl),
+            fused=dict(
+                value=ncell / (r["step_ms"] * 1e-3) / 1e9, ms_per_step=r["step_ms"], fused_step_ms=r["h_ms"],
+                nonfinite=r["nonfinite"], sweep_counts=r["sweep_counts"],
+                roofline=roof("fused_step_kernel (edge classes)", r["h_ms"], f_cell, "fused_step_kernel")),
             maps_path=dict(
                 value=ncell / (m["step_ms"] * 1e-3) / 1e9, ms_per_step=m["step_ms"], nonfinite=m["nonfinite"],
                 roofline=roof("fused_step_kernel (maps)", m["h_ms"], m_cell, "fused_step_kernel_maps")),
             two_pass=dict(
                 value=ncell / (t["step_ms"] * 1e-3) / 1e9, ms_per_step=t["step_ms"], h_pass_ms=t["h_ms"],
                 e_pass_ms=t["e_ms"], h_pass_GBs=h_cell * ncell / (t["h_ms"] * 1e-3) / 1e9, nonfinite=t["nonfinite"],
-                roofline=roof("e_pass_kernel (edge classes)", t["e_ms"], e_cell, "e_pass_kernel")),
+                roofline=roof("e_pass_kernel (edge classes)", t["e_ms"], e_cell, "e_pass_kernel", 0)),
         )
     f64 = out["f64"]
     line = {
@@ -510,6 +592,9 @@ def main():
         "f64": {k: v for k, v in f64.items() if k != "roofline"},
         "f32": out["f32"],
     }
+    if not args.no_cpw:
+        print("# cpw-shaped grid step rate", file=sys.stderr, flush=True)
+        line["cpw_shaped"] = cpw_rate()
     if not args.no_adjoint:
         ratios = {}
         for name, dt in (("f64", torch.float64), ("f32", torch.float32)):

@@ -147,10 +147,10 @@ int tfl_bind_state(tfl_sim *sim, void *const E[3], void *const H[3], void *const
  * workspace may be NULL when its size is 0. */
 int tfl_bind_workspace(tfl_sim *sim, void *workspace, void *scratch, void *stream);
 
-/* Optional second set of E and H fields for the fused sweep.
- * tfl_fused_buffer_bytes reports its size: 6 fields, each padded to 256
- * bytes, then on each CPML axis a second set of its two H-side auxiliary
- * variables (2 x the slab cells of the axis, padded to 256 bytes).
+/* Optional second set of E, H and Js fields for the fused sweeps.
+ * tfl_fused_buffer_bytes reports its size: 9 fields (E, H, Js), each padded
+ * to 256 bytes, then on each CPML axis a second set of its two H-side
+ * auxiliary variables (2 x the slab cells of the axis, padded to 256 bytes).
  * With a buffer bound, tfl_step runs H and E updates of a step in one sweep
  * (Algorithm 1, steps 1-5 of a time step fused): it reads E^n, H^{n-1/2} (and
  * the H-side CPML variables) from one set and writes E^{n+1}, H^{n+1/2} (and
@@ -159,11 +159,38 @@ int tfl_bind_workspace(tfl_sim *sim, void *workspace, void *scratch, void *strea
  * step instead of twice; results equal those of the two passes bit for bit.
  * Steps run in pairs (bound fields -> buffer -> bound fields), an odd last
  * step with the two passes, so the state is in the bound fields and the
- * workspace after every call.  The buffer is caller-owned device memory,
+ * workspace after every call.  On periodic grids with edge classes bound,
+ * stretches of at least four steps with no sources, probes or non-finite
+ * checks run two time steps per sweep (temporal blocking): each sweep reads
+ * E^n, H^{n-1/2}, Js^{n-1/2} from one set and writes E^{n+2}, H^{n+3/2},
+ * Js^{n+3/2} to the other, so per step each cell's fields cross HBM half as
+ * often; the results again equal those of the two passes bit for bit.  The buffer is caller-owned device memory,
  * 256-byte aligned, holding nothing between calls; bind NULL to go back to
  * the two passes.  TFL_E_INVAL on a misaligned buffer. */
 int tfl_fused_buffer_bytes(const tfl_sim *sim, size_t *bytes);
 int tfl_bind_fused_buffer(tfl_sim *sim, void *buffer);
+
+/* Which sweeps a step may take (the results are the same bits on every path).
+ *  TFL_SWEEP_AUTO      (default) the two-step sweep where it applies and pays
+ *                      (FP32 grids of at least 2^21 cells, nx >= 64,
+ *                      ny >= 32, nz >= 16; in FP64 it is no faster than the
+ *                      fused sweep), else the fused
+ *                      sweep where a buffer is bound and it pays (FP64 CPML
+ *                      grids below two rounds of its wavefronts take the
+ *                      two passes), else the two passes;
+ *  TFL_SWEEP_TWO_PASS  always the H and E passes;
+ *  TFL_SWEEP_FUSED     the fused sweep wherever a buffer is bound, no
+ *                      two-step sweep;
+ *  TFL_SWEEP_TWO_STEP  the two-step sweep wherever it applies (periodic grid,
+ *                      edge classes bound, buffer bound, no sources, probes or
+ *                      checks, stretches of four steps), whatever the size;
+ *                      the fused sweep elsewhere.
+ * tfl_sweep_counts: steps the last tfl_step call ran on the two passes, the
+ * fused sweep and the two-step sweep (counts[0..2]).  TFL_E_INVAL on a bad
+ * value. */
+enum { TFL_SWEEP_AUTO = 0, TFL_SWEEP_TWO_PASS = 1, TFL_SWEEP_FUSED = 2, TFL_SWEEP_TWO_STEP = 3 };
+int tfl_set_sweep(tfl_sim *sim, int32_t sweep);
+int tfl_sweep_counts(const tfl_sim *sim, int64_t counts[3]);
 
 /* Bind the per-cell maps (device, dtype, N elements each).  Validates them
  * on the device (eps_r > 0, sigma >= 0, inv_lambda2 >= 0, all finite) and

@@ -33,6 +33,7 @@ ERROR_NAMES = {
 
 TFL_F64, TFL_F32 = 0, 1
 TFL_PERIODIC, TFL_CPML = 0, 1
+TFL_SWEEP_AUTO, TFL_SWEEP_TWO_PASS, TFL_SWEEP_FUSED, TFL_SWEEP_TWO_STEP = 0, 1, 2, 3
 TFL_WAVE_SIN, TFL_WAVE_GAUSS, TFL_WAVE_MOD_GAUSS = 0, 1, 2
 TFL_MAX_SOURCES = 32
 TFL_MAX_PROBES = 32
@@ -113,6 +114,8 @@ SIGNATURES = {
     "tfl_clear_sources_probes": [P],
     "tfl_step": [P, ctypes.c_int64, P],
     "tfl_set_nonfinite_check": [P, ctypes.c_int64],
+    "tfl_set_sweep": [P, ctypes.c_int32],
+    "tfl_sweep_counts": [P, ctypes.POINTER(ctypes.c_int64)],
     "tfl_profile_step": [P, ctypes.c_int64, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "tfl_sync_integer_time": [P, PP, PP, P],
     "tfl_energy": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), P],

@@ -81,7 +81,7 @@ size_t round256(size_t bytes) { return (bytes + 255) & ~size_t(255); }
 size_t fused_layout(const tfl_sim *s, size_t psi_at[3], size_t *total)
 {
     const size_t fb = round256((size_t)s->N * s->esz);
-    size_t off = 6 * fb;
+    size_t off = 9 * fb;  // second E, H and Js
     for (int ax = 0; ax < 3; ++ax) {
         psi_at[ax] = off;
         if (s->cfg.bc[ax] == TFL_CPML) off += round256(2 * s->psi_count[ax] * s->esz);
@@ -126,6 +126,7 @@ StepArgs<T> make_args(const tfl_sim *s)
         a.H[q] = (T *)s->H[q];
         a.Hout[q] = (T *)s->H[q];
         a.J[q] = (T *)s->J[q];
+        a.Jout[q] = (T *)s->J[q];
     }
     a.eps = (const T *)s->eps;
     a.sig = (const T *)s->sig;
@@ -190,7 +191,16 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
     // fields, B the buffer), so the state is back in A after every call; an odd last step runs the
     // two passes in place on A.
     StepArgs<T> ab = a, ba = a;
-    const bool fused = s->fused != nullptr && fused_step_pays<T>(a);
+    const bool fused = s->fused != nullptr && s->sweep != TFL_SWEEP_TWO_PASS &&
+                       (s->sweep != TFL_SWEEP_AUTO || fused_step_pays<T>(a));
+    // Two steps per sweep (periodic grids with edge classes) where nothing happens between the steps:
+    // no sources, probes or non-finite checks.  Launches go A -> B -> A (E, H and Js), four steps per
+    // round trip, so the state is back in A; the remaining steps take the paths below.
+    const bool two_applies = fused && sa.nsrc == 0 && np == 0 && !(s->checking && s->check_every > 0) &&
+                             !(a.pml[0].on || a.pml[1].on || a.pml[2].on) && a.cls[0] != nullptr;
+    const bool two = two_applies && (s->sweep == TFL_SWEEP_TWO_STEP || (s->sweep == TFL_SWEEP_AUTO &&
+                                                                        two_step_pays<T>(a)));
+    StepArgs<T> ab2 = a, ba2 = a;
     if (fused) {
         size_t psi_at[3];
         const size_t fb = fused_layout(s, psi_at);
@@ -214,14 +224,45 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
             ba.pml[ax].psiHo[1] = a.pml[ax].psiH[1];
         }
     }
+    int64_t it = 0;
+    if (two) {
+        size_t psi_at[3];
+        const size_t fb = fused_layout(s, psi_at);
+        for (int q = 0; q < 3; ++q) {
+            T *eb = (T *)((char *)s->fused + q * fb), *hb = (T *)((char *)s->fused + (3 + q) * fb);
+            T *jb = (T *)((char *)s->fused + (6 + q) * fb);
+            ab2.Eout[q] = eb;
+            ab2.Hout[q] = hb;
+            ab2.Jout[q] = jb;
+            ba2.E[q] = eb;
+            ba2.H[q] = hb;
+            ba2.J[q] = jb;
+            ba2.Eout[q] = a.E[q];
+            ba2.Hout[q] = a.H[q];
+            ba2.Jout[q] = a.J[q];
+        }
+        for (; it + 4 <= nsteps; it += 4) {
+            for (int h = 0; h < 2; ++h) {
+                if (ev && (e = hipEventRecord(ev[2 * (it + 2 * h)], st)) != hipSuccess) return hip_fail(s, e, "event");
+                if ((e = launch_two_step<T>(h == 0 ? ab2 : ba2, st)) != hipSuccess) return hip_fail(s, e, "two steps");
+                // the two steps' events: the sweep in the first interval, the others empty
+                for (int q = 1; q < 4 && ev; ++q)
+                    if ((e = hipEventRecord(ev[2 * (it + 2 * h) + q], st)) != hipSuccess) return hip_fail(s, e, "event");
+            }
+            s->step += 4;
+            s->sweep_counts[2] += 4;
+        }
+    }
     bool inB = false;
-    for (int64_t it = 0; it < nsteps; ++it) {
+    for (; it < nsteps; ++it) {
         if (ev && (e = hipEventRecord(ev[2 * it], st)) != hipSuccess) return hip_fail(s, e, "event");
         if (fused && (inB || it + 1 < nsteps)) {
             if ((e = launch_fused_step<T>(inB ? ba : ab, st)) != hipSuccess) return hip_fail(s, e, "fused step");
             if (ev && (e = hipEventRecord(ev[2 * it + 1], st)) != hipSuccess) return hip_fail(s, e, "event");
             inB = !inB;
+            s->sweep_counts[1] += 1;
         } else {
+            s->sweep_counts[0] += 1;
             if ((e = launch_h_pass<T>(a, st)) != hipSuccess) return hip_fail(s, e, "h_pass");
             if (ev && (e = hipEventRecord(ev[2 * it + 1], st)) != hipSuccess) return hip_fail(s, e, "event");
             if ((e = launch_e_pass<T>(a, st)) != hipSuccess) return hip_fail(s, e, "e_pass");
@@ -626,9 +667,25 @@ int tfl_step(tfl_sim *s, int64_t nsteps, void *stream)
     if (nsteps < 0) return fail(s, TFL_E_INVAL, "nsteps must be >= 0");
     hipStream_t st = (hipStream_t)stream;
     if ((rc = nonfinite_begin(s, st)) != TFL_OK) return rc;
+    for (auto &c : s->sweep_counts) c = 0;
     rc = s->esz == 8 ? do_step<double>(s, nsteps, st) : do_step<float>(s, nsteps, st);
     const int rc2 = nonfinite_end(s, st);
     return rc != TFL_OK ? rc : rc2;
+}
+
+int tfl_set_sweep(tfl_sim *s, int32_t sweep)
+{
+    if (!s) return fail(nullptr, TFL_E_INVAL, "null handle");
+    if (sweep < TFL_SWEEP_AUTO || sweep > TFL_SWEEP_TWO_STEP) return fail(s, TFL_E_INVAL, "bad sweep %d", sweep);
+    s->sweep = sweep;
+    return TFL_OK;
+}
+
+int tfl_sweep_counts(const tfl_sim *s, int64_t counts[3])
+{
+    if (!s || !counts) return fail(nullptr, TFL_E_INVAL, "null argument");
+    for (int q = 0; q < 3; ++q) counts[q] = s->sweep_counts[q];
+    return TFL_OK;
 }
 
 int tfl_set_nonfinite_check(tfl_sim *s, int64_t every)
@@ -650,6 +707,7 @@ int tfl_profile_step(tfl_sim *s, int64_t nsteps, void *stream, double *h_ms, dou
     for (auto &x : ev)
         if ((e = hipEventCreate(&x)) != hipSuccess) break;
     if (e == hipSuccess) {
+        for (auto &c : s->sweep_counts) c = 0;
         rc = s->esz == 8 ? do_step<double>(s, nsteps, st, ev.data()) : do_step<float>(s, nsteps, st, ev.data());
         if (rc == TFL_OK) {
             e = hipEventSynchronize(ev.back());

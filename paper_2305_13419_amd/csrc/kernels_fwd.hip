@@ -586,6 +586,216 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
 }
 
 // ---------------------------------------------------------------------------
+// Two time steps in one sweep (temporal blocking; periodic grids, edge classes)
+// ---------------------------------------------------------------------------
+// A block covers a footprint of 64 x TY columns of the x-y plane (one wavefront per row) and marches
+// along z, one plane per iteration, the second step one plane behind the first:
+//   A  H^{n+1/2}(k) at the lane's own faces and at its x-1 and y-1 faces, from E^n and H^{n-1/2} read
+//      from global memory (the fused sweep's first half);
+//   B  Js^{n+1/2}(k) and E^{n+1}(k), kept in registers, E^{n+1}(k) also written to LDS;
+//   C  H^{n+3/2}(k-1) at the lane's own faces from E^{n+1}(k-1) (own, and x+1 / y+1 from LDS) and
+//      E^{n+1}(k) (own), written to LDS;
+//   D  Js^{n+3/2}(k-1) and E^{n+2}(k-1) from H^{n+3/2}(k-1) (own, and x-1 / y-1 from LDS) and
+//      H^{n+3/2}(k-2) (own, from the previous iteration).
+// Stage C is exact on lanes 0..62 and rows 0..TY-2 (the x+1 / y+1 neighbours of the last lane and row
+// lie outside the footprint), stage D on lanes 1..62 and rows 1..TY-2: a footprint's outputs are its
+// 62 x (TY-2) interior cells, footprints overlap by two columns and two rows (those cells are computed
+// by both), and along z a block computes the first step on two planes before its range.  Per cell the
+// sweep reads E, H, Js (on superconducting edges) and the classes once and writes them once for two
+// steps.  Every expression is the fused sweep's, so the results equal two fused steps bit for bit.
+static __device__ __forceinline__ int wrap_index(int v, int n)
+{
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+template <typename T, int TY, int TZ, bool NT>
+__global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<T> a)
+{
+    constexpr int OX = kTileX - 2, OY = TY - 2;
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const int ntx = (nx + OX - 1) / OX, nty = (ny + OY - 1) / OY, ntz = (nz + TZ - 1) / TZ;
+    const int t = logical_block(blockIdx.x, ntx * nty * ntz);
+    const int tx = t % ntx, tr = t / ntx, ty = tr % nty, tz = tr / nty;
+    const int lane = threadIdx.x, row = threadIdx.y;
+    const int xo = tx * OX + lane - 1, yo = ty * OY + row - 1;  // the cell's output coordinates
+    const int i = wrap_index(xo, nx), j = wrap_index(yo, ny);
+    const bool out = lane >= 1 && lane <= OX && xo < nx && row >= 1 && row <= OY && yo < ny;
+    const int k0 = tz * TZ, k1 = min(k0 + TZ, nz);
+    const long long sxy = a.g.sxy;
+    const int im = (i == 0) ? nx - 1 : i - 1, ip = (i + 1 == nx) ? 0 : i + 1;
+    const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j + 1 == ny) ? 0 : j + 1;
+    constexpr uint32_t w = sizeof(T);
+    const uint32_t o00 = uint32_t(j * nx + i) * w, o10 = uint32_t(j * nx + im) * w;
+    const uint32_t o01 = uint32_t(jm * nx + i) * w;
+    const uint32_t oxp = uint32_t(j * nx + ip) * w, oyp = uint32_t(jp * nx + i) * w;
+    const uint32_t oxm_yp = uint32_t(jp * nx + im) * w, oxp_ym = uint32_t(jm * nx + ip) * w;
+    const uint32_t oc = uint32_t(j * nx + i) * 2u;
+    const T rdx = a.rd[0], rdy = a.rd[1], rdz = a.rd[2], hdt = a.hdt;
+
+    __shared__ T lds_e[2][3][TY][kTileX];  // E^{n+1} of the last two planes
+    __shared__ T lds_h[3][TY][kTileX];     // H^{n+3/2} of the previous plane
+    const int lxp = min(lane + 1, kTileX - 1), lxm = max(lane - 1, 0);
+    const int ryp = min(row + 1, TY - 1), rym = max(row - 1, 0);
+
+    struct Classes {
+        uint32_t x, y, z;
+    };
+    auto load_cls = [&](int kk) {
+        const long long b = opaque_offset((long long)kk * sxy);
+        return Classes{ldp(a.cls[0] + b, oc), ldp(a.cls[1] + b, oc), ldp(a.cls[2] + b, oc)};
+    };
+    EdgeCoef<T> cx, cy, cz;
+    auto coefs = [&](const Classes &m) {
+        cx = class_coef(a.ctab, m.x);
+        cy = class_coef(a.ctab, m.y);
+        cz = class_coef(a.ctab, m.z);
+    };
+
+    // prologue: H^{n+1/2} (Hx, Hy) at plane k0-2 and E^n of plane k0-1 carried into the loop
+    const int kb = wrap_index(k0 - 1, nz), km0 = wrap_index(k0 - 2, nz);
+    T hx_km, hy_km, ex0, exm, ey0, eym;
+    {
+        const long long bm = (long long)km0 * sxy, b = (long long)kb * sxy;
+        const T *Ex = a.E[0] + bm, *Ey = a.E[1] + bm, *Ez = a.E[2] + bm;
+        const T exk = ldp(Ex, o00), eyk = ldp(Ey, o00), ez = ldp(Ez, o00);
+        const T exk1 = ldp(a.E[0] + b, o00), eyk1 = ldp(a.E[1] + b, o00);
+        const T ez_x = ldp(Ez, oxp), ez_y = ldp(Ez, oyp);
+        const T dyEz = (ez_y - ez) * rdy, dzEy = (eyk1 - eyk) * rdz;
+        const T dzEx = (exk1 - exk) * rdz, dxEz = (ez_x - ez) * rdx;
+        hx_km = ldp(a.H[0] + bm, o00) - hdt * (dyEz - dzEy);
+        hy_km = ldp(a.H[1] + bm, o00) - hdt * (dzEx - dxEz);
+        ex0 = exk1;
+        ey0 = eyk1;
+        exm = ldp(a.E[0] + b, o10);
+        eym = ldp(a.E[1] + b, o01);
+    }
+    coefs(load_cls(kb));
+
+    // carried from the previous plane k-1: H^{n+1/2}, E^{n+1}, Js^{n+3/2} (the London update of the
+    // second step, formed as soon as E^{n+1} exists), the E-update coefficients; and H^{n+3/2}(k-2)
+    T phx = T(0), phy = T(0), phz = T(0), pex = T(0), pey = T(0), pez = T(0);
+    T pjx = T(0), pjy = T(0), pjz = T(0);
+    EdgeCoef<T> px_ = {T(0), T(0), T(0)}, py_ = px_, pz_ = px_;
+    T qhx_km = T(0), qhy_km = T(0);
+
+    const int nit = (k1 - k0) + 2;
+    for (int it = 0; it < nit; ++it) {
+        const int kc = wrap_index(k0 - 1 + it, nz);
+        const int kn = (kc + 1 == nz) ? 0 : kc + 1;
+        const long long b = opaque_offset((long long)kc * sxy), bp = opaque_offset((long long)kn * sxy);
+        // ---- stages A and B at plane kc (the fused sweep's periodic arithmetic)
+        const EdgeCoef<T> qx = cx, qy = cy, qz = cz;
+        T jx = T(0), jy = T(0), jz = T(0);
+        if (qx.cj > T(0)) jx = ldp(a.J[0] + b, o00);
+        if (qy.cj > T(0)) jy = ldp(a.J[1] + b, o00);
+        if (qz.cj > T(0)) jz = ldp(a.J[2] + b, o00);
+        const T *Ex = a.E[0] + b, *Ey = a.E[1] + b, *Ez = a.E[2] + b;
+        const T *Hx = a.H[0] + b, *Hy = a.H[1] + b, *Hz = a.H[2] + b;
+        const T ex_yp = ldp(Ex, oyp), exm_yp = ldp(Ex, oxm_yp), ex_ym = ldp(Ex, o01);
+        const T ey_xp = ldp(Ey, oxp), ey_xm = ldp(Ey, o10), eym_xp = ldp(Ey, oxp_ym);
+        const T ez = ldp(Ez, o00), ez_xp = ldp(Ez, oxp), ez_yp = ldp(Ez, oyp), ez_xm = ldp(Ez, o10),
+                ez_ym = ldp(Ez, o01);
+        const T ex1 = ldp(a.E[0] + bp, o00), exm1 = ldp(a.E[0] + bp, o10);
+        const T ey1 = ldp(a.E[1] + bp, o00), eym1 = ldp(a.E[1] + bp, o01);
+        const T hx = ldp(Hx, o00), hy = ldp(Hy, o00), hz = ldp(Hz, o00);
+        const T hz_xm = ldp(Hz, o10), hy_xm = ldp(Hy, o10), hz_ym = ldp(Hz, o01), hx_ym = ldp(Hx, o01);
+        const Classes mn = load_cls(kn);
+
+        const T nhx = hx - hdt * ((ez_yp - ez) * rdy - (ey1 - ey0) * rdz);
+        const T nhy = hy - hdt * ((ex1 - ex0) * rdz - (ez_xp - ez) * rdx);
+        const T nhz = hz - hdt * ((ey_xp - ey0) * rdx - (ex_yp - ex0) * rdy);
+        const T nhz_xm = hz_xm - hdt * ((ey0 - ey_xm) * rdx - (exm_yp - exm) * rdy);
+        const T nhy_xm = hy_xm - hdt * ((exm1 - exm) * rdz - (ez - ez_xm) * rdx);
+        const T nhz_ym = hz_ym - hdt * ((eym_xp - eym) * rdx - (ex0 - ex_ym) * rdy);
+        const T nhx_ym = hx_ym - hdt * ((ez - ez_ym) * rdy - (eym1 - eym) * rdz);
+        T ex_n, ey_n, ez_n;  // E^{n+1} at plane kc
+        {
+            const T dyHz = (nhz - nhz_ym) * rdy, dzHy = (nhy - hy_km) * rdz;
+            const T dzHx = (nhx - hx_km) * rdz, dxHz = (nhz - nhz_xm) * rdx;
+            const T dxHy = (nhy - nhy_xm) * rdx, dyHx = (nhx - nhx_ym) * rdy;
+            if (qx.cj > T(0)) jx = jx + qx.cj * ex0;
+            if (qy.cj > T(0)) jy = jy + qy.cj * ey0;
+            if (qz.cj > T(0)) jz = jz + qz.cj * ez;
+            ex_n = qx.ca * ex0 + qx.cb * ((dyHz - dzHy) - jx);
+            ey_n = qy.ca * ey0 + qy.cb * ((dzHx - dxHz) - jy);
+            ez_n = qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz);
+        }
+        const int buf = it & 1;
+        lds_e[buf][0][row][lane] = ex_n;
+        lds_e[buf][1][row][lane] = ey_n;
+        lds_e[buf][2][row][lane] = ez_n;
+        __syncthreads();
+
+        // ---- stage C: H^{n+3/2} at plane kc - 1 (the fused sweep's H arithmetic on E^{n+1})
+        T h2x = T(0), h2y = T(0), h2z = T(0);
+        if (it >= 1) {
+            const int pb = buf ^ 1;
+            const T ez1_yp = lds_e[pb][2][ryp][lane], ex1_yp = lds_e[pb][0][ryp][lane];
+            const T ey1_xp = lds_e[pb][1][row][lxp], ez1_xp = lds_e[pb][2][row][lxp];
+            h2x = phx - hdt * ((ez1_yp - pez) * rdy - (ey_n - pey) * rdz);
+            h2y = phy - hdt * ((ex_n - pex) * rdz - (ez1_xp - pez) * rdx);
+            h2z = phz - hdt * ((ey1_xp - pey) * rdx - (ex1_yp - pex) * rdy);
+            lds_h[0][row][lane] = h2x;
+            lds_h[1][row][lane] = h2y;
+            lds_h[2][row][lane] = h2z;
+        }
+        __syncthreads();
+
+        // ---- stage D: Js^{n+3/2} and E^{n+2} at plane kc - 1, stored for the footprint's interior
+        if (it >= 2) {
+            const T h2z_xm = lds_h[2][row][lxm], h2y_xm = lds_h[1][row][lxm];
+            const T h2z_ym = lds_h[2][rym][lane], h2x_ym = lds_h[0][rym][lane];
+            const T dyHz = (h2z - h2z_ym) * rdy, dzHy = (h2y - qhy_km) * rdz;
+            const T dzHx = (h2x - qhx_km) * rdz, dxHz = (h2z - h2z_xm) * rdx;
+            const T dxHy = (h2y - h2y_xm) * rdx, dyHx = (h2x - h2x_ym) * rdy;
+            T j2x = pjx, j2y = pjy, j2z = pjz;
+            if (px_.cj > T(0)) j2x = j2x + px_.cj * pex;
+            if (py_.cj > T(0)) j2y = j2y + py_.cj * pey;
+            if (pz_.cj > T(0)) j2z = j2z + pz_.cj * pez;
+            const T e2x = px_.ca * pex + px_.cb * ((dyHz - dzHy) - j2x);
+            const T e2y = py_.ca * pey + py_.cb * ((dzHx - dxHz) - j2y);
+            const T e2z = pz_.ca * pez + pz_.cb * ((dxHy - dyHx) - j2z);
+            if (out) {
+                const int kw = (kc == 0) ? nz - 1 : kc - 1;
+                const long long bw = opaque_offset((long long)kw * sxy);
+                stp_hint<NT>(a.Hout[0] + bw, o00, h2x);
+                stp_hint<NT>(a.Hout[1] + bw, o00, h2y);
+                stp_hint<NT>(a.Hout[2] + bw, o00, h2z);
+                stp_hint<NT>(a.Eout[0] + bw, o00, e2x);
+                stp_hint<NT>(a.Eout[1] + bw, o00, e2y);
+                stp_hint<NT>(a.Eout[2] + bw, o00, e2z);
+                if (px_.cj > T(0)) stp(a.Jout[0] + bw, o00, j2x);
+                if (py_.cj > T(0)) stp(a.Jout[1] + bw, o00, j2y);
+                if (pz_.cj > T(0)) stp(a.Jout[2] + bw, o00, j2z);
+            }
+        }
+        // carry to the next plane
+        qhx_km = h2x;
+        qhy_km = h2y;
+        phx = nhx;
+        phy = nhy;
+        phz = nhz;
+        pex = ex_n;
+        pey = ey_n;
+        pez = ez_n;
+        pjx = jx;
+        pjy = jy;
+        pjz = jz;
+        px_ = qx;
+        py_ = qy;
+        pz_ = qz;
+        hx_km = nhx;
+        hy_km = nhy;
+        ex0 = ex1;
+        exm = exm1;
+        ey0 = ey1;
+        eym = eym1;
+        coefs(mn);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Soft sources and probes
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double waveform(int wave, double f, double t0, double tw, double t)
@@ -1138,6 +1348,62 @@ hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Two-step sweep: footprints of 64 x TY cells (the rows of a block share LDS), TZ output planes per
+// block.  Measured on 256^3 (TY 4 to 16, TZ 16 to 64): FP32 is fastest with TY = 16 (4 wavefronts per
+// SIMD, one block per CU) and TZ = 32, 0.250 ms per step against the fused sweep's 0.273; FP64 (168
+// VGPRs, 3 wavefronts per SIMD) with TY = 8 and TZ = 32, 0.554 against 0.562 ms: a block's wavefronts
+// wait for each other at the two barriers of every plane and no other block on the CU covers the
+// wait, which takes back most of what the halved traffic gains.
+template <typename T>
+struct TwoStepTiles;
+template <>
+struct TwoStepTiles<double> {
+    static constexpr int ty = 8;
+};
+template <>
+struct TwoStepTiles<float> {
+    static constexpr int ty = 16;
+};
+
+template <typename T, int TY, bool NT>
+static void launch_two_step_nt(const StepArgs<T> &a, hipStream_t s)
+{
+    constexpr int OX = kTileX - 2, OY = TY - 2;
+    const long long cols = (long long)((a.g.nx + OX - 1) / OX) * ((a.g.ny + OY - 1) / OY);
+    // z runs of 32 planes (at 256^3: 16 and 64 were 3-20 % slower), shorter where the grid would then
+    // give fewer than two blocks per CU (256 CUs)
+    int tz = 32;
+    while (tz > 8 && cols * ((a.g.nz + tz - 1) / tz) < 512) tz /= 2;
+    const dim3 blk(kTileX, TY);
+    const unsigned grd = (unsigned)(cols * ((a.g.nz + tz - 1) / tz));
+    switch (tz) {
+    case 64: hipLaunchKernelGGL((two_step_kernel<T, TY, 64, NT>), dim3(grd), blk, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((two_step_kernel<T, TY, 32, NT>), dim3(grd), blk, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((two_step_kernel<T, TY, 16, NT>), dim3(grd), blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((two_step_kernel<T, TY, 8, NT>), dim3(grd), blk, 0, s, a); break;
+    }
+}
+
+template <typename T>
+hipError_t launch_two_step(const StepArgs<T> &a, hipStream_t s)
+{
+    constexpr int TY = TwoStepTiles<T>::ty;
+    const double touched = (double)a.g.sxy * a.g.nz * (15.0 * sizeof(T) + 6.0);
+    if (touched > 512.0 * 1024 * 1024) launch_two_step_nt<T, TY, true>(a, s);
+    else launch_two_step_nt<T, TY, false>(a, s);
+    return hipGetLastError();
+}
+
+template <typename T>
+bool two_step_pays(const StepArgs<T> &a)
+{
+    if (a.pml[0].on || a.pml[1].on || a.pml[2].on || !a.cls[0]) return false;
+    // FP64: no faster than the fused sweep (above); FP32: the footprints' overlap costs (64/62)(16/14) in
+    // cells computed, repaid on grids well past the infinity cache
+    if (sizeof(T) != 4) return false;
+    return (long long)a.g.sxy * a.g.nz >= (1LL << 21) && a.g.nx >= 64 && a.g.ny >= 32 && a.g.nz >= 16;
+}
+
 // With its CPML code the FP64 fused sweep holds ~154 VGPRs (3 waves per SIMD, 3072 on the GPU);
 // below two rounds of such waves the two passes are faster.  Measured: 256 x 128 x 64 with CPML
 // on x and z (4096 waves) 94 us fused vs 85 us; 256^3 with the same slabs (8192 waves) 0.70 vs
@@ -1249,6 +1515,8 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
     template hipError_t launch_e_pass<T>(const StepArgs<T> &, hipStream_t);                                 \
     template hipError_t launch_fused_step<T>(const StepArgs<T> &, hipStream_t);                             \
     template bool fused_step_pays<T>(const StepArgs<T> &);                                                 \
+    template hipError_t launch_two_step<T>(const StepArgs<T> &, hipStream_t);                               \
+    template bool two_step_pays<T>(const StepArgs<T> &);                                                   \
     template hipError_t launch_class_table<T>(const StepArgs<T> &, const T *, const uint64_t *, int, T *,     \
                                               hipStream_t);                                                 \
     template hipError_t launch_sources<T>(const SrcArgs<T> &, hipStream_t);                                 \

@@ -43,6 +43,10 @@ struct tfl_sim {
     // reports it runs (tfl_step, tfl_forward_checkpointed), `checked` once a check was launched
     int64_t check_every = 0;
     bool checking = false, checked = false;
+    // sweep policy (TFL_SWEEP_*) and the steps of the last tfl_step call per path: two passes, fused
+    // sweep, two-step sweep
+    int sweep = TFL_SWEEP_AUTO;
+    int64_t sweep_counts[3] = {0, 0, 0};
     std::string err;
 };
 

@@ -50,6 +50,7 @@ struct StepArgs {
     T *H[3];
     T *Hout[3];  // where the fused sweep writes H^{n+1/2} (the two-pass H pass updates H in place)
     T *J[3];
+    T *Jout[3];  // where the two-step sweep writes Js^{n+3/2} (every other sweep updates Js in place)
     const T *eps, *sig, *ell;  // per-cell maps
     const uint16_t *cls[3];    // edge classes (x, y, z edges), or null: form coefficients from the maps
     const T *ctab;             // class table: 4 values (ca, cb, cj, 0) per class
@@ -193,6 +194,12 @@ template <typename T> hipError_t launch_fused_step(const StepArgs<T> &a, hipStre
 // Whether the fused sweep beats the two passes on this grid (false only for FP64 CPML grids too
 // small to fill the GPU at the fused sweep's occupancy).
 template <typename T> bool fused_step_pays(const StepArgs<T> &a);
+// Two time steps in one sweep (periodic grids with edge classes, no sources or probes in between):
+// reads E^n, H^{n-1/2}, Js^{n-1/2} from E, H, J and writes E^{n+2}, H^{n+3/2}, Js^{n+3/2} to Eout,
+// Hout, Jout, which must not overlap the inputs.  Results equal two fused steps bit for bit.
+template <typename T> hipError_t launch_two_step(const StepArgs<T> &a, hipStream_t s);
+// Whether the two-step sweep applies (periodic on every axis, edge classes bound) and pays on this grid.
+template <typename T> bool two_step_pays(const StepArgs<T> &a);
 // Class table of the edge-coefficient path: entry c = coefficients of the four cells
 // mat[(tuple[c] >> 16 q) & 0xffff], q = 0..3 (mat: eps_r, sigma, ell per cell material).
 template <typename T>

@@ -190,6 +190,18 @@ class Simulation:
     def step(self, n=1):
         self._call("tfl_step", ctypes.c_int64(int(n)), _stream())
 
+    SWEEPS = {"auto": 0, "two_pass": 1, "fused": 2, "two_step": 3}
+
+    def set_sweep(self, sweep):
+        """Sweep policy: 'auto' (default), 'two_pass', 'fused' or 'two_step' (tfl_set_sweep)."""
+        self._call("tfl_set_sweep", ctypes.c_int32(self.SWEEPS[sweep]))
+
+    def sweep_counts(self):
+        """Steps of the last step() call on (two passes, fused sweep, two-step sweep)."""
+        c = (ctypes.c_int64 * 3)()
+        self._call("tfl_sweep_counts", c)
+        return tuple(int(v) for v in c)
+
     def set_nonfinite_check(self, every):
         """Count NaN / Inf values of E, H and Js on the device after every `every`-th step (0: off);
         a step() or forward_checkpointed() that saw any raises TflError with code TFL_E_NONFINITE."""

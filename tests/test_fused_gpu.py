@@ -11,6 +11,17 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+def assert_paths(sim, steps, fused):
+    """The last step() call of `steps` steps ran the path under test: with the fused sweep, every pair
+    of steps fused and an odd last step on the two passes; without it, the two passes only."""
+    two_pass, fsd, two_step = sim.sweep_counts()
+    assert two_step == 0
+    if fused:
+        assert (fsd, two_pass) == (steps - steps % 2, steps % 2), sim.sweep_counts()
+    else:
+        assert (fsd, two_pass) == (0, steps), sim.sweep_counts()
+
+
 def run(wl, steps, dtype, fused, chunks=None):
     from paper_2305_13419_amd import Simulation
     npdt = np.float64 if dtype == torch.float64 else np.float32
@@ -24,8 +35,11 @@ def run(wl, steps, dtype, fused, chunks=None):
                    t0=2e-15, tw=8e-16)
     sim.add_source(comp=2, box=(10, 50, 5, 6, 20, 21), amplitude=-1.0, waveform="sin", freq=1e14)
     pid = sim.add_probe(1, (40, 41, 0, 21, 0, 40), steps + 1, [3e14])
+    if fused:
+        sim.set_sweep("fused")  # the fused sweep whatever the grid size (the automatic rule aside)
     for c in (chunks or [steps]):
         sim.step(c)
+        assert_paths(sim, c, fused)
     torch.cuda.synchronize()
     out = [t.clone() for t in sim.E + sim.H + sim.J] + [torch.tensor(np.asarray(sim.probe(pid)[0]))]
     sim.close()
@@ -54,7 +68,10 @@ def run_plain(wl, steps, dtype, fused):
     sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
     E, H, _ = wl["fields"]
     sim.set_fields([np.asarray(a, dtype=npdt) for a in E], [np.asarray(a, dtype=npdt) for a in H])
+    if fused:
+        sim.set_sweep("fused")  # the fused sweep whatever the grid size (the automatic rule aside)
     sim.step(steps)
+    assert_paths(sim, steps, fused)
     torch.cuda.synchronize()
     out = [t.clone() for t in sim.E + sim.H + sim.J]
     sim.close()
@@ -80,8 +97,8 @@ CPML_CASES = [((6, 5), None, (4, 7)), ((5, 5), (4, 3), (6, 4)), (None, (3, 4), N
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("pml", CPML_CASES)
 def test_fused_equals_two_pass_cpml(pml, dtype):
-    # FP64 on CPML grids takes the fused sweep only when its launch has at least 6144 wavefronts
-    # (64 x 4 column tiles, z runs of 8 planes here): 256 x 192 x 64 gives 4 * 48 * 8 * 4 = 6144
+    # a larger FP64 grid as well: the one the automatic rule sends to the fused sweep (256 x 192 x 64
+    # gives 6144 wavefronts); the sweep is forced in any case (set_sweep)
     shape = (256, 192, 64) if dtype == torch.float64 else (66, 21, 40)
     wl = workloads.random_medium(shape, seed=5, pml=pml)
     print(f"case: fused vs two-pass, {shape} CPML {pml}, 9 steps in chunks [4, 5], {dtype}", flush=True)

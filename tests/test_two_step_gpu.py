@@ -1,0 +1,94 @@
+"""The two-step sweep (two time steps per sweep on periodic grids with edge classes) gives the fields
+and currents of the fused sweep bit for bit: footprints that do not tile the grid (ragged x, y and z
+ranges, grids narrower than a footprint), odd remainders after the four-step groups, both storage
+types; and it matches the FP64 oracle."""
+import numpy as np
+import pytest
+
+from paper_2305_13419_amd import workloads
+from tests.helpers import compare, run_oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def run(wl, steps, dtype, sweep, chunks=None):
+    from paper_2305_13419_amd import Simulation
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"])
+    sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
+    assert sim.edge_classes > 0
+    E, H, J = wl["fields"]
+    sim.set_fields([np.asarray(a, dtype=npdt) for a in E], [np.asarray(a, dtype=npdt) for a in H],
+                   None if J is None else [np.asarray(a, dtype=npdt) for a in J])
+    sim.set_sweep(sweep)
+    counts = np.zeros(3, dtype=np.int64)
+    for c in (chunks or [steps]):
+        sim.step(c)
+        counts += np.array(sim.sweep_counts())
+    torch.cuda.synchronize()
+    out = ([t.clone() for t in sim.E + sim.H + sim.J], counts, sim)
+    return out
+
+
+SHAPES = [(256, 64, 32), (200, 50, 40), (130, 33, 17), (62, 10, 9), (40, 7, 70), (300, 12, 5)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_two_step_equals_fused(shape, dtype):
+    wl = workloads.roofline_grid(shape)
+    print(f"case: two-step vs fused, {shape}, {dtype}, 11 steps (chunks 8, 3) and 4", flush=True)
+    for chunks in ([8, 3], [4]):
+        steps = sum(chunks)
+        a, ca, sa = run(wl, steps, dtype, "two_step", chunks)
+        b, cb, sb = run(wl, steps, dtype, "fused", chunks)
+        expect_two = sum(c - c % 4 for c in chunks)
+        assert ca[2] == expect_two and cb[2] == 0, (ca, cb)
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+        sa.close()
+        sb.close()
+
+
+def test_two_step_is_automatic_on_large_periodic_fp32_grids():
+    """The default policy takes the two-step sweep on a large periodic FP32 grid with classes (FP64 keeps
+    the fused sweep, which is as fast), and not where sources or probes act every step."""
+    from paper_2305_13419_amd import Simulation
+    wl = workloads.roofline_grid((128, 128, 128))
+    E, H, _ = wl["fields"]
+    for dtype, expect in ((torch.float32, (0, 2, 8)), (torch.float64, (0, 10, 0))):
+        sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype)
+        sim.set_materials(*wl["maps"])
+        sim.set_fields(E, H)
+        sim.step(10)
+        assert sim.sweep_counts() == expect
+        sim.add_probe(0, (5, 6, 0, 128, 7, 8), 0)
+        sim.step(10)
+        assert sim.sweep_counts() == (0, 10, 0)
+        sim.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_two_step_matches_oracle(dtype, tol):
+    wl = workloads.random_medium((130, 33, 20), seed=19)
+    # few distinct materials, so that edge classes bind: the random boxes of the roofline workload; the
+    # medium's initial Js (on its own superconducting cells) is dropped with its maps
+    wl["maps"] = workloads.roofline_grid((130, 33, 20))["maps"]
+    wl["fields"] = (wl["fields"][0], wl["fields"][1], None)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    wl["fields"] = tuple(None if g is None else [np.asarray(a, dtype=npdt).astype(np.float64) for a in g]
+                         for g in wl["fields"])
+    wl["maps"] = tuple(np.asarray(m, dtype=npdt).astype(np.float64) for m in wl["maps"])
+    steps = 12
+    a, counts, sim = run(wl, steps, dtype, "two_step")
+    assert counts[2] == 12
+    Eg, Hg, Jg = sim.integer_time_fields()
+    torch.cuda.synchronize()
+    g = ([t.double().cpu().numpy() for t in Eg], [t.double().cpu().numpy() for t in Hg],
+         [t.double().cpu().numpy() for t in Jg], [])
+    sim.close()
+    o = run_oracle(wl, steps)
+    r = compare(g, o)
+    print(f"two-step {dtype} vs oracle, 12 steps: {r}", flush=True)
+    assert max(r.values()) <= tol
