@@ -136,7 +136,9 @@ const char *tfl_last_error(const tfl_sim *sim);
 
 /* Byte sizes of the caller-owned buffers: the workspace (CPML coefficient
  * tables and auxiliary variables; 0 when no axis is CPML), a scratch buffer
- * for reductions, and one saved state (E, H, Js and the workspace). */
+ * (1 MiB: reductions, probe descriptors, and the copies of the probe boxes
+ * that the sweeps hand to the next sweep), and one saved state (E, H, Js and
+ * the workspace). */
 int tfl_buffer_sizes(const tfl_sim *sim, size_t *workspace_bytes, size_t *scratch_bytes, size_t *state_bytes);
 
 /* Bind the nine state arrays (device, dtype, N elements each). */
@@ -245,7 +247,14 @@ int tfl_add_source(tfl_sim *sim, const tfl_source *src, int *id);
 int tfl_add_probe(tfl_sim *sim, const tfl_probe *probe, int *id);
 int tfl_clear_sources_probes(tfl_sim *sim);
 
-/* Advance nsteps >= 0 time steps (Algorithm 1), with sources and probes. */
+/* Advance nsteps >= 0 time steps (Algorithm 1), with sources and probes.
+ * The sources are added inside the sweep that updates E.  With at most four
+ * probes whose boxes fit the scratch copy space (448 KiB per copy: e.g. 57344
+ * FP64 values over all boxes), each sweep also copies the new E on the boxes to
+ * scratch and the next sweep sums the copies of the previous one (one probe
+ * launch after the call's last step sums the last copies), so a step is one
+ * launch; otherwise a probe launch follows every step.  The sums are formed in
+ * the same order either way. */
 int tfl_step(tfl_sim *sim, int64_t nsteps, void *stream);
 
 /* Optional non-finite check (a guard for long runs; off by default).  With
@@ -260,10 +269,11 @@ int tfl_step(tfl_sim *sim, int64_t nsteps, void *stream);
  * (Stability is otherwise guarded by the dt bound of tfl_bind_materials.) */
 int tfl_set_nonfinite_check(tfl_sim *sim, int64_t every);
 
-/* tfl_step with HIP events recorded on `stream` around each pass of every
- * step; returns the summed device time of the H passes and of the E passes
- * (the latter including the source and probe launches that follow them) in
- * milliseconds.  Synchronises `stream`.  For measurement only. */
+/* tfl_step with HIP events recorded on `stream` at the start of every step and
+ * after its first launch; returns the summed device time of the first launches
+ * (the H pass of the two passes, the whole fused sweep) and of the rest of the
+ * steps (the E pass, probe launches) in milliseconds.  Synchronises `stream`.
+ * For measurement only. */
 int tfl_profile_step(tfl_sim *sim, int64_t nsteps, void *stream, double *h_ms, double *e_ms);
 
 /* Integer-time values at the current step n (Algorithm 1 steps 1 and 2 of

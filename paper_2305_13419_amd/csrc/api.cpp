@@ -164,12 +164,8 @@ StepArgs<T> make_args(const tfl_sim *s)
 template <typename T>
 int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool probes)
 {
-    const StepArgs<T> a = make_args<T>(s);
-    SrcArgs<T> sa{};
-    sa.g = a.g;
-    for (int q = 0; q < 3; ++q) sa.E[q] = a.E[q];
-    sa.nsrc = (int)s->src.size();
-    for (int q = 0; q < sa.nsrc; ++q) sa.src[q] = s->src[q];
+    StepArgs<T> a = make_args<T>(s);
+    source_boxes(s, a.side);
     ProbeArgs<T> pa{};
     pa.g = a.g;
     for (int q = 0; q < 3; ++q) pa.E[q] = a.E[q];
@@ -187,6 +183,54 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
         if ((e = launch_probes<T>(pa, np, st)) != hipSuccess) return hip_fail(s, e, "probe");
         s->sampled0 = true;
     }
+    // Probes ride along with the sweeps when there are few enough and their boxes fit the copy
+    // halves of scratch: each sweep copies its new E on the boxes to one half and first sums the
+    // copies the previous sweep left in the other; one probe launch after the last step sums the
+    // last copies.  Otherwise a probe launch follows every step.
+    size_t coff[kFoldProbes] = {};
+    bool fold = np > 0 && np <= kFoldProbes;
+    {
+        size_t off = 0;
+        for (int p = 0; p < np && fold; ++p) {
+            const ProbeDesc &d = s->probe[p];
+            coff[p] = off;
+            off += round256((size_t)(d.i1 - d.i0) * (d.j1 - d.j0) * (d.k1 - d.k0) * sizeof(T));
+            fold = off <= kProbeCopyHalf;
+        }
+    }
+    char *const copy_base = (char *)s->scratch + kProbeCopyOffset;
+    if (fold) {
+        a.side.pdesc = pa.p;
+        a.side.dt = s->cfg.dt;
+        for (int p = 0; p < np; ++p) {
+            const ProbeDesc &d = s->probe[p];
+            const int bx[7] = {d.comp, d.i0, d.i1, d.j0, d.j1, d.k0, d.k1};
+            for (int c = 0; c < 7; ++c) a.side.pbox[p][c] = bx[c];
+        }
+    }
+    int half = 0;          // copy half the next sweep writes
+    bool pending = false;  // copies of sample pending_n wait in the other half
+    int64_t pending_n = 0;
+    // the side work of the sweep of step s->step -> s->step + 1
+    auto side = [&](StepArgs<T> g) {
+        source_values(s, g.side, (double)(s->step + 1) * s->cfg.dt);
+        if (fold) {
+            g.side.nprobe = np;
+            g.side.nred = pending ? np : 0;
+            g.side.rn = pending_n;
+            for (int p = 0; p < np; ++p) {
+                g.side.pcopy[p] = copy_base + half * kProbeCopyHalf + coff[p];
+                g.side.rcopy[p] = copy_base + (1 - half) * kProbeCopyHalf + coff[p];
+            }
+        }
+        return g;
+    };
+    auto side_done = [&]() {
+        if (!fold) return;
+        pending = true;
+        pending_n = s->step;  // after the increment: the sample index of the new E
+        half = 1 - half;
+    };
     // With a fused buffer bound, steps go A -> B -> A in pairs through the fused sweep (A the bound
     // fields, B the buffer), so the state is back in A after every call; an odd last step runs the
     // two passes in place on A.
@@ -196,7 +240,7 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
     // Two steps per sweep (periodic grids with edge classes) where nothing happens between the steps:
     // no sources, probes or non-finite checks.  Launches go A -> B -> A (E, H and Js), four steps per
     // round trip, so the state is back in A; the remaining steps take the paths below.
-    const bool two_applies = fused && sa.nsrc == 0 && np == 0 && !(s->checking && s->check_every > 0) &&
+    const bool two_applies = fused && a.side.nsrc == 0 && np == 0 && !(s->checking && s->check_every > 0) &&
                              !(a.pml[0].on || a.pml[1].on || a.pml[2].on) && a.cls[0] != nullptr;
     const bool two = two_applies && (s->sweep == TFL_SWEEP_TWO_STEP || (s->sweep == TFL_SWEEP_AUTO &&
                                                                         two_step_pays<T>(a)));
@@ -257,7 +301,7 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
     for (; it < nsteps; ++it) {
         if (ev && (e = hipEventRecord(ev[2 * it], st)) != hipSuccess) return hip_fail(s, e, "event");
         if (fused && (inB || it + 1 < nsteps)) {
-            if ((e = launch_fused_step<T>(inB ? ba : ab, st)) != hipSuccess) return hip_fail(s, e, "fused step");
+            if ((e = launch_fused_step<T>(side(inB ? ba : ab), st)) != hipSuccess) return hip_fail(s, e, "fused step");
             if (ev && (e = hipEventRecord(ev[2 * it + 1], st)) != hipSuccess) return hip_fail(s, e, "event");
             inB = !inB;
             s->sweep_counts[1] += 1;
@@ -265,25 +309,19 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
             s->sweep_counts[0] += 1;
             if ((e = launch_h_pass<T>(a, st)) != hipSuccess) return hip_fail(s, e, "h_pass");
             if (ev && (e = hipEventRecord(ev[2 * it + 1], st)) != hipSuccess) return hip_fail(s, e, "event");
-            if ((e = launch_e_pass<T>(a, st)) != hipSuccess) return hip_fail(s, e, "e_pass");
+            if ((e = launch_e_pass<T>(side(a), st)) != hipSuccess) return hip_fail(s, e, "e_pass");
         }
-        for (int q = 0; q < 3; ++q) {
-            sa.E[q] = inB ? ab.Eout[q] : a.E[q];
-            pa.E[q] = sa.E[q];
-        }
-        if (sa.nsrc > 0) {
-            sa.t = (double)(s->step + 1) * s->cfg.dt;
-            if ((e = launch_sources<T>(sa, st)) != hipSuccess) return hip_fail(s, e, "source");
-        }
+        for (int q = 0; q < 3; ++q) pa.E[q] = inB ? ab.Eout[q] : a.E[q];
         s->step += 1;
-        if (np > 0) {
+        side_done();
+        if (np > 0 && !fold) {
             pa.n = s->step;
             if ((e = launch_probes<T>(pa, np, st)) != hipSuccess) return hip_fail(s, e, "probe");
         }
         if (s->checking && s->check_every > 0 && s->step % s->check_every == 0) {
             NonfiniteArgs<T> na{};
             for (int q = 0; q < 3; ++q) {
-                na.f[q] = sa.E[q];
+                na.f[q] = pa.E[q];
                 na.f[3 + q] = inB ? ab.Hout[q] : a.H[q];
                 na.f[6 + q] = a.J[q];
             }
@@ -292,6 +330,11 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
             if ((e = launch_nonfinite<T>(na, ctr, s->step, st)) != hipSuccess) return hip_fail(s, e, "non-finite check");
             s->checked = true;
         }
+    }
+    if (pending) {  // the last sweep's copies
+        pa.n = pending_n;
+        for (int p = 0; p < np; ++p) pa.copy[p] = (const T *)(copy_base + (1 - half) * kProbeCopyHalf + coff[p]);
+        if ((e = launch_probes<T>(pa, np, st)) != hipSuccess) return hip_fail(s, e, "probe");
     }
     if (ev && nsteps > 0 && (e = hipEventRecord(ev[2 * nsteps], st)) != hipSuccess) return hip_fail(s, e, "event");
     return TFL_OK;
@@ -346,6 +389,29 @@ int check_bound(tfl_sim *s, bool need_maps)
     if (!s->work_bound) return fail(s, TFL_E_STATE, "workspace not bound (tfl_bind_workspace)");
     if (need_maps && !s->maps_bound) return fail(s, TFL_E_STATE, "materials not bound (tfl_bind_materials)");
     return TFL_OK;
+}
+
+double source_value(const SourceDesc &d, double t)
+{
+    if (d.wave == TFL_WAVE_SIN) return d.amp * std::sin(kTwoPi * d.f * t);
+    const double g = std::exp(-(t - d.t0) * (t - d.t0) / (2.0 * d.tw * d.tw));
+    return d.amp * (d.wave == TFL_WAVE_GAUSS ? g : g * std::sin(kTwoPi * d.f * t));
+}
+
+void source_boxes(const tfl_sim *s, SideArgs &sd)
+{
+    sd.nsrc = (int)s->src.size();
+    for (int q = 0; q < sd.nsrc; ++q) {
+        const SourceDesc &d = s->src[q];
+        const int bx[7] = {d.comp, d.i0, d.i1, d.j0, d.j1, d.k0, d.k1};
+        for (int c = 0; c < 7; ++c) sd.sbox[q][c] = bx[c];
+        sd.sg[q] = 0.0;
+    }
+}
+
+void source_values(const tfl_sim *s, SideArgs &sd, double t)
+{
+    for (int q = 0; q < sd.nsrc; ++q) sd.sg[q] = source_value(s->src[q], t);
 }
 
 bool box_ok(const tfl_config &c, const int64_t *b)
@@ -612,7 +678,6 @@ int tfl_add_source(tfl_sim *s, const tfl_source *src, int *id)
     d.i0 = (int)src->box[0]; d.i1 = (int)src->box[1];
     d.j0 = (int)src->box[2]; d.j1 = (int)src->box[3];
     d.k0 = (int)src->box[4]; d.k1 = (int)src->box[5];
-    d.count = (long long)(d.i1 - d.i0) * (d.j1 - d.j0) * (d.k1 - d.k0);
     d.amp = src->amplitude;
     d.wave = src->waveform;
     d.f = src->freq;

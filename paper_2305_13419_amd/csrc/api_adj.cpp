@@ -117,14 +117,6 @@ int forward_ckpt(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg
     return TFL_OK;
 }
 
-// Value a soft source adds at time t (the waveforms of the source kernel).
-double source_value(const SourceDesc &d, double t)
-{
-    if (d.wave == TFL_WAVE_SIN) return d.amp * std::sin(kTwoPi * d.f * t);
-    const double g = std::exp(-(t - d.t0) * (t - d.t0) / (2.0 * d.tw * d.tw));
-    return d.amp * (d.wave == TFL_WAVE_GAUSS ? g : g * std::sin(kTwoPi * d.f * t));
-}
-
 template <typename T>
 struct Reverse {
     tfl_sim *s;
@@ -159,10 +151,7 @@ struct Reverse {
             if (e != hipSuccess) return hip_fail(s, e, "snapshot");
         }
         StepArgs<T> f = make_args<T>(s);
-        SrcArgs<T> fs{};
-        fs.g = f.g;
-        fs.nsrc = (int)s->src.size();
-        for (int q = 0; q < fs.nsrc; ++q) fs.src[q] = s->src[q];
+        source_boxes(s, f.side);
         const double dt = s->cfg.dt;
         // With the fused buffer bound (and the fused sweep paying on this grid) the recomputation
         // runs the fused sweep: E goes from snapshot t to snapshot t + 1 as in the two passes, H and
@@ -195,24 +184,20 @@ struct Reverse {
             for (int q = 0; q < 3; ++q) {
                 g.E[q] = snapE(t, q);
                 g.Eout[q] = snapE(t + 1, q);
-                fs.E[q] = snapE(t + 1, q);
             }
+            source_values(s, g.side, (double)(s0 + t + 1) * dt);
             if (fused) {
                 if ((e = launch_fused_step<T>(g, st)) != hipSuccess) return hip_fail(s, e, "recompute fused step");
             } else {
                 if ((e = launch_h_pass<T>(g, st)) != hipSuccess) return hip_fail(s, e, "recompute h_pass");
                 if ((e = launch_e_pass<T>(g, st)) != hipSuccess) return hip_fail(s, e, "recompute e_pass");
             }
-            if (fs.nsrc > 0) {
-                fs.t = (double)(s0 + t + 1) * dt;
-                if ((e = launch_sources<T>(fs, st)) != hipSuccess) return hip_fail(s, e, "recompute sources");
-            }
         }
         s->step = s0 + len;
         const int64_t end = s0 + len;
         for (int64_t n = end; n >= s0 + 1; --n) {
             if (n != end && (e = launch_adj_faces<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint faces");
-            for (int q = 0; q < A.nsrc; ++q) A.sg[q] = source_value(s->src[q], (double)n * dt);
+            source_values(s, A.f.side, (double)n * dt);
             A.doC = (n != nend);
             A.doA = 1;
             A.obj = 1;
@@ -272,12 +257,7 @@ int make_reverse(tfl_sim *s, const tfl_objective *o, const double F[2], void *sn
     for (int q = 0; q < 3; ++q) { A.gS[q] = (double *)p; p += L.grad; }
     A.ocomp = o->comp;
     for (int q = 0; q < 6; ++q) A.ob[q] = (int)o->box[q];
-    A.nsrc = (int)s->src.size();
-    for (int q = 0; q < A.nsrc; ++q) {
-        const SourceDesc &d = s->src[q];
-        const int bx[7] = {d.comp, d.i0, d.i1, d.j0, d.j1, d.k0, d.k1};
-        for (int c = 0; c < 7; ++c) A.sbox[q][c] = bx[c];
-    }
+    source_boxes(s, A.f.side);
     return TFL_OK;
 }
 

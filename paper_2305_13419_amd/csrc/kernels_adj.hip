@@ -390,11 +390,12 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
                 gS[q] = ldo(A.gS[q] + b, od);
             }
             // E'_pre: the soft sources of this step taken out of the stored E^{m+1}
-            for (int sidx = 0; sidx < A.nsrc; ++sidx) {
-                if (k >= A.sbox[sidx][5] && k < A.sbox[sidx][6] && jw >= A.sbox[sidx][3] && jw < A.sbox[sidx][4] &&
-                    i >= A.sbox[sidx][1] && i < A.sbox[sidx][2]) {
-                    const int c = A.sbox[sidx][0];
-                    const double g = A.sg[sidx];
+            const SideArgs &sd = A.f.side;
+            for (int sidx = 0; sidx < sd.nsrc; ++sidx) {
+                if (k >= sd.sbox[sidx][5] && k < sd.sbox[sidx][6] && jw >= sd.sbox[sidx][3] && jw < sd.sbox[sidx][4] &&
+                    i >= sd.sbox[sidx][1] && i < sd.sbox[sidx][2]) {
+                    const int c = sd.sbox[sidx][0];
+                    const double g = sd.sg[sidx];
                     // selects, not a store to Ep[c]: a variable index would move Ep to scratch memory
                     Ep[0] = (c == 0) ? (T)((double)Ep[0] - g) : Ep[0];
                     Ep[1] = (c == 1) ? (T)((double)Ep[1] - g) : Ep[1];

@@ -19,7 +19,9 @@
 // from the grid size), so the z neighbour of every stencil comes from
 // registers; x and y neighbours come from L1/L2.  Blocks are renumbered so that each XCD
 // (blocks are dealt to the 8 XCDs round robin) receives a contiguous range of
-// tiles, keeping the halo rows of neighbouring tiles in the same L2.
+// tiles, keeping the halo rows of neighbouring tiles in the same L2.  The soft
+// sources and the probe samples of a step ride along with the sweep that
+// writes E^{n+1} (SideArgs), so a step with sources and probes is one launch.
 #include <mutex>
 
 #include "fdtd_common.h"
@@ -107,12 +109,107 @@ __device__ __forceinline__ EdgeCoef<T> edge_coef(const T e[4], const T s[4], con
     return {(eps - (T(1) - theta) * sdt) * inv, dt * inv, hdt * ell};
 }
 
+// ---------------------------------------------------------------------------
+// Soft sources and probes (Sec. 4.2, 5), folded into the E update of a sweep
+// ---------------------------------------------------------------------------
+constexpr int kProbeThreads = 256;
+
+// Sum of the cnt values of a probe box, load(idx) in box order (x fastest), formed as 256 lanes
+// would: lane t adds idx = t, t + 256, ... in order, each wavefront of 64 such lanes folds its sums
+// by shuffles, and the four wavefront sums are added in order.  A block of any whole number of
+// wavefronts gives the same bits (its wavefronts take the four parts in turn); every thread gets
+// the sum.
+template <typename Load>
+__device__ __forceinline__ double probe_sum(long long cnt, Load load)
+{
+    __shared__ double part[kProbeThreads / 64];
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int lane = tid & 63, nw = (int)(blockDim.x * blockDim.y) >> 6;
+    for (int vw = tid >> 6; vw < kProbeThreads / 64; vw += nw) {
+        double acc = 0.0;
+        for (long long idx = vw * 64 + lane; idx < cnt; idx += kProbeThreads) acc += load(idx);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if (lane == 0) part[vw] = acc;
+    }
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kProbeThreads / 64; ++w) s += part[w];
+    return s;
+}
+
+// Sample n of probe p: the series value and the running DFT sum_n s_n dt exp(-2 pi i f n dt).
+__device__ __forceinline__ void probe_record(const ProbeDesc &p, double s, long long n, double dt)
+{
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    if (tid == 0 && p.series != nullptr && n < p.cap) p.series[n] = s;
+    if (tid < p.nfreq) {
+        const double ph = kTwoPi * p.freq[tid] * (double)n * dt;
+        p.dft[2 * tid] += s * dt * cos(ph);
+        p.dft[2 * tid + 1] -= s * dt * sin(ph);
+    }
+}
+
+// Side work a wavefront can meet: bit p (p < 32) for source p, bit 32 + p for probe p, set when the
+// box holds an edge of some lane's column (i, j) within planes [k0, k1).  Uniform over the
+// wavefront, so the sweep's planes skip the side work with one scalar test where the mask is empty
+// (nearly everywhere).
+__device__ __forceinline__ uint64_t side_mask(const SideArgs &sd, int i, int j, int k0, int k1)
+{
+    uint64_t m = 0;
+    auto meets = [&](const int *b) {
+        return __any(i >= b[1] && i < b[2] && j >= b[3] && j < b[4] && k0 < b[6] && b[5] < k1);
+    };
+    for (int p = 0; p < sd.nsrc; ++p)
+        if (meets(sd.sbox[p])) m |= 1ull << p;
+    for (int p = 0; p < sd.nprobe; ++p)
+        if (meets(sd.pbox[p])) m |= 1ull << (32 + p);
+    return m;
+}
+
+// Side work at the new E of edge (i, j, k), component q, after the PEC walls, for the sources and
+// probes of mask m: the sources whose boxes hold the edge add their values in source order, and the
+// probes whose boxes hold it receive a copy of the result.
+template <typename T>
+__device__ __forceinline__ T side_e(const SideArgs &sd, uint64_t m, int q, int i, int j, int k, T v)
+{
+    for (uint32_t ms = (uint32_t)m; ms != 0; ms &= ms - 1) {
+        const int *b = sd.sbox[__builtin_ctz(ms)];
+        if (b[0] == q && k >= b[5] && k < b[6] && j >= b[3] && j < b[4] && i >= b[1] && i < b[2])
+            v = (T)((double)v + sd.sg[__builtin_ctz(ms)]);
+    }
+    for (uint32_t mp = (uint32_t)(m >> 32); mp != 0; mp &= mp - 1) {
+        const int p = __builtin_ctz(mp);
+        const int *b = sd.pbox[p];
+        if (b[0] == q && k >= b[5] && k < b[6] && j >= b[3] && j < b[4] && i >= b[1] && i < b[2]) {
+            const long long c = ((long long)(k - b[5]) * (b[4] - b[3]) + (j - b[3])) * (b[2] - b[1]) + (i - b[1]);
+            ((T *)sd.pcopy[p])[c] = v;
+        }
+    }
+    return v;
+}
+
+// First thing of a sweep: blocks 0 .. nred-1 record the previous sweep's probe sample rn, one probe
+// per block, from the copies it left.
+template <typename T>
+__device__ __forceinline__ void side_reduce(const SideArgs &sd)
+{
+    if ((int)blockIdx.x >= sd.nred) return;
+    const ProbeDesc &p = sd.pdesc[blockIdx.x];
+    const T *c = (const T *)sd.rcopy[blockIdx.x];
+    const long long cnt = (long long)(p.i1 - p.i0) * (p.j1 - p.j0) * (p.k1 - p.k0);
+    const double s = probe_sum(cnt, [c](long long idx) { return (double)c[idx]; });
+    probe_record(p, s, sd.rn, sd.dt);
+}
+
 template <typename T, int TY, int TZ, bool CLS, int W>
 __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const StepArgs<T> a)
 {
+    side_reduce<T>(a.side);
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     int i, j, k0, k1;
     if (!tile_of_w<TY, TZ, W>(nx, ny, nz, i, j, k0, k1)) return;
+    const uint64_t side = side_mask(a.side, i, j, k0, k1);
     const long long sxy = a.g.sxy;
     const int im = (i == 0) ? nx - 1 : i - 1;
     const int jm = (j == 0) ? ny - 1 : j - 1;
@@ -240,10 +337,17 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const
         const T nez = qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz);
         // E and Eout are the same arrays except in the adjoint's recomputation; each lane reads E at
         // its own offset before writing Eout there and no other lane touches that word
+        T vx = (wall_y || wall_z) ? T(0) : nex, vy = (wall_z || wall_x) ? T(0) : ney;
+        T vz = (wall_x || wall_y) ? T(0) : nez;
+        if (side != 0) {
+            vx = side_e(a.side, side, 0, i, j, k, vx);
+            vy = side_e(a.side, side, 1, i, j, k, vy);
+            vz = side_e(a.side, side, 2, i, j, k, vz);
+        }
         T *Exo = a.Eout[0] + b, *Eyo = a.Eout[1] + b, *Ezo = a.Eout[2] + b;
-        stp(Exo, o00, (wall_y || wall_z) ? T(0) : nex);
-        stp(Eyo, o00, (wall_z || wall_x) ? T(0) : ney);
-        stp(Ezo, o00, (wall_x || wall_y) ? T(0) : nez);
+        stp(Exo, o00, vx);
+        stp(Eyo, o00, vy);
+        stp(Ezo, o00, vz);
         hx_km = hx;
         hy_km = hy;
         coefs(mn);
@@ -272,9 +376,11 @@ __global__ __launch_bounds__(kTileX *TY, TFL_MIN_WAVES) void e_pass_kernel(const
 template <typename T, int TY, int TZ, bool CLS, bool NT, int TX, bool PML>
 __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const StepArgs<T> a)
 {
+    side_reduce<T>(a.side);
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     int i, j, k0, k1;
     if (!tile_of<TY, TZ, TX>(nx, ny, nz, i, j, k0, k1)) return;
+    const uint64_t side = side_mask(a.side, i, j, k0, k1);
     const long long sxy = a.g.sxy;
     const int im = (i == 0) ? nx - 1 : i - 1, ip = (i + 1 == nx) ? 0 : i + 1;
     const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j + 1 == ny) ? 0 : j + 1;
@@ -530,10 +636,18 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
             if (qx.cj > T(0)) { jx = jx + qx.cj * ex0; stp(Jx, o00, jx); }
             if (qy.cj > T(0)) { jy = jy + qy.cj * ey0; stp(Jy, o00, jy); }
             if (qz.cj > T(0)) { jz = jz + qz.cj * ez; stp(Jz, o00, jz); }
+            T nex = qx.ca * ex0 + qx.cb * ((dyHz - dzHy) - jx);
+            T ney = qy.ca * ey0 + qy.cb * ((dzHx - dxHz) - jy);
+            T nez = qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz);
+            if (side != 0) {
+                nex = side_e(a.side, side, 0, i, j, k, nex);
+                ney = side_e(a.side, side, 1, i, j, k, ney);
+                nez = side_e(a.side, side, 2, i, j, k, nez);
+            }
             T *Exo = a.Eout[0] + b, *Eyo = a.Eout[1] + b, *Ezo = a.Eout[2] + b;
-            stp_hint<NT>(Exo, o00, qx.ca * ex0 + qx.cb * ((dyHz - dzHy) - jx));
-            stp_hint<NT>(Eyo, o00, qy.ca * ey0 + qy.cb * ((dzHx - dxHz) - jy));
-            stp_hint<NT>(Ezo, o00, qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz));
+            stp_hint<NT>(Exo, o00, nex);
+            stp_hint<NT>(Eyo, o00, ney);
+            stp_hint<NT>(Ezo, o00, nez);
         } else {
             T dyHz = (nhz - nhz_ym) * rdy, dzHy = (nhy - hy_km) * rdz;  // Ex
             T dzHx = (nhx - hx_km) * rdz, dxHz = (nhz - nhz_xm) * rdx;  // Ey
@@ -569,6 +683,11 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
                 nex = (wall_y || wall_z) ? T(0) : nex;
                 ney = (wall_z || wall_x) ? T(0) : ney;
                 nez = (wall_x || wall_y) ? T(0) : nez;
+            }
+            if (side != 0) {
+                nex = side_e(a.side, side, 0, i, jw, k, nex);
+                ney = side_e(a.side, side, 1, i, jw, k, ney);
+                nez = side_e(a.side, side, 2, i, jw, k, nez);
             }
             T *Exo = a.Eout[0] + b, *Eyo = a.Eout[1] + b, *Ezo = a.Eout[2] + b;
             stp_hint<NT>(Exo, o00, nex);
@@ -796,89 +915,30 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
 }
 
 // ---------------------------------------------------------------------------
-// Soft sources and probes
+// Probes on their own launch (the sample at the start of a run, probes beyond the sweeps' fold)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double waveform(int wave, double f, double t0, double tw, double t)
-{
-    if (wave == TFL_WAVE_SIN) return sin(kTwoPi * f * t);
-    const double g = exp(-(t - t0) * (t - t0) / (2.0 * tw * tw));
-    return wave == TFL_WAVE_GAUSS ? g : g * sin(kTwoPi * f * t);
-}
-
-// All soft sources of a step in one launch, a thread per cell of the boxes laid
-// end to end (src[q].offset is the prefix of the counts).  Where boxes of one
-// component overlap, the thread of the first box holding an edge adds every
-// source holding it in source order (the sums one launch per source would
-// form) and the threads of the later boxes leave it.
-template <typename T>
-__global__ void source_kernel(const SrcArgs<T> a)
-{
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.total) return;
-    int q = 0;
-    while (q + 1 < a.nsrc && idx >= a.src[q + 1].offset) ++q;
-    const SourceDesc &s = a.src[q];
-    const long long loc = idx - s.offset;
-    const int wx = s.i1 - s.i0, wy = s.j1 - s.j0;
-    const int i = s.i0 + (int)(loc % wx);
-    const long long r = loc / wx;
-    const int j = s.j0 + (int)(r % wy);
-    const int k = s.k0 + (int)(r / wy);
-    auto holds = [&](const SourceDesc &d) {
-        return d.comp == s.comp && i >= d.i0 && i < d.i1 && j >= d.j0 && j < d.j1 && k >= d.k0 && k < d.k1;
-    };
-    for (int p = 0; p < q; ++p)
-        if (holds(a.src[p])) return;
-    T *E = a.E[s.comp];
-    const long long c = ((long long)k * a.g.ny + j) * a.g.nx + i;
-    T v = E[c];
-    for (int p = q; p < a.nsrc; ++p) {
-        const SourceDesc &d = a.src[p];
-        if (!holds(d)) continue;
-        const double g = d.amp * waveform(d.wave, d.f, d.t0, d.tw, a.t);
-        v = (T)((double)v + g);
-    }
-    E[c] = v;
-}
-
-constexpr int kProbeThreads = 256;
-
 template <typename T>
 __global__ __launch_bounds__(kProbeThreads) void probe_kernel(const ProbeArgs<T> a)
 {
     const ProbeDesc &p = a.p[a.first + blockIdx.x];
-    const T *E = a.E[p.comp];
     const int wx = p.i1 - p.i0, wy = p.j1 - p.j0, wz = p.k1 - p.k0;
     const long long cnt = (long long)wx * wy * wz;
-    double acc = 0.0;
-    for (long long idx = threadIdx.x; idx < cnt; idx += kProbeThreads) {
-        const int i = p.i0 + (int)(idx % wx);
-        const long long r = idx / wx;
-        const int j = p.j0 + (int)(r % wy);
-        const int k = p.k0 + (int)(r / wy);
-        acc += (double)E[((long long)k * a.g.ny + j) * a.g.nx + i];
+    double s;
+    if (blockIdx.x < kFoldProbes && a.copy[blockIdx.x] != nullptr) {
+        const T *c = a.copy[blockIdx.x];
+        s = probe_sum(cnt, [c](long long idx) { return (double)c[idx]; });
+    } else {
+        const T *E = a.E[p.comp];
+        const long long ny = a.g.ny, nx = a.g.nx;
+        s = probe_sum(cnt, [&](long long idx) {
+            const int i = p.i0 + (int)(idx % wx);
+            const long long r = idx / wx;
+            const int j = p.j0 + (int)(r % wy);
+            const int k = p.k0 + (int)(r / wy);
+            return (double)E[((long long)k * ny + j) * nx + i];
+        });
     }
-    // wave64 reduction, then across the block's waves through LDS
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    __shared__ double part[kProbeThreads / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) part[wv] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < kProbeThreads / 64; ++w) s += part[w];
-        part[0] = s;
-    }
-    __syncthreads();
-    const double s = part[0];
-    if (threadIdx.x == 0 && p.series != nullptr && a.n < p.cap) p.series[a.n] = s;
-    if ((int)threadIdx.x < p.nfreq) {
-        const int f = threadIdx.x;
-        const double ph = kTwoPi * p.freq[f] * (double)a.n * a.dt;
-        p.dft[2 * f] += s * a.dt * cos(ph);
-        p.dft[2 * f + 1] -= s * a.dt * sin(ph);
-    }
+    probe_record(p, s, a.n, a.dt);
 }
 
 // ---------------------------------------------------------------------------
@@ -1420,21 +1480,6 @@ bool fused_step_pays(const StepArgs<T> &a)
 }
 
 template <typename T>
-hipError_t launch_sources(const SrcArgs<T> &a, hipStream_t s)
-{
-    SrcArgs<T> b = a;
-    long long total = 0;
-    for (int q = 0; q < b.nsrc; ++q) {
-        b.src[q].offset = total;
-        total += b.src[q].count > 0 ? b.src[q].count : 0;
-    }
-    b.total = total;
-    if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(source_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, b);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_probes(const ProbeArgs<T> &a, int nprobe, hipStream_t s)
 {
     if (nprobe <= 0) return hipSuccess;
@@ -1519,7 +1564,6 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
     template bool two_step_pays<T>(const StepArgs<T> &);                                                   \
     template hipError_t launch_class_table<T>(const StepArgs<T> &, const T *, const uint64_t *, int, T *,     \
                                               hipStream_t);                                                 \
-    template hipError_t launch_sources<T>(const SrcArgs<T> &, hipStream_t);                                 \
     template hipError_t launch_probes<T>(const ProbeArgs<T> &, int, hipStream_t);                           \
     template hipError_t launch_half_kick<T>(const StepArgs<T> &, T, T *const[3], T *const[3], hipStream_t); \
     template hipError_t launch_energy<T>(const StepArgs<T> &, double *, int, hipStream_t, double *);        \

@@ -74,15 +74,24 @@ size_t fused_layout(const tfl_sim *s, size_t psi_at[3], size_t *total = nullptr)
 // Device pointers of the bound edge classes (x, y, z) and class table; all null when none are bound.
 void class_pointers(const tfl_sim *s, const uint16_t *cls[3], const void **table);
 
-// scratch buffer layout: reduction partials, the objective DFT, probe descriptors
-constexpr size_t kScratchBytes = 1 << 17;
+// scratch buffer layout: reduction partials, the objective DFT, probe descriptors, and two halves
+// for the sweeps' probe copies (a sweep writes one half while it sums the other)
+constexpr size_t kScratchBytes = 1 << 20;
 constexpr int kRedBlocks = 1024;            // reductions use doubles [0, 5 * kRedBlocks)
 constexpr size_t kObjectiveSlot = 6144;     // doubles [6144, 6146): objective DFT
 constexpr size_t kNonfiniteOffset = 49408;  // bytes: two uint64 counters of the non-finite check
 constexpr size_t kProbeDescOffset = 65536;  // bytes: TFL_MAX_PROBES + 1 ProbeDesc
+constexpr size_t kProbeCopyOffset = 1 << 17;
+constexpr size_t kProbeCopyHalf = (kScratchBytes - kProbeCopyOffset) / 2;
 static_assert(kNonfiniteOffset >= (kObjectiveSlot + 2) * sizeof(double) && kNonfiniteOffset + 16 <= kProbeDescOffset,
               "non-finite counters overlap the objective or the probe descriptors");
-static_assert(kProbeDescOffset + (TFL_MAX_PROBES + 1) * sizeof(ProbeDesc) <= kScratchBytes, "scratch too small");
+static_assert(kProbeDescOffset + (TFL_MAX_PROBES + 1) * sizeof(ProbeDesc) <= kProbeCopyOffset, "scratch too small");
+static_assert(sizeof(AdjArgs<double>) <= 4096 && sizeof(StepArgs<double>) <= 4096, "kernel arguments above 4 KiB");
+// Value soft source d adds at time t (its waveform times its amplitude).
+double source_value(const SourceDesc &d, double t);
+// Boxes of the bound sources into sd (values zero), and their values at time t.
+void source_boxes(const tfl_sim *s, SideArgs &sd);
+void source_values(const tfl_sim *s, SideArgs &sd, double t);
 // Upload the probe descriptors to scratch when they changed (synchronises).
 int upload_probes(tfl_sim *s, hipStream_t st);
 // Non-finite check around an entry point's steps: begin clears the counters when the check is on;

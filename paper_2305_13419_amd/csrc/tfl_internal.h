@@ -42,6 +42,30 @@ struct PmlAxis {
     T *psiHo[2];            // where the fused sweep writes the new H-side variables (psiH elsewhere)
 };
 
+struct ProbeDesc;
+
+// Work that rides along with the E update of a sweep (the fused sweep and the E pass), so that a
+// step with sources and probes is still one launch:
+//  - soft sources: the sweep adds sg[p] (the value source p adds at this step) to the new E of every
+//    edge of box p, in source order, after the PEC walls are zeroed;
+//  - probe copies: the new E of each edge of probe p's box goes to pcopy[p] in box order (x fastest);
+//  - probe sums: blocks 0 .. nred-1 first sum the copies rcopy[b] that the previous sweep wrote
+//    and record sample rn of probe b (series and DFT), with the probe kernel's summation order.
+constexpr int kFoldProbes = 4;
+struct SideArgs {
+    int nsrc;
+    int nprobe;
+    int nred;
+    int sbox[TFL_MAX_SOURCES][7];  // component, i0, i1, j0, j1, k0, k1
+    double sg[TFL_MAX_SOURCES];
+    int pbox[kFoldProbes][7];
+    void *pcopy[kFoldProbes];
+    const void *rcopy[kFoldProbes];
+    const ProbeDesc *pdesc;        // descriptors of the probes (device memory)
+    long long rn;
+    double dt;
+};
+
 template <typename T>
 struct StepArgs {
     GridDims g;
@@ -59,13 +83,12 @@ struct StepArgs {
     T dt;
     T theta;
     PmlAxis<T> pml[3];
+    SideArgs side;
 };
 
 struct SourceDesc {
     int comp;
     int i0, i1, j0, j1, k0, k1;
-    long long count;   // cells in the box
-    long long offset;  // prefix of counts
     double amp;
     int wave;
     double f, t0, tw;
@@ -81,18 +104,9 @@ struct ProbeDesc {
     double *dft;
 };
 
-template <typename T>
-struct SrcArgs {
-    GridDims g;
-    T *E[3];
-    int nsrc;
-    long long total;
-    double t;
-    SourceDesc src[TFL_MAX_SOURCES];
-};
-
 // Probe descriptors live in device memory (the bound scratch buffer); a
-// launch samples probes [first, first + gridDim.x).
+// launch samples probes [first, first + gridDim.x), from the fields or, where
+// copy[b] is set, from the box values a sweep copied out (launch block b).
 template <typename T>
 struct ProbeArgs {
     GridDims g;
@@ -101,6 +115,7 @@ struct ProbeArgs {
     double dt;
     const ProbeDesc *p;
     int first;
+    const T *copy[kFoldProbes];
 };
 
 // The nine state arrays (Ex, Ey, Ez, Hx, Hy, Hz, Jx, Jy, Jz) of the non-finite check.
@@ -120,10 +135,8 @@ struct AdjArgs {
     T *lpsiH[3][2], *lpsiE[3][2];
     double *gL[3], *gS[3];
     const T *En[3];  // E^m: input E of the forward step m -> m+1 (A part)
-    const T *Ep[3];  // E^{m+1} after the sources: the sweep takes them out again (A part)
-    int nsrc;        // soft sources of the step: component and box (comp, i0, i1, j0, j1, k0, k1) and
-    int sbox[TFL_MAX_SOURCES][7];  // the value they added, subtracted from Ep in source order
-    double sg[TFL_MAX_SOURCES];
+    const T *Ep[3];  // E^{m+1} after the sources: the sweep takes them out again (A part): the
+                     // boxes and values of f.side, subtracted in source order
     int doC, doA;
     int obj;         // add og to lE[ocomp] on the objective box
     int ocomp, ob[6];
@@ -205,7 +218,6 @@ template <typename T> bool two_step_pays(const StepArgs<T> &a);
 template <typename T>
 hipError_t launch_class_table(const StepArgs<T> &a, const T *mat, const uint64_t *tuple, int ncls, T *tab,
                               hipStream_t s);
-template <typename T> hipError_t launch_sources(const SrcArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_probes(const ProbeArgs<T> &a, int nprobe, hipStream_t s);
 // Integer-time half kick: Hout = Hin + sgn dt/(2 mu0) curlE (stretched, with
 // the PML variables advanced virtually), Jout = Jin - sgn dt/2 ell_e E / mu0 on

@@ -59,9 +59,9 @@ def test_cpml_sources_probes(pml, dtype):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_overlapping_sources(dtype):
-    """Boxes that overlap on one component add in source order (all sources of a step run in one
-    launch, where the first box holding an edge adds every source there); a second component
-    overlaps them too, and a one-cell box sits inside two others."""
+    """Boxes that overlap on one component add in source order (the sweep adds every source whose
+    box holds an edge to the new E there, in source order); a second component overlaps them too,
+    and a one-cell box sits inside two others."""
     wl = workloads.random_medium((40, 18, 22), seed=11, pml=(None, (3, 3), None))
     wl["sources"] = [
         dict(comp=1, box=(5, 30, 2, 14, 4, 18), amplitude=1.5, waveform="sin", freq=2e14),

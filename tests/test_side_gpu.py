@@ -1,0 +1,113 @@
+"""Sources and probes riding along with the sweeps.
+
+The sweeps add the soft sources to the new E in source order and copy the new E on up to four probe
+boxes to scratch; the next sweep (or one probe launch after a call's last step) sums the copies in
+the order of the probe launch that runs when the probes do not fit that scheme (more than four, or
+boxes beyond the copy space).  Both ways must give the same bits, on every sweep path and however
+the steps are split into calls, and both must match the oracle.
+"""
+import numpy as np
+import pytest
+
+from paper_2305_13419_amd import workloads
+from tests.helpers import compare, fields_of, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def run(wl, steps, dtype, sweep="auto", chunks=None, fused=True):
+    from paper_2305_13419_amd import Simulation
+
+    sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"], fused=fused)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
+    sim.set_fields(*fields_of(wl, npdt))
+    sim.set_sweep(sweep)
+    for s in wl["sources"]:
+        sim.add_source(**s)
+    pids = [sim.add_probe(p["comp"], p["box"], steps + 1, p.get("freqs", ())) for p in wl["probes"]]
+    for c in chunks or [steps]:
+        sim.step(c)
+    Eg, Hg, Jg = sim.integer_time_fields()
+    torch.cuda.synchronize()
+    out = ([t.double().cpu().numpy() for t in Eg], [t.double().cpu().numpy() for t in Hg],
+           [t.double().cpu().numpy() for t in Jg], [sim.probe(p) for p in pids])
+    sim.close()
+    return out
+
+
+def workload(pml=((5, 4), None, (3, 6))):
+    wl = workloads.random_medium((70, 21, 40), seed=31, pml=pml)
+    wl["sources"] = [
+        dict(comp=1, box=(30, 31, 0, 21, 10, 30), amplitude=2.0, waveform="mod_gauss", freq=3e14, t0=2e-15, tw=8e-16),
+        dict(comp=1, box=(25, 35, 5, 9, 12, 14), amplitude=-1.0, waveform="sin", freq=1e14),
+        dict(comp=0, box=(12, 14, 7, 9, 3, 5), amplitude=0.5, waveform="gauss", t0=1e-15, tw=5e-16),
+    ]
+    wl["probes"] = [dict(comp=1, box=(40, 41, 0, 21, 0, 40), freqs=(3e14, 1e14)),
+                    dict(comp=0, box=(20, 21, 10, 11, 15, 16), freqs=(2e14,)),
+                    dict(comp=2, box=(0, 70, 0, 21, 20, 22)),
+                    dict(comp=1, box=(30, 31, 0, 21, 10, 30), freqs=(1e14,))]
+    return wl
+
+
+def same(a, b):
+    for x, y in zip(a[:3], b[:3]):
+        for p, q in zip(x, y):
+            assert np.array_equal(p, q)
+    for (sa, da), (sb, db) in zip(a[3], b[3]):
+        assert np.array_equal(sa, sb)
+        assert np.array_equal(da, db)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("sweep", ["fused", "two_pass"])
+def test_folded_probes_equal_probe_launches(dtype, sweep):
+    """Four probes ride along with the sweeps; a fifth makes every probe take its own launch.  The
+    four probes' series and DFTs and the fields are the same bits either way, with the steps in one
+    call and split over calls of 1, 6 and 10 steps (an odd call ends on the two passes)."""
+    wl = workload()
+    steps = 17
+    five = dict(wl, probes=wl["probes"] + [dict(comp=2, box=(3, 4, 3, 4, 3, 4))])
+    print(f"case: dtype={dtype} sweep={sweep} steps={steps}", flush=True)
+    a = run(wl, steps, dtype, sweep)
+    b = run(five, steps, dtype, sweep)
+    b = (b[0], b[1], b[2], b[3][:4])
+    same(a, b)
+    c = run(wl, steps, dtype, sweep, chunks=[1, 6, 10])
+    same(a, c)
+    o = run_oracle(wl, steps, np.float64 if dtype == torch.float64 else np.float32)
+    res = compare(a, o)
+    print("  rel-L2:", {k: f"{v:.2e}" for k, v in res.items()}, flush=True)
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    for k, v in res.items():
+        assert v <= tol, (k, v)
+
+
+def test_probe_box_beyond_copy_space():
+    """A probe box of 70 x 21 x 40 FP64 values is larger than a copy half of scratch: the probe takes
+    its own launch after every step, next to a small probe that then does as well."""
+    wl = workload()
+    wl["probes"] = [dict(comp=2, box=(0, 70, 0, 21, 0, 40), freqs=(2e14,)), wl["probes"][1]]
+    steps = 12
+    g = run(wl, steps, torch.float64, "fused")
+    o = run_oracle(wl, steps)
+    res = compare(g, o)
+    print("  rel-L2:", {k: f"{v:.2e}" for k, v in res.items()}, flush=True)
+    for k, v in res.items():
+        assert v <= 1e-12, (k, v)
+    one = run(dict(wl, probes=wl["probes"][1:]), steps, torch.float64, "fused")
+    assert np.array_equal(one[3][0][0], g[3][1][0])
+    assert np.array_equal(one[3][0][1], g[3][1][1])
+
+
+def test_no_fused_buffer_sources_probes():
+    """Without the fused buffer every step is the two passes: sources and probes ride on the E pass."""
+    wl = workload(pml=(None, (4, 4), None))
+    a = run(wl, 9, torch.float64, fused=False)
+    b = run(wl, 9, torch.float64, "two_pass")
+    same(a, b)
+    o = run_oracle(wl, 9)
+    for k, v in compare(a, o).items():
+        assert v <= 1e-12, (k, v)
