@@ -709,53 +709,149 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
 // ---------------------------------------------------------------------------
 // A block covers a footprint of 64 x TY columns of the x-y plane (one wavefront per row) and marches
 // along z, one plane per iteration, the second step one plane behind the first:
-//   A  H^{n+1/2}(k) at the lane's own faces and at its x-1 and y-1 faces, from E^n and H^{n-1/2} read
-//      from global memory (the fused sweep's first half);
+//   A  H^{n+1/2}(k) at the lane's own faces and at its x-1 and y-1 faces, from E^n and H^{n-1/2}
+//      (the fused sweep's first half);
 //   B  Js^{n+1/2}(k) and E^{n+1}(k), kept in registers, E^{n+1}(k) also written to LDS;
 //   C  H^{n+3/2}(k-1) at the lane's own faces from E^{n+1}(k-1) (own, and x+1 / y+1 from LDS) and
 //      E^{n+1}(k) (own), written to LDS;
 //   D  Js^{n+3/2}(k-1) and E^{n+2}(k-1) from H^{n+3/2}(k-1) (own, and x-1 / y-1 from LDS) and
 //      H^{n+3/2}(k-2) (own, from the previous iteration).
-// Stage C is exact on lanes 0..62 and rows 0..TY-2 (the x+1 / y+1 neighbours of the last lane and row
-// lie outside the footprint), stage D on lanes 1..62 and rows 1..TY-2: a footprint's outputs are its
-// 62 x (TY-2) interior cells, footprints overlap by two columns and two rows (those cells are computed
-// by both), and along z a block computes the first step on two planes before its range.  Per cell the
-// sweep reads E, H, Js (on superconducting edges) and the classes once and writes them once for two
-// steps.  Every expression is the fused sweep's, so the results equal two fused steps bit for bit.
+// Stage A reads E^n and H^{n-1/2} from LDS tiles of the footprint's 64 columns with the rows -1..TY
+// (as each component's stencil needs), filled by asynchronous global-to-LDS loads issued two planes
+// ahead, before the first barrier of a plane: E^n in a ring of four planes (stage A reads planes k and
+// k+1, plane k+2 is in flight, plane k+3 is issued into the slot of plane k-1), H^{n-1/2} in a ring of
+// three.  The wavefronts of a block meet at two barriers per plane that order LDS only (lds_barrier):
+// a wavefront waits for its own tile loads of the previous plane just before the first barrier, so
+// the loads stay in flight for a whole plane of compute, where __syncthreads would wait for them (and
+// for every other outstanding global access) at once.  (Issuing after the first barrier into the
+// slots of plane k, with rings of three and two, measured 4 % slower; so did loading Js^{n-1/2} one
+// plane ahead.)  The tiles hold no columns beyond the footprint,
+// so stages A and B are exact on lanes 1..62 (lanes 0 and 63 miss their x-1 or x+1 neighbour), stage
+// C on lanes 1..61 and rows 0..TY-2 (the x+1 / y+1 neighbours), stage D on lanes 2..61 and rows
+// 1..TY-2: a footprint's outputs are its 60 x (TY-2) interior cells, footprints overlap by four
+// columns and two rows (those cells are computed by both), and along z a block computes the first
+// step on two planes before its range.  Per cell the sweep reads E, H, Js (on superconducting edges)
+// and the classes once and writes them once for two steps.  Every expression is the fused sweep's,
+// so the results equal two fused steps bit for bit.
 static __device__ __forceinline__ int wrap_index(int v, int n)
 {
     const int r = v % n;
     return r < 0 ? r + n : r;
 }
 
+constexpr int kTwoStepOX = kTileX - 4;  // output columns of a footprint
+// s_waitcnt vmcnt(6) with expcnt and lgkmcnt left alone (gfx9 encoding: vmcnt bits 3:0 and 15:14,
+// expcnt 6:4, lgkmcnt 11:8)
+constexpr int kWaitVm6 = 0x0F76;
+constexpr int kWaitLgkm0 = 0xC07F;  // s_waitcnt lgkmcnt(0)
+
+// Barrier for LDS data only: this wavefront's LDS accesses complete before it and no LDS access moves
+// across it, but global memory operations stay in flight (__syncthreads also waits for every
+// outstanding global load and store of the wavefront).
+static __device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// LDS pointer of the global-to-LDS loads (the instruction writes lane t's dword at this address + 4 t).
+template <typename T>
+static __device__ __forceinline__ __attribute__((address_space(3))) void *lds_ptr(T *p)
+{
+    return (__attribute__((address_space(3))) void *)p;
+}
+
+
+// Footprint tiles of the two-step sweep in LDS.
+template <typename T, int TY>
+struct TwoStepShared {
+    static constexpr int RW = kTileX + 2, NR = TY + 2;  // a tile row (lane t at t + 1); rows -1..TY
+    T e[4][3][NR][RW];          // E^n, ring of four planes
+    T h[3][3][NR][RW];          // H^{n-1/2}, ring of three planes
+    T e1[2][3][TY][kTileX];     // E^{n+1} of the last two planes
+    T h2[3][TY][kTileX];        // H^{n+3/2} of the previous plane
+};
+
 template <typename T, int TY, int TZ, bool NT>
 __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<T> a)
 {
-    constexpr int OX = kTileX - 2, OY = TY - 2;
+    constexpr int OX = kTwoStepOX, OY = TY - 2;
+    using S = TwoStepShared<T, TY>;
+    constexpr int RW = S::RW, NR = S::NR;
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const int ntx = (nx + OX - 1) / OX, nty = (ny + OY - 1) / OY, ntz = (nz + TZ - 1) / TZ;
     const int t = logical_block(blockIdx.x, ntx * nty * ntz);
     const int tx = t % ntx, tr = t / ntx, ty = tr % nty, tz = tr / nty;
     const int lane = threadIdx.x, row = threadIdx.y;
-    const int xo = tx * OX + lane - 1, yo = ty * OY + row - 1;  // the cell's output coordinates
+    const int wave = __builtin_amdgcn_readfirstlane(row);
+    const int xo = tx * OX + lane - 2, yo = ty * OY + row - 1;  // the cell's output coordinates
     const int i = wrap_index(xo, nx), j = wrap_index(yo, ny);
-    const bool out = lane >= 1 && lane <= OX && xo < nx && row >= 1 && row <= OY && yo < ny;
+    const bool out = lane >= 2 && lane <= OX + 1 && xo < nx && row >= 1 && row <= OY && yo < ny;
     const int k0 = tz * TZ, k1 = min(k0 + TZ, nz);
     const long long sxy = a.g.sxy;
-    const int im = (i == 0) ? nx - 1 : i - 1, ip = (i + 1 == nx) ? 0 : i + 1;
-    const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j + 1 == ny) ? 0 : j + 1;
+    const int jp = (j + 1 == ny) ? 0 : j + 1, ip = (i + 1 == nx) ? 0 : i + 1;
     constexpr uint32_t w = sizeof(T);
-    const uint32_t o00 = uint32_t(j * nx + i) * w, o10 = uint32_t(j * nx + im) * w;
-    const uint32_t o01 = uint32_t(jm * nx + i) * w;
+    const uint32_t o00 = uint32_t(j * nx + i) * w;
     const uint32_t oxp = uint32_t(j * nx + ip) * w, oyp = uint32_t(jp * nx + i) * w;
-    const uint32_t oxm_yp = uint32_t(jp * nx + im) * w, oxp_ym = uint32_t(jm * nx + ip) * w;
     const uint32_t oc = uint32_t(j * nx + i) * 2u;
     const T rdx = a.rd[0], rdy = a.rd[1], rdz = a.rd[2], hdt = a.hdt;
 
-    __shared__ T lds_e[2][3][TY][kTileX];  // E^{n+1} of the last two planes
-    __shared__ T lds_h[3][TY][kTileX];     // H^{n+3/2} of the previous plane
+    __shared__ S sh;
     const int lxp = min(lane + 1, kTileX - 1), lxm = max(lane - 1, 0);
     const int ryp = min(row + 1, TY - 1), rym = max(row - 1, 0);
+
+    // ---- the tile loads of this wavefront: jobs (component, row slot) dealt to the wavefronts in
+    // turn, E: Ex rows -1..TY, Ey rows -1..TY-1, Ez rows -1..TY; H (dealt on from where the E jobs
+    // leave off): Hx rows -1..TY-1, Hy rows 0..TY-1, Hz rows -1..TY-1.  Row slot s is grid row
+    // wrap(ty OY - 2 + s); lane t loads column wrap(tx OX - 2 + t) (FP64: two loads of 32 values).
+    constexpr int NJE = 3 * NR - 1, NJH = 3 * NR - 4;
+    constexpr int JE = (NJE + TY - 1) / TY, JH = (NJH + TY - 1) / TY;
+    const int x0 = tx * OX - 2;
+    const uint32_t cmain0 = sizeof(T) == 8 ? uint32_t(wrap_index(x0 + lane / 2, nx)) * w + 4u * (lane & 1)
+                                           : uint32_t(wrap_index(x0 + lane, nx)) * w;
+    const uint32_t cmain1 = uint32_t(wrap_index(x0 + 32 + lane / 2, nx)) * w + 4u * (lane & 1);
+    auto row_of = [&](int sr) { return (long long)wrap_index(ty * OY - 2 + sr, ny) * nx; };
+    const T *ebase[JE], *hbase[JH];
+    int elds[JE], hlds[JH];
+    int ne = 0, nh = 0;
+#pragma unroll
+    for (int m = 0; m < JE; ++m) {
+        const int q = wave + m * TY;
+        const int c = q < NR ? 0 : (q < 2 * NR - 1 ? 1 : 2);
+        const int sr = q - (c == 0 ? 0 : (c == 1 ? NR : 2 * NR - 1));
+        ebase[m] = a.E[c] + row_of(sr);
+        elds[m] = (c * NR + sr) * RW + 1;
+        ne += q < NJE;
+    }
+    const int hw = (wave + TY - NJE % TY) % TY;
+#pragma unroll
+    for (int m = 0; m < JH; ++m) {
+        const int q = hw + m * TY;
+        const int c = q < NR - 1 ? 0 : (q < 2 * NR - 3 ? 1 : 2);
+        const int sr = c == 0 ? q : (c == 1 ? q - (NR - 1) + 1 : q - (2 * NR - 3));
+        hbase[m] = a.H[c] + row_of(sr);
+        hlds[m] = (c * NR + sr) * RW + 1;
+        nh += q < NJH;
+    }
+    auto tile_row = [&](const T *src, T *dst) {
+        __builtin_amdgcn_global_load_lds((const char *)src + cmain0, lds_ptr(dst), 4, 0, 0);
+        if constexpr (sizeof(T) == 8)
+            __builtin_amdgcn_global_load_lds((const char *)src + cmain1, lds_ptr(dst + 32), 4, 0, 0);
+    };
+    auto load_e = [&](int kk, int slot) {
+        const long long b = (long long)kk * sxy;
+#pragma unroll
+        for (int m = 0; m < JE; ++m)
+            if (m < ne) tile_row(ebase[m] + b, &sh.e[slot][0][0][0] + elds[m]);
+    };
+    auto load_h = [&](int kk, int slot) {
+        const long long b = (long long)kk * sxy;
+#pragma unroll
+        for (int m = 0; m < JH; ++m)
+            if (m < nh) tile_row(hbase[m] + b, &sh.h[slot][0][0][0] + hlds[m]);
+    };
 
     struct Classes {
         uint32_t x, y, z;
@@ -771,9 +867,11 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
         cz = class_coef(a.ctab, m.z);
     };
 
-    // prologue: H^{n+1/2} (Hx, Hy) at plane k0-2 and E^n of plane k0-1 carried into the loop
-    const int kb = wrap_index(k0 - 1, nz), km0 = wrap_index(k0 - 2, nz);
-    T hx_km, hy_km, ex0, exm, ey0, eym;
+    // prologue: H^{n+1/2} (Hx, Hy) at plane k0-2 carried into the loop, and the first tiles
+    const int p0 = k0 - 1;  // stage A plane of the first iteration
+    const int nit = (k1 - k0) + 2;
+    const int km0 = wrap_index(k0 - 2, nz), kb = wrap_index(p0, nz);
+    T hx_km, hy_km;
     {
         const long long bm = (long long)km0 * sxy, b = (long long)kb * sxy;
         const T *Ex = a.E[0] + bm, *Ey = a.E[1] + bm, *Ez = a.E[2] + bm;
@@ -784,12 +882,21 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
         const T dzEx = (exk1 - exk) * rdz, dxEz = (ez_x - ez) * rdx;
         hx_km = ldp(a.H[0] + bm, o00) - hdt * (dyEz - dzEy);
         hy_km = ldp(a.H[1] + bm, o00) - hdt * (dzEx - dxEz);
-        ex0 = exk1;
-        ey0 = eyk1;
-        exm = ldp(a.E[0] + b, o10);
-        eym = ldp(a.E[1] + b, o01);
     }
+    for (int q = 0; q < 3 && q <= nit; ++q) load_e(wrap_index(p0 + q, nz), q);
+    for (int q = 0; q < 2 && q < nit; ++q) load_h(wrap_index(p0 + q, nz), q);
     coefs(load_cls(kb));
+    // Js^{n-1/2} of the stage A plane, loaded one plane ahead on every edge (the step writes it only
+    // on superconducting edges: the others are masked to 0 where it is used)
+    T jnx, jny, jnz;
+    {
+        const long long b = (long long)kb * sxy;
+        jnx = ldp(a.J[0] + b, o00);
+        jny = ldp(a.J[1] + b, o00);
+        jnz = ldp(a.J[2] + b, o00);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
 
     // carried from the previous plane k-1: H^{n+1/2}, E^{n+1}, Js^{n+3/2} (the London update of the
     // second step, formed as soon as E^{n+1} exists), the E-update coefficients; and H^{n+3/2}(k-2)
@@ -797,29 +904,35 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
     T pjx = T(0), pjy = T(0), pjz = T(0);
     EdgeCoef<T> px_ = {T(0), T(0), T(0)}, py_ = px_, pz_ = px_;
     T qhx_km = T(0), qhy_km = T(0);
+    const int L = lane + 1, R = row + 1;  // the lane's column and row slots in the tiles
 
-    const int nit = (k1 - k0) + 2;
     for (int it = 0; it < nit; ++it) {
-        const int kc = wrap_index(k0 - 1 + it, nz);
+        const int kc = wrap_index(p0 + it, nz);
         const int kn = (kc + 1 == nz) ? 0 : kc + 1;
-        const long long b = opaque_offset((long long)kc * sxy), bp = opaque_offset((long long)kn * sxy);
         // ---- stages A and B at plane kc (the fused sweep's periodic arithmetic)
         const EdgeCoef<T> qx = cx, qy = cy, qz = cz;
-        T jx = T(0), jy = T(0), jz = T(0);
-        if (qx.cj > T(0)) jx = ldp(a.J[0] + b, o00);
-        if (qy.cj > T(0)) jy = ldp(a.J[1] + b, o00);
-        if (qz.cj > T(0)) jz = ldp(a.J[2] + b, o00);
-        const T *Ex = a.E[0] + b, *Ey = a.E[1] + b, *Ez = a.E[2] + b;
-        const T *Hx = a.H[0] + b, *Hy = a.H[1] + b, *Hz = a.H[2] + b;
-        const T ex_yp = ldp(Ex, oyp), exm_yp = ldp(Ex, oxm_yp), ex_ym = ldp(Ex, o01);
-        const T ey_xp = ldp(Ey, oxp), ey_xm = ldp(Ey, o10), eym_xp = ldp(Ey, oxp_ym);
-        const T ez = ldp(Ez, o00), ez_xp = ldp(Ez, oxp), ez_yp = ldp(Ez, oyp), ez_xm = ldp(Ez, o10),
-                ez_ym = ldp(Ez, o01);
-        const T ex1 = ldp(a.E[0] + bp, o00), exm1 = ldp(a.E[0] + bp, o10);
-        const T ey1 = ldp(a.E[1] + bp, o00), eym1 = ldp(a.E[1] + bp, o01);
-        const T hx = ldp(Hx, o00), hy = ldp(Hy, o00), hz = ldp(Hz, o00);
-        const T hz_xm = ldp(Hz, o10), hy_xm = ldp(Hy, o10), hz_ym = ldp(Hz, o01), hx_ym = ldp(Hx, o01);
+        T jx = qx.cj > T(0) ? jnx : T(0), jy = qy.cj > T(0) ? jny : T(0), jz = qz.cj > T(0) ? jnz : T(0);
+        // the next plane's Js and classes: exactly six loads, issued after every load the wait below
+        // is for
+        {
+            const long long bn = opaque_offset((long long)kn * sxy);
+            jnx = ldp(a.J[0] + bn, o00);
+            jny = ldp(a.J[1] + bn, o00);
+            jnz = ldp(a.J[2] + bn, o00);
+        }
         const Classes mn = load_cls(kn);
+        const auto &E0 = sh.e[it & 3], &E1 = sh.e[(it + 1) & 3];
+        const auto &H0 = sh.h[it % 3];
+        const T ex0 = E0[0][R][L], exm = E0[0][R][L - 1], ex_yp = E0[0][R + 1][L], exm_yp = E0[0][R + 1][L - 1];
+        const T ex_ym = E0[0][R - 1][L];
+        const T ey0 = E0[1][R][L], ey_xp = E0[1][R][L + 1], ey_xm = E0[1][R][L - 1], eym = E0[1][R - 1][L];
+        const T eym_xp = E0[1][R - 1][L + 1];
+        const T ez = E0[2][R][L], ez_xp = E0[2][R][L + 1], ez_yp = E0[2][R + 1][L], ez_xm = E0[2][R][L - 1];
+        const T ez_ym = E0[2][R - 1][L];
+        const T ex1 = E1[0][R][L], exm1 = E1[0][R][L - 1], ey1 = E1[1][R][L], eym1 = E1[1][R - 1][L];
+        const T hx = H0[0][R][L], hx_ym = H0[0][R - 1][L];
+        const T hy = H0[1][R][L], hy_xm = H0[1][R][L - 1];
+        const T hz = H0[2][R][L], hz_xm = H0[2][R][L - 1], hz_ym = H0[2][R - 1][L];
 
         const T nhx = hx - hdt * ((ez_yp - ez) * rdy - (ey1 - ey0) * rdz);
         const T nhy = hy - hdt * ((ex1 - ex0) * rdz - (ez_xp - ez) * rdx);
@@ -841,30 +954,38 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
             ez_n = qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz);
         }
         const int buf = it & 1;
-        lds_e[buf][0][row][lane] = ex_n;
-        lds_e[buf][1][row][lane] = ey_n;
-        lds_e[buf][2][row][lane] = ez_n;
-        __syncthreads();
+        sh.e1[buf][0][row][lane] = ex_n;
+        sh.e1[buf][1][row][lane] = ey_n;
+        sh.e1[buf][2][row][lane] = ez_n;
+        // this wavefront's tile loads of the previous plane have landed (the barrier makes every
+        // wavefront's visible): vector memory operations complete in issue order, and only the six
+        // loads of the next plane's Js and classes came after them.  Then the next tile loads: E^n
+        // plane kc+3, H^{n-1/2} plane kc+2, into the slots of plane kc-1, whose stage A every
+        // wavefront finished before the last barrier
+        __builtin_amdgcn_s_waitcnt(kWaitVm6);
+        if (it + 3 <= nit) load_e(wrap_index(p0 + it + 3, nz), (it + 3) & 3);
+        if (it + 2 < nit) load_h(wrap_index(p0 + it + 2, nz), (it + 2) % 3);
+        lds_barrier();
 
         // ---- stage C: H^{n+3/2} at plane kc - 1 (the fused sweep's H arithmetic on E^{n+1})
         T h2x = T(0), h2y = T(0), h2z = T(0);
         if (it >= 1) {
             const int pb = buf ^ 1;
-            const T ez1_yp = lds_e[pb][2][ryp][lane], ex1_yp = lds_e[pb][0][ryp][lane];
-            const T ey1_xp = lds_e[pb][1][row][lxp], ez1_xp = lds_e[pb][2][row][lxp];
+            const T ez1_yp = sh.e1[pb][2][ryp][lane], ex1_yp = sh.e1[pb][0][ryp][lane];
+            const T ey1_xp = sh.e1[pb][1][row][lxp], ez1_xp = sh.e1[pb][2][row][lxp];
             h2x = phx - hdt * ((ez1_yp - pez) * rdy - (ey_n - pey) * rdz);
             h2y = phy - hdt * ((ex_n - pex) * rdz - (ez1_xp - pez) * rdx);
             h2z = phz - hdt * ((ey1_xp - pey) * rdx - (ex1_yp - pex) * rdy);
-            lds_h[0][row][lane] = h2x;
-            lds_h[1][row][lane] = h2y;
-            lds_h[2][row][lane] = h2z;
+            sh.h2[0][row][lane] = h2x;
+            sh.h2[1][row][lane] = h2y;
+            sh.h2[2][row][lane] = h2z;
         }
-        __syncthreads();
+        lds_barrier();
 
         // ---- stage D: Js^{n+3/2} and E^{n+2} at plane kc - 1, stored for the footprint's interior
         if (it >= 2) {
-            const T h2z_xm = lds_h[2][row][lxm], h2y_xm = lds_h[1][row][lxm];
-            const T h2z_ym = lds_h[2][rym][lane], h2x_ym = lds_h[0][rym][lane];
+            const T h2z_xm = sh.h2[2][row][lxm], h2y_xm = sh.h2[1][row][lxm];
+            const T h2z_ym = sh.h2[2][rym][lane], h2x_ym = sh.h2[0][rym][lane];
             const T dyHz = (h2z - h2z_ym) * rdy, dzHy = (h2y - qhy_km) * rdz;
             const T dzHx = (h2x - qhx_km) * rdz, dxHz = (h2z - h2z_xm) * rdx;
             const T dxHy = (h2y - h2y_xm) * rdx, dyHx = (h2x - h2x_ym) * rdy;
@@ -906,10 +1027,6 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
         pz_ = qz;
         hx_km = nhx;
         hy_km = nhy;
-        ex0 = ex1;
-        exm = exm1;
-        ey0 = ey1;
-        eym = eym1;
         coefs(mn);
     }
 }
@@ -1428,7 +1545,7 @@ struct TwoStepTiles<float> {
 template <typename T, int TY, bool NT>
 static void launch_two_step_nt(const StepArgs<T> &a, hipStream_t s)
 {
-    constexpr int OX = kTileX - 2, OY = TY - 2;
+    constexpr int OX = kTwoStepOX, OY = TY - 2;
     const long long cols = (long long)((a.g.nx + OX - 1) / OX) * ((a.g.ny + OY - 1) / OY);
     // z runs of 32 planes (at 256^3: 16 and 64 were 3-20 % slower), shorter where the grid would then
     // give fewer than two blocks per CU (256 CUs)
