@@ -51,13 +51,22 @@ def test_two_step_equals_fused(shape, dtype):
         sb.close()
 
 
-def test_two_step_is_automatic_on_large_periodic_fp32_grids():
-    """The default policy takes the two-step sweep on a large periodic FP32 grid with classes (FP64 keeps
-    the fused sweep, which is as fast), and not where sources or probes act every step."""
+def test_two_step_is_automatic_on_large_periodic_grids():
+    """The default policy takes the two-step sweep on a periodic grid with classes past the infinity
+    cache (here 3.3 M cells), in both precisions, the fused sweep on a smaller one, and not where
+    sources or probes act every step."""
     from paper_2305_13419_amd import Simulation
-    wl = workloads.roofline_grid((128, 128, 128))
+    small = workloads.roofline_grid((128, 128, 128))
+    for dtype in (torch.float32, torch.float64):
+        sim = Simulation(small["shape"], small["spacing"], small["dt"], small["theta"], dtype)
+        sim.set_materials(*small["maps"])
+        sim.set_fields(*small["fields"][:2])
+        sim.step(10)
+        assert sim.sweep_counts() == (0, 10, 0)
+        sim.close()
+    wl = workloads.roofline_grid((160, 160, 128))
     E, H, _ = wl["fields"]
-    for dtype, expect in ((torch.float32, (0, 2, 8)), (torch.float64, (0, 10, 0))):
+    for dtype, expect in ((torch.float32, (0, 2, 8)), (torch.float64, (0, 2, 8))):
         sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype)
         sim.set_materials(*wl["maps"])
         sim.set_fields(E, H)
