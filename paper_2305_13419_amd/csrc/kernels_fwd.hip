@@ -421,7 +421,8 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
     // x slabs cut through the wavefronts of a row: their coefficients (the tables cover the whole
     // axis) are loaded once, and each plane's x-slab variables are loaded with the plane's other
     // loads at slots clamped into the slab, so that only arithmetic and stores depend on the lane
-    [[maybe_unused]] const bool xv = PML && px.on && px.P > 0;
+    // (only in the wavefronts whose columns, or their x-1 neighbours, lie in a slab)
+    [[maybe_unused]] const bool xv = PML && px.on && px.P > 0 && __any(sx >= 0 || sxm >= 0);
     [[maybe_unused]] T xbh = T(0), xch = T(0), xkh = T(0), xbn = T(0), xcn = T(0), xkn = T(0);
     [[maybe_unused]] T xbhm = T(0), xchm = T(0), xkhm = T(0);
     [[maybe_unused]] uint32_t osxc = 0, osxmc = 0;
@@ -557,10 +558,25 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
                 qe1 = ldo(px.psiE[1] + r, osxc);
             }
         }
+        // z slabs (a plane is in one or not): the plane's auxiliary variables of the lane's column,
+        // loaded with the plane's other loads (the H-side ones also at x-1 and y-1)
+        [[maybe_unused]] int sz = -1;
+        [[maybe_unused]] T zh0 = T(0), zh1 = T(0), zh1xm = T(0), zh0ym = T(0), ze0 = T(0), ze1 = T(0);
+        if constexpr (PML) {
+            sz = pz.on ? slab_slot(k, pz.lo, pz.hi, nz) : -1;
+            if (sz >= 0) {
+                const long long r = ((long long)sz * ny + jw) * nx, rym = ((long long)sz * ny + jmw) * nx;
+                zh0 = ldo(pz.psiH[0] + r, oi);
+                zh1 = ldo(pz.psiH[1] + r, oi);
+                zh1xm = ldo(pz.psiH[1] + r, oim);
+                zh0ym = ldo(pz.psiH[0] + rym, oi);
+                ze0 = ldo(pz.psiE[0] + r, oi);
+                ze1 = ldo(pz.psiE[1] + r, oi);
+            }
+        }
 
         // H^{n+1/2} with the H pass's arithmetic: own faces, Hz and Hy at x-1, Hz and Hx at y-1
         T nhx, nhy, nhz, nhz_xm, nhy_xm, nhz_ym, nhx_ym;
-        [[maybe_unused]] int sz = -1;
         if constexpr (!PML) {
             nhx = hx - hdt * ((ez_yp - ez) * rdy - (ey1 - ey0) * rdz);
             nhy = hy - hdt * ((ex1 - ex0) * rdz - (ez_xp - ez) * rdx);
@@ -579,7 +595,6 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
             T dyEz_ym = (ez - ez_ym) * rdy, dzEy_ym = (eym1 - eym) * rdz;       // Hx at y-1
             // stretched differences: the lane's own faces update their variables (old set in,
             // new set out); the faces at x-1 and y-1 belong to other lanes and only read them
-            sz = pz.on ? slab_slot(k, pz.lo, pz.hi, nz) : -1;
             if (sx >= 0) {
                 const long long r = ((long long)k * ny + jw) * px.P;
                 T p0, p1, pv;
@@ -608,12 +623,15 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
                 dyEz_ym = stretch_virtual_o(dyEz_ym, py.psiH[1] + r, oi, bh, ch, kh);
             }
             if (sz >= 0) {
-                const long long r = ((long long)sz * ny + jw) * nx, rym = ((long long)sz * ny + jmw) * nx;
+                const long long r = ((long long)sz * ny + jw) * nx;
                 const T bh = pz.bh[k], ch = pz.ch[k], kh = pz.kh[k];
-                dzEy = stretch_to_o(dzEy, pz.psiH[0] + r, pz.psiHo[0] + r, oi, bh, ch, kh);
-                dzEx = stretch_to_o(dzEx, pz.psiH[1] + r, pz.psiHo[1] + r, oi, bh, ch, kh);
-                dzEx_xm = stretch_virtual_o(dzEx_xm, pz.psiH[1] + r, oim, bh, ch, kh);
-                dzEy_ym = stretch_virtual_o(dzEy_ym, pz.psiH[0] + rym, oi, bh, ch, kh);
+                T p0, p1, pv;
+                dzEy = stretch_v(dzEy, zh0, bh, ch, kh, p0);
+                dzEx = stretch_v(dzEx, zh1, bh, ch, kh, p1);
+                sto(pz.psiHo[0] + r, oi, p0);
+                sto(pz.psiHo[1] + r, oi, p1);
+                dzEx_xm = stretch_v(dzEx_xm, zh1xm, bh, ch, kh, pv);
+                dzEy_ym = stretch_v(dzEy_ym, zh0ym, bh, ch, kh, pv);
             }
             nhx = hx - hdt * (dyEz - dzEy);
             nhy = hy - hdt * (dzEx - dxEz);
@@ -668,8 +686,11 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
                 }
                 if (sz >= 0) {
                     const long long r = ((long long)sz * ny + jw) * nx;
-                    dzHy = stretch_o(dzHy, pz.psiE[0] + r, oi, pz.bn[k], pz.cn[k], pz.kn[k]);  // Ex
-                    dzHx = stretch_o(dzHx, pz.psiE[1] + r, oi, pz.bn[k], pz.cn[k], pz.kn[k]);  // Ey
+                    T p0, p1;
+                    dzHy = stretch_v(dzHy, ze0, pz.bn[k], pz.cn[k], pz.kn[k], p0);  // Ex
+                    dzHx = stretch_v(dzHx, ze1, pz.bn[k], pz.cn[k], pz.kn[k], p1);  // Ey
+                    sto(pz.psiE[0] + r, oi, p0);
+                    sto(pz.psiE[1] + r, oi, p1);
                 }
             }
             if (qx.cj > T(0)) { jx = jx + qx.cj * ex0; stp(Jx, o00, jx); }
