@@ -18,16 +18,33 @@ static __device__ __forceinline__ int logical_block(int b, int nblocks)
 // wavefronts per row) and TZ planes along z.  Tiles are numbered x fastest,
 // then y, then z, and blocks are renumbered so that each XCD takes a contiguous
 // range: the blocks of one XCD sweep neighbouring columns of the same planes at
-// the same time.  Returns false for lanes outside the grid.
+// the same time.  With zmix (the fused and adjoint sweeps on grids with CPML
+// slabs along z) z is numbered before y: the slab planes cost more, and with z
+// last the XCDs would take one z range each, the two at the ends all the slab
+// planes (measured: 1-3 % faster for those sweeps on 16-cell z slabs, 2-5 %
+// slower for the two passes, which keep z last).  Returns false for lanes
+// outside the grid.
+static __device__ __forceinline__ void tile_yz(int tr, int nty, int ntz, bool zmix, int &ty, int &tz)
+{
+    if (zmix) {
+        tz = tr % ntz;
+        ty = tr / ntz;
+    } else {
+        ty = tr % nty;
+        tz = tr / nty;
+    }
+}
+
 template <int TY, int TZ, int TX = kTileX>
-static __device__ __forceinline__ bool tile_of(int nx, int ny, int nz, int &i, int &j, int &k0, int &k1)
+static __device__ __forceinline__ bool tile_of(int nx, int ny, int nz, int &i, int &j, int &k0, int &k1,
+                                               bool zmix = false)
 {
     const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, ntz = (nz + TZ - 1) / TZ;
     const int t = logical_block(blockIdx.x, ntx * nty * ntz);
     const int tx = t % ntx;
     const int tr = t / ntx;
-    const int ty = tr % nty;
-    const int tz = tr / nty;
+    int ty, tz;
+    tile_yz(tr, nty, ntz, zmix, ty, tz);
     i = tx * TX + threadIdx.x;
     j = ty * TY + threadIdx.y;
     k0 = tz * TZ;
@@ -39,15 +56,16 @@ static __device__ __forceinline__ bool tile_of(int nx, int ny, int nz, int &i, i
 // wavefront covers 64 / W rows of W cells and a block 64 TY / W rows, for grids whose nx would
 // leave much of a 64-lane row idle.
 template <int TY, int TZ, int W>
-static __device__ __forceinline__ bool tile_of_w(int nx, int ny, int nz, int &i, int &j, int &k0, int &k1)
+static __device__ __forceinline__ bool tile_of_w(int nx, int ny, int nz, int &i, int &j, int &k0, int &k1,
+                                                 bool zmix = false)
 {
     constexpr int rows = kTileX * TY / W;
     const int ntx = (nx + W - 1) / W, nty = (ny + rows - 1) / rows, ntz = (nz + TZ - 1) / TZ;
     const int t = logical_block(blockIdx.x, ntx * nty * ntz);
     const int tx = t % ntx;
     const int tr = t / ntx;
-    const int ty = tr % nty;
-    const int tz = tr / nty;
+    int ty, tz;
+    tile_yz(tr, nty, ntz, zmix, ty, tz);
     const int lane = threadIdx.x + kTileX * threadIdx.y;
     i = tx * W + lane % W;
     j = ty * rows + lane / W;

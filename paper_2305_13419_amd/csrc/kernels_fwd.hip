@@ -379,7 +379,7 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
     side_reduce<T>(a.side);
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     int i, j, k0, k1;
-    if (!tile_of<TY, TZ, TX>(nx, ny, nz, i, j, k0, k1)) return;
+    if (!tile_of<TY, TZ, TX>(nx, ny, nz, i, j, k0, k1, PML && a.pml[2].on)) return;
     const uint64_t side = side_mask(a.side, i, j, k0, k1);
     const long long sxy = a.g.sxy;
     const int im = (i == 0) ? nx - 1 : i - 1, ip = (i + 1 == nx) ? 0 : i + 1;
