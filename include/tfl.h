@@ -174,12 +174,10 @@ int tfl_bind_fused_buffer(tfl_sim *sim, void *buffer);
 
 /* Which sweeps a step may take (the results are the same bits on every path).
  *  TFL_SWEEP_AUTO      (default) the two-step sweep where it applies and pays
- *                      (FP32 grids of at least 2^21 cells, nx >= 64,
- *                      ny >= 32, nz >= 16; in FP64 it is no faster than the
- *                      fused sweep), else the fused
- *                      sweep where a buffer is bound and it pays (FP64 CPML
- *                      grids below two rounds of its wavefronts take the
- *                      two passes), else the two passes;
+ *                      (grids of at least 3 * 2^20 cells, past the GPU's
+ *                      infinity cache, nx >= 64, ny >= 32, nz >= 16), else
+ *                      the fused sweep where a buffer is bound, else the
+ *                      two passes;
  *  TFL_SWEEP_TWO_PASS  always the H and E passes;
  *  TFL_SWEEP_FUSED     the fused sweep wherever a buffer is bound, no
  *                      two-step sweep;

@@ -235,8 +235,7 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
     // fields, B the buffer), so the state is back in A after every call; an odd last step runs the
     // two passes in place on A.
     StepArgs<T> ab = a, ba = a;
-    const bool fused = s->fused != nullptr && s->sweep != TFL_SWEEP_TWO_PASS &&
-                       (s->sweep != TFL_SWEEP_AUTO || fused_step_pays<T>(a));
+    const bool fused = s->fused != nullptr && s->sweep != TFL_SWEEP_TWO_PASS;
     // Two steps per sweep (periodic grids with edge classes) where nothing happens between the steps:
     // no sources, probes or non-finite checks.  Launches go A -> B -> A (E, H and Js), four steps per
     // round trip, so the state is back in A; the remaining steps take the paths below.

@@ -153,10 +153,10 @@ struct Reverse {
         StepArgs<T> f = make_args<T>(s);
         source_boxes(s, f.side);
         const double dt = s->cfg.dt;
-        // With the fused buffer bound (and the fused sweep paying on this grid) the recomputation
-        // runs the fused sweep: E goes from snapshot t to snapshot t + 1 as in the two passes, H and
-        // the H-side CPML variables alternate between the bound set (even t) and the buffer (odd t).
-        const bool fused = s->fused != nullptr && fused_step_pays<T>(f);
+        // With the fused buffer bound the recomputation runs the fused sweep: E goes from snapshot t
+        // to snapshot t + 1 as in the two passes, H and the H-side CPML variables alternate between
+        // the bound set (even t) and the buffer (odd t).
+        const bool fused = s->fused != nullptr;
         StepArgs<T> fo = f, fe = f;  // odd t: buffer -> bound set; even t: bound set -> buffer
         if (fused) {
             size_t psi_at[3];

@@ -1603,21 +1603,6 @@ bool two_step_pays(const StepArgs<T> &a)
     return (long long)a.g.sxy * a.g.nz >= (3LL << 20) && a.g.nx >= 64 && a.g.ny >= 32 && a.g.nz >= 16;
 }
 
-// With its CPML code the FP64 fused sweep holds ~154 VGPRs (3 waves per SIMD, 3072 on the GPU);
-// below two rounds of such waves the two passes are faster.  Measured: 256 x 128 x 64 with CPML
-// on x and z (4096 waves) 94 us fused vs 85 us; 256^3 with the same slabs (8192 waves) 0.70 vs
-// 0.82 ms; the paper's CPW (64512 waves) 8.76 vs 9.12 ms.  FP32 (5 waves per SIMD) gained on
-// every CPML grid measured but one (512 x 256 x 128, within 4 %).
-template <typename T>
-bool fused_step_pays(const StepArgs<T> &a)
-{
-    if (sizeof(T) != 8 || !(a.pml[0].on || a.pml[1].on || a.pml[2].on)) return true;
-    using C = FwdTiles<T>;
-    const int tz = pick_tile_z(a.g, C::fy, C::f_waves, C::fz_max, kTileX);
-    const long long waves = (long long)tile_blocks(a.g, C::fy, tz, kTileX) * C::fy;
-    return waves >= 2LL * 3 * 4 * 256;
-}
-
 template <typename T>
 hipError_t launch_probes(const ProbeArgs<T> &a, int nprobe, hipStream_t s)
 {
@@ -1698,7 +1683,6 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
     template hipError_t launch_h_pass<T>(const StepArgs<T> &, hipStream_t);                                 \
     template hipError_t launch_e_pass<T>(const StepArgs<T> &, hipStream_t);                                 \
     template hipError_t launch_fused_step<T>(const StepArgs<T> &, hipStream_t);                             \
-    template bool fused_step_pays<T>(const StepArgs<T> &);                                                 \
     template hipError_t launch_two_step<T>(const StepArgs<T> &, hipStream_t);                               \
     template bool two_step_pays<T>(const StepArgs<T> &);                                                   \
     template hipError_t launch_class_table<T>(const StepArgs<T> &, const T *, const uint64_t *, int, T *,     \

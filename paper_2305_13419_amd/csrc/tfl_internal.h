@@ -204,9 +204,6 @@ template <typename T> hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t
 // H^{n+1/2} (Hout), and on CPML axes the H-side variables from psiH to psiHo; Js and the E-side
 // variables in place.  E, Eout, H, Hout and psiH, psiHo must not overlap.
 template <typename T> hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s);
-// Whether the fused sweep beats the two passes on this grid (false only for FP64 CPML grids too
-// small to fill the GPU at the fused sweep's occupancy).
-template <typename T> bool fused_step_pays(const StepArgs<T> &a);
 // Two time steps in one sweep (periodic grids with edge classes, no sources or probes in between):
 // reads E^n, H^{n-1/2}, Js^{n-1/2} from E, H, J and writes E^{n+2}, H^{n+3/2}, Js^{n+3/2} to Eout,
 // Hout, Jout, which must not overlap the inputs.  Results equal two fused steps bit for bit.
