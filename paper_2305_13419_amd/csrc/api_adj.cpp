@@ -23,7 +23,7 @@ AdjLayout adj_layout(const tfl_sim *s)
     L.field = round256((size_t)s->N * s->esz);
     L.grad = round256((size_t)s->N * 8);
     for (int a = 0; a < 3; ++a) L.psi += round256(4 * s->psi_count[a] * s->esz);
-    L.total = 12 * L.field + L.psi + 6 * L.grad;
+    L.total = (9 + 3 * kGradWindow) * L.field + L.psi + 6 * L.grad;
     return L;
 }
 
@@ -130,6 +130,26 @@ struct Reverse {
 
     T *snapE(int64_t t, int q) const { return (T *)((char *)snap + ((size_t)t * 3 + q) * fb); }
 
+    // mu of the edge sweeps, one set of three fields per step of a window; the window's sigma
+    // gradient is added when it is full and at the end of every range (before the snapshots are
+    // overwritten)
+    char *mu_base = nullptr;
+    size_t field = 0;
+    GradSigmaArgs<T> G{};
+
+    void set_mu_slot(int w)
+    {
+        for (int q = 0; q < 3; ++q) A.mu[q] = (T *)(mu_base + ((size_t)w * 3 + q) * field);
+    }
+
+    int flush_grad_sigma()
+    {
+        hipError_t e = launch_adj_grad_sigma<T>(G, st);
+        G.nwin = 0;
+        if (e != hipSuccess) return hip_fail(s, e, "sigma gradient");
+        return TFL_OK;
+    }
+
     double objective_coef(int64_t n) const
     {
         const double ph = kTwoPi * o->f0 * (double)n * s->cfg.dt;
@@ -197,18 +217,27 @@ struct Reverse {
         const int64_t end = s0 + len;
         for (int64_t n = end; n >= s0 + 1; --n) {
             if (n != end && (e = launch_adj_faces<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint faces");
+            if (G.nwin == kGradWindow && (rc = flush_grad_sigma()) != TFL_OK) return rc;
             source_values(s, A.f.side, (double)n * dt);
             A.doC = (n != nend);
             A.doA = 1;
             A.obj = 1;
             A.og = objective_coef(n);
+            for (int q = 0; q < 3; ++q) A.En[q] = snapE(n - 1 - s0, q);
+            // this step's mu goes to slot nwin of the window, read by the next face sweep and then by
+            // the window's sigma gradient together with E^{m+1}, E^m and the step's source values
+            const int w = G.nwin++;
+            set_mu_slot(w);
             for (int q = 0; q < 3; ++q) {
-                A.En[q] = snapE(n - 1 - s0, q);
-                A.Ep[q] = snapE(n - s0, q);
+                G.mu[w][q] = A.mu[q];
+                G.Ep[w][q] = snapE(n - s0, q);
+                G.En[w][q] = (A.f.theta == T(1)) ? nullptr : snapE(n - 1 - s0, q);
             }
+            for (int p = 0; p < G.nsrc; ++p) G.sg[w][p] = A.f.side.sg[p];
             if ((e = launch_adj_edges<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint edges");
         }
         if ((e = launch_adj_faces<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint faces");
+        if ((rc = flush_grad_sigma()) != TFL_OK) return rc;
         if (s0 == n0) {
             A.doC = 1;
             A.doA = 0;
@@ -244,7 +273,10 @@ int make_reverse(tfl_sim *s, const tfl_objective *o, const double F[2], void *sn
     for (int q = 0; q < 3; ++q) { A.lE[q] = (T *)p; p += L.field; }
     for (int q = 0; q < 3; ++q) { A.lH[q] = (T *)p; p += L.field; }
     for (int q = 0; q < 3; ++q) { A.lJ[q] = (T *)p; p += L.field; }
-    for (int q = 0; q < 3; ++q) { A.mu[q] = (T *)p; p += L.field; }
+    R.mu_base = p;
+    R.field = L.field;
+    R.set_mu_slot(0);
+    p += (size_t)kGradWindow * 3 * L.field;
     for (int a = 0; a < 3; ++a) {
         const size_t m = s->psi_count[a] * s->esz;
         if (s->cfg.bc[a] == TFL_CPML) {
@@ -258,6 +290,14 @@ int make_reverse(tfl_sim *s, const tfl_objective *o, const double F[2], void *sn
     A.ocomp = o->comp;
     for (int q = 0; q < 6; ++q) A.ob[q] = (int)o->box[q];
     source_boxes(s, A.f.side);
+    GradSigmaArgs<T> &G = R.G;
+    G = GradSigmaArgs<T>{};
+    G.g = A.f.g;
+    for (int q = 0; q < 3; ++q) G.gS[q] = A.gS[q];
+    G.theta = (double)A.f.theta;
+    G.nsrc = A.f.side.nsrc;
+    for (int q = 0; q < G.nsrc; ++q)
+        for (int c = 0; c < 7; ++c) G.sbox[q][c] = A.f.side.sbox[q][c];
     return TFL_OK;
 }
 

@@ -208,15 +208,16 @@ struct EdgeSlabs {
 
 // Edge-local part of F2^T for component Q of the edge at plane offset b, lane
 // byte offsets ow (arrays of T) and od (FP64 gradient arrays), from values
-// loaded by the caller: lJ and gL (superconducting edges only), gS, E^n, E'_pre.
+// loaded by the caller: lJ, gL and E^n (superconducting edges only).  The sigma
+// gradient term of the edge, -mu (theta E'_pre + (1 - theta) E^n), is added by
+// adj_grad_sigma_kernel from the stored mu of a window of steps.
 // `wall`: the edge lies on the PEC wall of a CPML axis other than Q (E' = 0
 // there, so its adjoint does not propagate).
 template <int Q, typename T>
 __device__ __forceinline__ void adj_edge_local(const AdjArgs<T> &A, long long b, uint32_t ow, uint32_t od, bool wall,
-                                               const EdgeSlabs &sl, T lEq, const EdgeCoef<T> &k, T En, T Ep, T lJ,
-                                               double gL, double gS)
+                                               const EdgeSlabs &sl, T lEq, const EdgeCoef<T> &k, T En, T lJ, double gL)
 {
-    const T theta = A.f.theta, hdt = A.f.hdt;
+    const T hdt = A.f.hdt;
     const T lEp = wall ? T(0) : lEq;
     const T mu = k.cb * lEp;
     T ljt = T(0);
@@ -225,7 +226,6 @@ __device__ __forceinline__ void adj_edge_local(const AdjArgs<T> &A, long long b,
         sto(A.lJ[Q] + b, ow, ljt);
         sto(A.gL[Q] + b, od, gL + (double)hdt * (double)ljt * (double)En);
     }
-    sto(A.gS[Q] + b, od, gS - (double)lEp * (double)k.cb * ((double)theta * (double)Ep + (1.0 - (double)theta) * (double)En));
     sto(A.mu[Q] + b, ow, mu);
     sto(A.lE[Q] + b, ow, k.ca * lEp + k.cj * ljt);
     // E-side PML adjoint variables of the two axes component Q is differentiated along:
@@ -280,7 +280,6 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
     const uint32_t oi = uint32_t(i) * sizeof(T), oim = uint32_t(im) * sizeof(T);
     const T rdx = A.f.rd[0], rdy = A.f.rd[1], rdz = A.f.rd[2];
     const T dt = A.f.dt, theta = A.f.theta, hdt = A.f.hdt;
-    const bool theta_one = (theta == T(1));
     const PmlAxis<T> &px = A.f.pml[0], &py = A.f.pml[1], &pz = A.f.pml[2];
     // a wavefront is one row (blockDim.x = 64): j is uniform over it
     const int jw = __builtin_amdgcn_readfirstlane(j), jmw = __builtin_amdgcn_readfirstlane(jm);
@@ -372,34 +371,15 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
             hz_ym = ldo(Hz, o01); hz_xm = ldo(Hz, o10); hx_ym = ldo(Hx, o01); hy_xm = ldo(Hy, o10);
         }
         const EdgeCoef<T> kq[3] = {cq[0], cq[1], cq[2]};
-        T En[3] = {}, Ep[3] = {}, lJ[3] = {};
-        double gL[3] = {}, gS[3] = {};
+        T En[3] = {}, lJ[3] = {};
+        double gL[3] = {};
         decltype(load_maps(0)) mn{};
         if (A.doA) {
             for (int q = 0; q < 3; ++q) {
-                if (kq[q].cj > T(0)) {
+                if (kq[q].cj > T(0)) {  // the ell gradient's terms: superconducting edges only
                     lJ[q] = ldo(A.lJ[q] + b, o00);
                     gL[q] = ldo(A.gL[q] + b, od);
-                }
-            }
-            for (int q = 0; q < 3; ++q) {
-                // E^n enters the sigma gradient only through (1 - theta) E^n: with theta = 1 it is read
-                // on superconducting edges only (the ell gradient)
-                if (!theta_one || kq[q].cj > T(0)) En[q] = ldo(A.En[q] + b, o00);
-                Ep[q] = ldo(A.Ep[q] + b, o00);
-                gS[q] = ldo(A.gS[q] + b, od);
-            }
-            // E'_pre: the soft sources of this step taken out of the stored E^{m+1}
-            const SideArgs &sd = A.f.side;
-            for (int sidx = 0; sidx < sd.nsrc; ++sidx) {
-                if (k >= sd.sbox[sidx][5] && k < sd.sbox[sidx][6] && jw >= sd.sbox[sidx][3] && jw < sd.sbox[sidx][4] &&
-                    i >= sd.sbox[sidx][1] && i < sd.sbox[sidx][2]) {
-                    const int c = sd.sbox[sidx][0];
-                    const double g = sd.sg[sidx];
-                    // selects, not a store to Ep[c]: a variable index would move Ep to scratch memory
-                    Ep[0] = (c == 0) ? (T)((double)Ep[0] - g) : Ep[0];
-                    Ep[1] = (c == 1) ? (T)((double)Ep[1] - g) : Ep[1];
-                    Ep[2] = (c == 2) ? (T)((double)Ep[2] - g) : Ep[2];
+                    En[q] = ldo(A.En[q] + b, o00);
                 }
             }
             // maps of the next plane (the last iteration re-reads its own plane and discards them)
@@ -458,10 +438,45 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
         const bool wz = pz.on && k == 0;
         const EdgeSlabs sl{sxi, syj, szk, osxi, oi, rx, ((long long)k * py.P + syj) * nx,
                            ((long long)szk * ny + jw) * nx, jw, k};
-        adj_edge_local<0>(A, b, o00, od, wy || wz, sl, le[0], kq[0], En[0], Ep[0], lJ[0], gL[0], gS[0]);
-        adj_edge_local<1>(A, b, o00, od, wx || wz, sl, le[1], kq[1], En[1], Ep[1], lJ[1], gL[1], gS[1]);
-        adj_edge_local<2>(A, b, o00, od, wx || wy, sl, le[2], kq[2], En[2], Ep[2], lJ[2], gL[2], gS[2]);
+        adj_edge_local<0>(A, b, o00, od, wy || wz, sl, le[0], kq[0], En[0], lJ[0], gL[0]);
+        adj_edge_local<1>(A, b, o00, od, wx || wz, sl, le[1], kq[1], En[1], lJ[1], gL[1]);
+        adj_edge_local<2>(A, b, o00, od, wx || wy, sl, le[2], kq[2], En[2], lJ[2], gL[2]);
         coefs(mn);
+    }
+}
+
+// The sigma gradient of a window of reverse steps, for each edge and in the order the edge sweeps
+// ran those steps: gS -= mu (theta E'_pre + (1 - theta) E^n) in FP64, mu the step's b lE' stored by
+// its edge sweep and E'_pre its E^{m+1} with the step's soft sources taken out (as the forward added
+// them).  One sweep over a window replaces a read-modify-write of the FP64 accumulators per step.
+template <typename T>
+__global__ void adj_grad_sigma_kernel(const GradSigmaArgs<T> G)
+{
+    const long long N = G.g.sxy * G.g.nz;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+         c += (long long)gridDim.x * blockDim.x) {
+        int i = 0, j = 0, k = 0;
+        if (G.nsrc > 0) {
+            i = (int)(c % G.g.nx);
+            const long long r = c / G.g.nx;
+            j = (int)(r % G.g.ny);
+            k = (int)(r / G.g.ny);
+        }
+        for (int q = 0; q < 3; ++q) {
+            double g = G.gS[q][c];
+            for (int w = 0; w < G.nwin; ++w) {
+                const T mu = G.mu[w][q][c];
+                T Ep = G.Ep[w][q][c];
+                for (int p = 0; p < G.nsrc; ++p) {
+                    const int *b = G.sbox[p];
+                    if (b[0] == q && k >= b[5] && k < b[6] && j >= b[3] && j < b[4] && i >= b[1] && i < b[2])
+                        Ep = (T)((double)Ep - G.sg[w][p]);
+                }
+                const T En = G.En[w][q] ? G.En[w][q][c] : T(0);
+                g = g - (double)mu * ((double)G.theta * (double)Ep + (1.0 - (double)G.theta) * (double)En);
+            }
+            G.gS[q][c] = g;
+        }
     }
 }
 
@@ -589,6 +604,14 @@ hipError_t launch_adj_initial_kick(const AdjArgs<T> &a, hipStream_t s)
 }
 
 template <typename T>
+hipError_t launch_adj_grad_sigma(const GradSigmaArgs<T> &g, hipStream_t s)
+{
+    if (g.nwin <= 0) return hipSuccess;
+    hipLaunchKernelGGL(adj_grad_sigma_kernel<T>, dim3(grid_blocks(g.g.sxy * g.g.nz)), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_adj_edge_to_cell(const AdjArgs<T> &a, double *grad_ell, double *grad_sig, hipStream_t s)
 {
     hipLaunchKernelGGL(adj_edge_to_cell_kernel<T>, dim3(grid_blocks(a.f.g.sxy * a.f.g.nz)), dim3(256), 0, s, a,
@@ -600,6 +623,7 @@ hipError_t launch_adj_edge_to_cell(const AdjArgs<T> &a, double *grad_ell, double
     template hipError_t launch_adj_faces<T>(const AdjArgs<T> &, hipStream_t);         \
     template hipError_t launch_adj_edges<T>(const AdjArgs<T> &, hipStream_t);         \
     template hipError_t launch_adj_initial_kick<T>(const AdjArgs<T> &, hipStream_t);  \
+    template hipError_t launch_adj_grad_sigma<T>(const GradSigmaArgs<T> &, hipStream_t); \
     template hipError_t launch_adj_edge_to_cell<T>(const AdjArgs<T> &, double *, double *, hipStream_t);
 
 TFL_ADJ_INSTANTIATE(double)

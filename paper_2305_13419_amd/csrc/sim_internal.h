@@ -86,7 +86,9 @@ constexpr size_t kProbeCopyHalf = (kScratchBytes - kProbeCopyOffset) / 2;
 static_assert(kNonfiniteOffset >= (kObjectiveSlot + 2) * sizeof(double) && kNonfiniteOffset + 16 <= kProbeDescOffset,
               "non-finite counters overlap the objective or the probe descriptors");
 static_assert(kProbeDescOffset + (TFL_MAX_PROBES + 1) * sizeof(ProbeDesc) <= kProbeCopyOffset, "scratch too small");
-static_assert(sizeof(AdjArgs<double>) <= 4096 && sizeof(StepArgs<double>) <= 4096, "kernel arguments above 4 KiB");
+static_assert(sizeof(AdjArgs<double>) <= 4096 && sizeof(StepArgs<double>) <= 4096 &&
+                  sizeof(GradSigmaArgs<double>) <= 4096,
+              "kernel arguments above 4 KiB");
 // Value soft source d adds at time t (its waveform times its amplitude).
 double source_value(const SourceDesc &d, double t);
 // Boxes of the bound sources into sd (values zero), and their values at time t.

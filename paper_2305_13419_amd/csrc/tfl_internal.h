@@ -134,13 +134,30 @@ struct AdjArgs {
     T *lE[3], *lH[3], *lJ[3], *mu[3];
     T *lpsiH[3][2], *lpsiE[3][2];
     double *gL[3], *gS[3];
-    const T *En[3];  // E^m: input E of the forward step m -> m+1 (A part)
-    const T *Ep[3];  // E^{m+1} after the sources: the sweep takes them out again (A part): the
-                     // boxes and values of f.side, subtracted in source order
+    const T *En[3];  // E^m: input E of the forward step m -> m+1 (A part; ell gradient)
     int doC, doA;
     int obj;         // add og to lE[ocomp] on the objective box
     int ocomp, ob[6];
     double og;
+};
+
+// The sigma gradient of a window of up to kGradWindow reverse steps (adj_grad_sigma_kernel): per
+// step w of the window, in the order the edge sweeps ran them, the mu its edge sweep stored, its
+// E^{m+1} (E'_pre after the sources sg[w] are taken out of the boxes sbox) and E^m (null when theta
+// is 1, where it does not enter).
+constexpr int kGradWindow = 8;
+template <typename T>
+struct GradSigmaArgs {
+    GridDims g;
+    double *gS[3];
+    const T *mu[kGradWindow][3];
+    const T *Ep[kGradWindow][3];
+    const T *En[kGradWindow][3];
+    int nwin;
+    double theta;
+    int nsrc;
+    int sbox[TFL_MAX_SOURCES][7];
+    double sg[kGradWindow][TFL_MAX_SOURCES];
 };
 
 // z length of the column tiles of a z-marching sweep, chosen at launch: the
@@ -254,6 +271,7 @@ hipError_t launch_lp_residual(const double *series, long long start, long long c
 // Adjoint launchers (kernels_adj.hip).
 template <typename T> hipError_t launch_adj_faces(const AdjArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_adj_edges(const AdjArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_adj_grad_sigma(const GradSigmaArgs<T> &g, hipStream_t s);
 // gL += -dt/(2 mu0) lJ E^0 on superconducting edges (dependence of Js^{-1/2} on ell).
 template <typename T> hipError_t launch_adj_initial_kick(const AdjArgs<T> &a, hipStream_t s);
 // Per-edge FP64 accumulators -> per-cell gradients (derivative of the edge rule).
