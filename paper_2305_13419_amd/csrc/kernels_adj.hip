@@ -10,8 +10,9 @@
 //               and the H-side PML adjoint variables;
 //   edge sweep: lE += -dt/mu0 curl^T lH (+ H-side PML transposes), the
 //               objective source, then the edge-local part of F2^T for the
-//               preceding step (mu = b lE, lJ, gradient accumulation,
-//               lE <- a lE + j lJ).
+//               preceding step (mu = b lE, lJ, the ell gradient,
+//               lE <- a lE + j lJ); mu is kept per step for a window of
+//               steps, whose sigma gradient one more sweep then adds.
 // Gradients with respect to the per-edge j = dt ell/mu0 and sigma follow from
 // dJs'/d ell = dt E/mu0 and dE'/d sigma = -b (theta E'_pre + (1-theta) E).
 // The multiplication of a PML adjoint variable by its decay b is applied when
