@@ -338,8 +338,10 @@ typedef struct {
 
 /* Byte sizes of the caller-owned buffers for a run of nsteps with segments
  * of seg steps: checkpoints (ceil(nsteps/seg) saved states), E snapshots
- * (seg + 1 of them) and the adjoint workspace (adjoint fields, PML adjoint
- * variables, FP64 per-edge gradient accumulators). */
+ * (two sets of seg + 1: one segment is recomputed into one set while the
+ * adjoint sweeps of the next read the other) and the adjoint workspace
+ * (adjoint fields, eight steps of mu, PML adjoint variables, FP64 per-edge
+ * gradient accumulators). */
 int tfl_adjoint_sizes(const tfl_sim *sim, int64_t nsteps, int64_t seg, size_t *ckpt_bytes, size_t *snap_bytes,
                       size_t *adj_bytes);
 
@@ -355,7 +357,10 @@ int tfl_forward_checkpointed(tfl_sim *sim, const tfl_objective *obj, int64_t nst
  * dJ/d sigma_n per cell to grad_ell and grad_sigma (device FP64, N each).
  * snap and adj are device buffers of snap_bytes and adj_bytes.  Probes are
  * not sampled during the recomputation, which runs the fused sweep when a
- * fused buffer is bound (as tfl_step; same results).  On return the state
+ * fused buffer is bound (as tfl_step; same results), on a second stream the
+ * call creates and destroys (each segment's recomputation overlaps the adjoint
+ * sweeps of the segment after it); all work is ordered before the end of the
+ * call's work on `stream`.  On return the state
  * arrays (and the fused buffer) hold intermediate values of the
  * recomputation: load a saved state (and set the step index) before stepping
  * again.  TFL_E_STATE if no matching forward run exists: none was made, it had

@@ -129,6 +129,7 @@ struct Reverse {
     hipStream_t st;
 
     T *snapE(int64_t t, int q) const { return (T *)((char *)snap + ((size_t)t * 3 + q) * fb); }
+    static T *snapIn(void *buf, size_t fb, int64_t t, int q) { return (T *)((char *)buf + ((size_t)t * 3 + q) * fb); }
 
     // mu of the edge sweeps, one set of three fields per step of a window; the window's sigma
     // gradient is added when it is full and at the end of every range (before the snapshots are
@@ -163,11 +164,19 @@ struct Reverse {
     // range is the first kernel of the range before it.
     int range(int64_t s0, int64_t len, const void *state_s0)
     {
+        const int rc = recompute(s0, len, state_s0, snap, st);
+        return rc != TFL_OK ? rc : reverse(s0, len);
+    }
+
+    // The recomputation of the forward steps [s0, s0 + len) from the saved state at s0 on stream rs,
+    // writing E^{s0+t} into snapshot t of buf.
+    int recompute(int64_t s0, int64_t len, const void *state_s0, void *buf, hipStream_t rs)
+    {
         hipError_t e;
-        int rc = copy_state(s, nullptr, state_s0, false, st);
+        int rc = copy_state(s, nullptr, state_s0, false, rs);
         if (rc != TFL_OK) return rc;
         for (int q = 0; q < 3; ++q) {
-            e = hipMemcpyAsync(snapE(0, q), s->E[q], (size_t)s->N * s->esz, hipMemcpyDeviceToDevice, st);
+            e = hipMemcpyAsync(snapIn(buf, fb, 0, q), s->E[q], (size_t)s->N * s->esz, hipMemcpyDeviceToDevice, rs);
             if (e != hipSuccess) return hip_fail(s, e, "snapshot");
         }
         StepArgs<T> f = make_args<T>(s);
@@ -202,18 +211,27 @@ struct Reverse {
         for (int64_t t = 0; t < len; ++t) {
             StepArgs<T> &g = fused ? ((t & 1) ? fo : fe) : f;
             for (int q = 0; q < 3; ++q) {
-                g.E[q] = snapE(t, q);
-                g.Eout[q] = snapE(t + 1, q);
+                g.E[q] = snapIn(buf, fb, t, q);
+                g.Eout[q] = snapIn(buf, fb, t + 1, q);
             }
             source_values(s, g.side, (double)(s0 + t + 1) * dt);
             if (fused) {
-                if ((e = launch_fused_step<T>(g, st)) != hipSuccess) return hip_fail(s, e, "recompute fused step");
+                if ((e = launch_fused_step<T>(g, rs)) != hipSuccess) return hip_fail(s, e, "recompute fused step");
             } else {
-                if ((e = launch_h_pass<T>(g, st)) != hipSuccess) return hip_fail(s, e, "recompute h_pass");
-                if ((e = launch_e_pass<T>(g, st)) != hipSuccess) return hip_fail(s, e, "recompute e_pass");
+                if ((e = launch_h_pass<T>(g, rs)) != hipSuccess) return hip_fail(s, e, "recompute h_pass");
+                if ((e = launch_e_pass<T>(g, rs)) != hipSuccess) return hip_fail(s, e, "recompute e_pass");
             }
         }
         s->step = s0 + len;
+        return TFL_OK;
+    }
+
+    // The adjoint sweeps over the recomputed range [s0, s0 + len) (snapshots in snap) on stream st.
+    int reverse(int64_t s0, int64_t len)
+    {
+        hipError_t e;
+        int rc = TFL_OK;
+        const double dt = s->cfg.dt;
         const int64_t end = s0 + len;
         for (int64_t n = end; n >= s0 + 1; --n) {
             if (n != end && (e = launch_adj_faces<T>(A, st)) != hipSuccess) return hip_fail(s, e, "adjoint faces");
@@ -310,12 +328,52 @@ int adjoint(tfl_sim *s, const tfl_objective *o, int64_t nsteps, int64_t seg, con
     if (rc != TFL_OK) return rc;
     const size_t sb = state_bytes(s);
     const int64_t nseg = (nsteps + seg - 1) / seg;
-    for (int64_t g = nseg - 1; g >= 0; --g) {
-        const int64_t s0 = R.n0 + g * seg;
-        const int64_t len = std::min(seg, R.nend - s0);
-        if ((rc = R.range(s0, len, (const char *)ckpt + (size_t)g * sb)) != TFL_OK) return rc;
+    // Two snapshot sets: segment g's recomputation (into set g mod 2, on a second stream) runs while
+    // the adjoint sweeps of segment g + 1 (on `st`) read the other set.  The recomputation of g waits
+    // for the sweeps of g + 2 (same set); the sweeps of g wait for the recomputation of g.
+    const size_t set_bytes = (size_t)(std::min(seg, nsteps) + 1) * 3 * R.fb;
+    auto set = [&](int64_t g) { return (void *)((char *)snap + (size_t)(g & 1) * set_bytes); };
+    auto state = [&](int64_t g) { return (const void *)((const char *)ckpt + (size_t)g * sb); };
+    auto first = [&](int64_t g) { return R.n0 + g * seg; };
+    auto length = [&](int64_t g) { return std::min(seg, R.nend - first(g)); };
+    hipStream_t rs = nullptr;
+    hipEvent_t ev[5] = {};  // recomputation of set 0 / 1 done, sweeps over set 0 / 1 done, `st` ready
+    hipError_t e = hipStreamCreateWithFlags(&rs, hipStreamNonBlocking);
+    for (int q = 0; q < 5 && e == hipSuccess; ++q) e = hipEventCreateWithFlags(&ev[q], hipEventDisableTiming);
+    // everything issued on `st` so far (the cleared workspace, the caller's state) before the second stream
+    if (e == hipSuccess) e = hipEventRecord(ev[4], st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(rs, ev[4], 0);
+    if (e != hipSuccess) rc = hip_fail(s, e, "recomputation stream");
+    if (rc == TFL_OK) rc = R.recompute(first(nseg - 1), length(nseg - 1), state(nseg - 1), set(nseg - 1), rs);
+    if (rc == TFL_OK && (e = hipEventRecord(ev[(nseg - 1) & 1], rs)) != hipSuccess) rc = hip_fail(s, e, "event");
+    for (int64_t g = nseg - 1; g >= 0 && rc == TFL_OK; --g) {
+        if (g >= 1) {  // the next recomputation, once the sweeps that last read its set are done
+            if (g + 1 <= nseg - 1 && (e = hipStreamWaitEvent(rs, ev[2 + ((g + 1) & 1)], 0)) != hipSuccess) {
+                rc = hip_fail(s, e, "event");
+                break;
+            }
+            if ((rc = R.recompute(first(g - 1), length(g - 1), state(g - 1), set(g - 1), rs)) != TFL_OK) break;
+            if ((e = hipEventRecord(ev[(g - 1) & 1], rs)) != hipSuccess) {
+                rc = hip_fail(s, e, "event");
+                break;
+            }
+        }
+        if ((e = hipStreamWaitEvent(st, ev[g & 1], 0)) != hipSuccess) {
+            rc = hip_fail(s, e, "event");
+            break;
+        }
+        R.snap = set(g);
+        if ((rc = R.reverse(first(g), length(g))) != TFL_OK) break;
+        if ((e = hipEventRecord(ev[2 + (g & 1)], st)) != hipSuccess) rc = hip_fail(s, e, "event");
     }
-    hipError_t e = launch_adj_edge_to_cell<T>(R.A, grad_ell, grad_sig, st);
+    // `st` has waited for every recomputation (the last one before the last sweeps); on an error, the
+    // second stream's work is waited for before its stream and events go
+    if (rc != TFL_OK && rs) (void)hipStreamSynchronize(rs);
+    if (rs) (void)hipStreamDestroy(rs);
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (rc != TFL_OK) return rc;
+    e = launch_adj_edge_to_cell<T>(R.A, grad_ell, grad_sig, st);
     if (e != hipSuccess) return hip_fail(s, e, "gradient to cells");
     return TFL_OK;
 }
@@ -367,7 +425,8 @@ int tfl_adjoint_sizes(const tfl_sim *s, int64_t nsteps, int64_t seg, size_t *ckp
     const int64_t nseg = (nsteps + seg - 1) / seg;
     const int64_t sl = std::min(seg, nsteps);
     if (ckpt_bytes) *ckpt_bytes = (size_t)nseg * state_bytes(s);
-    if (snap_bytes) *snap_bytes = (size_t)(sl + 1) * 3 * round256((size_t)s->N * s->esz);
+    // two snapshot sets: one segment's recomputation overlaps the previous segment's adjoint sweeps
+    if (snap_bytes) *snap_bytes = 2 * (size_t)(sl + 1) * 3 * round256((size_t)s->N * s->esz);
     if (adj_bytes) *adj_bytes = adj_layout(s).total;
     return TFL_OK;
 }
