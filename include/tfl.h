@@ -162,8 +162,9 @@ int tfl_bind_workspace(tfl_sim *sim, void *workspace, void *scratch, void *strea
  * Steps run in pairs (bound fields -> buffer -> bound fields), an odd last
  * step with the two passes, so the state is in the bound fields and the
  * workspace after every call.  On periodic grids with edge classes bound,
- * stretches of at least four steps with no sources, probes or non-finite
- * checks run two time steps per sweep (temporal blocking): each sweep reads
+ * stretches of at least four steps with no probes or non-finite checks (soft
+ * sources are added inside the sweep, to both steps' E) run two time steps per
+ * sweep (temporal blocking): each sweep reads
  * E^n, H^{n-1/2}, Js^{n-1/2} from one set and writes E^{n+2}, H^{n+3/2},
  * Js^{n+3/2} to the other, so per step each cell's fields cross HBM half as
  * often; the results again equal those of the two passes bit for bit.  The buffer is caller-owned device memory,
@@ -182,7 +183,7 @@ int tfl_bind_fused_buffer(tfl_sim *sim, void *buffer);
  *  TFL_SWEEP_FUSED     the fused sweep wherever a buffer is bound, no
  *                      two-step sweep;
  *  TFL_SWEEP_TWO_STEP  the two-step sweep wherever it applies (periodic grid,
- *                      edge classes bound, buffer bound, no sources, probes or
+ *                      edge classes bound, buffer bound, no probes or
  *                      checks, stretches of four steps), whatever the size;
  *                      the fused sweep elsewhere.
  * tfl_sweep_counts: steps the last tfl_step call ran on the two passes, the

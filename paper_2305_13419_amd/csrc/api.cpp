@@ -236,10 +236,10 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
     // two passes in place on A.
     StepArgs<T> ab = a, ba = a;
     const bool fused = s->fused != nullptr && s->sweep != TFL_SWEEP_TWO_PASS;
-    // Two steps per sweep (periodic grids with edge classes) where nothing happens between the steps:
-    // no sources, probes or non-finite checks.  Launches go A -> B -> A (E, H and Js), four steps per
-    // round trip, so the state is back in A; the remaining steps take the paths below.
-    const bool two_applies = fused && a.side.nsrc == 0 && np == 0 && !(s->checking && s->check_every > 0) &&
+    // Two steps per sweep (periodic grids with edge classes) where nothing but soft sources happens
+    // between the steps: no probes or non-finite checks.  Launches go A -> B -> A (E, H and Js), four
+    // steps per round trip, so the state is back in A; the remaining steps take the paths below.
+    const bool two_applies = fused && np == 0 && !(s->checking && s->check_every > 0) &&
                              !(a.pml[0].on || a.pml[1].on || a.pml[2].on) && a.cls[0] != nullptr;
     const bool two = two_applies && (s->sweep == TFL_SWEEP_TWO_STEP || (s->sweep == TFL_SWEEP_AUTO &&
                                                                         two_step_pays<T>(a)));
@@ -287,7 +287,12 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
         for (; it + 4 <= nsteps; it += 4) {
             for (int h = 0; h < 2; ++h) {
                 if (ev && (e = hipEventRecord(ev[2 * (it + 2 * h)], st)) != hipSuccess) return hip_fail(s, e, "event");
-                if ((e = launch_two_step<T>(h == 0 ? ab2 : ba2, st)) != hipSuccess) return hip_fail(s, e, "two steps");
+                // the sources' values at the launch's two steps
+                StepArgs<T> g = h == 0 ? ab2 : ba2;
+                source_values(s, g.side, (double)(s->step + 2 * h + 1) * s->cfg.dt);
+                for (int q = 0; q < g.side.nsrc; ++q)
+                    g.side.sg2[q] = source_value(s->src[q], (double)(s->step + 2 * h + 2) * s->cfg.dt);
+                if ((e = launch_two_step<T>(g, st)) != hipSuccess) return hip_fail(s, e, "two steps");
                 // the two steps' events: the sweep in the first interval, the others empty
                 for (int q = 1; q < 4 && ev; ++q)
                     if ((e = hipEventRecord(ev[2 * (it + 2 * h) + q], st)) != hipSuccess) return hip_fail(s, e, "event");

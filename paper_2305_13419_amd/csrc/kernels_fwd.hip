@@ -171,13 +171,21 @@ __device__ __forceinline__ uint64_t side_mask(const SideArgs &sd, int i, int j, 
 // probes of mask m: the sources whose boxes hold the edge add their values in source order, and the
 // probes whose boxes hold it receive a copy of the result.
 template <typename T>
-__device__ __forceinline__ T side_e(const SideArgs &sd, uint64_t m, int q, int i, int j, int k, T v)
+__device__ __forceinline__ T add_sources(const SideArgs &sd, const double *sg, uint64_t m, int q, int i, int j, int k,
+                                         T v)
 {
     for (uint32_t ms = (uint32_t)m; ms != 0; ms &= ms - 1) {
         const int *b = sd.sbox[__builtin_ctz(ms)];
         if (b[0] == q && k >= b[5] && k < b[6] && j >= b[3] && j < b[4] && i >= b[1] && i < b[2])
-            v = (T)((double)v + sd.sg[__builtin_ctz(ms)]);
+            v = (T)((double)v + sg[__builtin_ctz(ms)]);
     }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T side_e(const SideArgs &sd, uint64_t m, int q, int i, int j, int k, T v)
+{
+    v = add_sources(sd, sd.sg, m, q, i, j, k, v);
     for (uint32_t mp = (uint32_t)(m >> 32); mp != 0; mp &= mp - 1) {
         const int p = __builtin_ctz(mp);
         const int *b = sd.pbox[p];
@@ -795,7 +803,7 @@ struct TwoStepShared {
     T h2[3][TY][kTileX];        // H^{n+3/2} of the previous plane
 };
 
-template <typename T, int TY, int TZ, bool NT>
+template <typename T, int TY, int TZ, bool NT, bool SRC>
 __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<T> a)
 {
     constexpr int OX = kTwoStepOX, OY = TY - 2;
@@ -809,6 +817,9 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
     const int wave = __builtin_amdgcn_readfirstlane(row);
     const int xo = tx * OX + lane - 2, yo = ty * OY + row - 1;  // the cell's output coordinates
     const int i = wrap_index(xo, nx), j = wrap_index(yo, ny);
+    // soft sources whose boxes meet this wavefront's columns (any plane: the runs wrap along z); SRC:
+    // an instantiation of its own, so that the sweep without sources keeps its registers
+    [[maybe_unused]] const uint64_t side = SRC ? side_mask(a.side, i, j, 0, nz) : 0;
     const bool out = lane >= 2 && lane <= OX + 1 && xo < nx && row >= 1 && row <= OY && yo < ny;
     const int k0 = tz * TZ, k1 = min(k0 + TZ, nz);
     const long long sxy = a.g.sxy;
@@ -973,6 +984,11 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
             ex_n = qx.ca * ex0 + qx.cb * ((dyHz - dzHy) - jx);
             ey_n = qy.ca * ey0 + qy.cb * ((dzHx - dxHz) - jy);
             ez_n = qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz);
+            if (SRC && side != 0) {  // the first step's sources, on every lane (the halo lanes' copies too)
+                ex_n = add_sources(a.side, a.side.sg, side, 0, i, j, kc, ex_n);
+                ey_n = add_sources(a.side, a.side.sg, side, 1, i, j, kc, ey_n);
+                ez_n = add_sources(a.side, a.side.sg, side, 2, i, j, kc, ez_n);
+            }
         }
         const int buf = it & 1;
         sh.e1[buf][0][row][lane] = ex_n;
@@ -1014,11 +1030,16 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
             if (px_.cj > T(0)) j2x = j2x + px_.cj * pex;
             if (py_.cj > T(0)) j2y = j2y + py_.cj * pey;
             if (pz_.cj > T(0)) j2z = j2z + pz_.cj * pez;
-            const T e2x = px_.ca * pex + px_.cb * ((dyHz - dzHy) - j2x);
-            const T e2y = py_.ca * pey + py_.cb * ((dzHx - dxHz) - j2y);
-            const T e2z = pz_.ca * pez + pz_.cb * ((dxHy - dyHx) - j2z);
+            T e2x = px_.ca * pex + px_.cb * ((dyHz - dzHy) - j2x);
+            T e2y = py_.ca * pey + py_.cb * ((dzHx - dxHz) - j2y);
+            T e2z = pz_.ca * pez + pz_.cb * ((dxHy - dyHx) - j2z);
+            const int kw = (kc == 0) ? nz - 1 : kc - 1;
+            if (SRC && side != 0) {  // the second step's sources
+                e2x = add_sources(a.side, a.side.sg2, side, 0, i, j, kw, e2x);
+                e2y = add_sources(a.side, a.side.sg2, side, 1, i, j, kw, e2y);
+                e2z = add_sources(a.side, a.side.sg2, side, 2, i, j, kw, e2z);
+            }
             if (out) {
-                const int kw = (kc == 0) ? nz - 1 : kc - 1;
                 const long long bw = opaque_offset((long long)kw * sxy);
                 stp_hint<NT>(a.Hout[0] + bw, o00, h2x);
                 stp_hint<NT>(a.Hout[1] + bw, o00, h2y);
@@ -1563,7 +1584,7 @@ struct TwoStepTiles<float> {
     static constexpr int ty = 16;
 };
 
-template <typename T, int TY, bool NT>
+template <typename T, int TY, bool NT, bool SRC>
 static void launch_two_step_nt(const StepArgs<T> &a, hipStream_t s)
 {
     constexpr int OX = kTwoStepOX, OY = TY - 2;
@@ -1575,10 +1596,9 @@ static void launch_two_step_nt(const StepArgs<T> &a, hipStream_t s)
     const dim3 blk(kTileX, TY);
     const unsigned grd = (unsigned)(cols * ((a.g.nz + tz - 1) / tz));
     switch (tz) {
-    case 64: hipLaunchKernelGGL((two_step_kernel<T, TY, 64, NT>), dim3(grd), blk, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((two_step_kernel<T, TY, 32, NT>), dim3(grd), blk, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((two_step_kernel<T, TY, 16, NT>), dim3(grd), blk, 0, s, a); break;
-    default: hipLaunchKernelGGL((two_step_kernel<T, TY, 8, NT>), dim3(grd), blk, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((two_step_kernel<T, TY, 32, NT, SRC>), dim3(grd), blk, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((two_step_kernel<T, TY, 16, NT, SRC>), dim3(grd), blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((two_step_kernel<T, TY, 8, NT, SRC>), dim3(grd), blk, 0, s, a); break;
     }
 }
 
@@ -1587,8 +1607,14 @@ hipError_t launch_two_step(const StepArgs<T> &a, hipStream_t s)
 {
     constexpr int TY = TwoStepTiles<T>::ty;
     const double touched = (double)a.g.sxy * a.g.nz * (15.0 * sizeof(T) + 6.0);
-    if (touched > 512.0 * 1024 * 1024) launch_two_step_nt<T, TY, true>(a, s);
-    else launch_two_step_nt<T, TY, false>(a, s);
+    const bool nt = touched > 512.0 * 1024 * 1024, src = a.side.nsrc > 0;
+    if (src) {
+        if (nt) launch_two_step_nt<T, TY, true, true>(a, s);
+        else launch_two_step_nt<T, TY, false, true>(a, s);
+    } else {
+        if (nt) launch_two_step_nt<T, TY, true, false>(a, s);
+        else launch_two_step_nt<T, TY, false, false>(a, s);
+    }
     return hipGetLastError();
 }
 

@@ -58,6 +58,7 @@ struct SideArgs {
     int nred;
     int sbox[TFL_MAX_SOURCES][7];  // component, i0, i1, j0, j1, k0, k1
     double sg[TFL_MAX_SOURCES];
+    double sg2[TFL_MAX_SOURCES];   // the values at the second step of a two-step sweep
     int pbox[kFoldProbes][7];
     void *pcopy[kFoldProbes];
     const void *rcopy[kFoldProbes];

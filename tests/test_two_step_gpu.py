@@ -22,6 +22,8 @@ def run(wl, steps, dtype, sweep, chunks=None):
     sim.set_fields([np.asarray(a, dtype=npdt) for a in E], [np.asarray(a, dtype=npdt) for a in H],
                    None if J is None else [np.asarray(a, dtype=npdt) for a in J])
     sim.set_sweep(sweep)
+    for src in wl.get("sources", []):
+        sim.add_source(**src)
     counts = np.zeros(3, dtype=np.int64)
     for c in (chunks or [steps]):
         sim.step(c)
@@ -53,8 +55,8 @@ def test_two_step_equals_fused(shape, dtype):
 
 def test_two_step_is_automatic_on_large_periodic_grids():
     """The default policy takes the two-step sweep on a periodic grid with classes past the infinity
-    cache (here 3.3 M cells), in both precisions, the fused sweep on a smaller one, and not where
-    sources or probes act every step."""
+    cache (here 3.3 M cells), in both precisions, the fused sweep on a smaller one, still with soft
+    sources (which ride along with both steps), and not where probes record every step."""
     from paper_2305_13419_amd import Simulation
     small = workloads.roofline_grid((128, 128, 128))
     for dtype in (torch.float32, torch.float64):
@@ -70,6 +72,9 @@ def test_two_step_is_automatic_on_large_periodic_grids():
         sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype)
         sim.set_materials(*wl["maps"])
         sim.set_fields(E, H)
+        sim.step(10)
+        assert sim.sweep_counts() == expect
+        sim.add_source(comp=1, box=(0, 160, 0, 160, 9, 10), amplitude=1.0, waveform="sin", freq=2e14)
         sim.step(10)
         assert sim.sweep_counts() == expect
         sim.add_probe(0, (5, 6, 0, 128, 7, 8), 0)
@@ -101,3 +106,43 @@ def test_two_step_matches_oracle(dtype, tol):
     r = compare(g, o)
     print(f"two-step {dtype} vs oracle, 12 steps: {r}", flush=True)
     assert max(r.values()) <= tol
+
+
+SOURCES = [
+    # a plane source across every footprint row and column, boxes on the x = 0 and y = 0 edges (the
+    # wrapped halo columns and rows of neighbouring footprints), two boxes overlapping on Ey
+    dict(comp=1, box=(0, 130, 0, 33, 7, 8), amplitude=1.5, waveform="sin", freq=2e14),
+    dict(comp=1, box=(60, 64, 10, 20, 3, 15), amplitude=-0.7, waveform="mod_gauss", freq=3e14, t0=2e-15, tw=8e-16),
+    dict(comp=0, box=(0, 2, 0, 3, 0, 20), amplitude=0.9, waveform="gauss", t0=1e-15, tw=5e-16),
+    dict(comp=2, box=(125, 130, 30, 33, 18, 20), amplitude=2.0, waveform="sin", freq=1e14),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_two_step_with_sources(dtype):
+    """Soft sources ride along with both steps of the two-step sweep: the same bits as the fused sweep
+    (which adds them to E^{n+1} inside the sweep), and the oracle's fields."""
+    wl = workloads.random_medium((130, 33, 20), seed=19)
+    wl["maps"] = workloads.roofline_grid((130, 33, 20))["maps"]
+    wl["fields"] = (wl["fields"][0], wl["fields"][1], None)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    wl["fields"] = tuple(None if g is None else [np.asarray(a, dtype=npdt).astype(np.float64) for a in g]
+                         for g in wl["fields"])
+    wl["maps"] = tuple(np.asarray(m, dtype=npdt).astype(np.float64) for m in wl["maps"])
+    wl["sources"] = SOURCES
+    print(f"case: two-step with sources, (130, 33, 20), {dtype}, 11 steps (chunks 8, 3)", flush=True)
+    a, ca, sa = run(wl, 11, dtype, "two_step", [8, 3])
+    b, cb, sb = run(wl, 11, dtype, "fused", [8, 3])
+    assert ca[2] == 8 and cb[2] == 0, (ca, cb)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    Eg, Hg, Jg = sa.integer_time_fields()
+    torch.cuda.synchronize()
+    g = ([t.double().cpu().numpy() for t in Eg], [t.double().cpu().numpy() for t in Hg],
+         [t.double().cpu().numpy() for t in Jg], [])
+    sa.close()
+    sb.close()
+    o = run_oracle(wl, 11)
+    r = compare(g, o)
+    print(f"two-step with sources {dtype} vs oracle, 11 steps: {r}", flush=True)
+    assert max(r.values()) <= (1e-12 if dtype == torch.float64 else 1e-5)
