@@ -162,9 +162,10 @@ int tfl_bind_workspace(tfl_sim *sim, void *workspace, void *scratch, void *strea
  * Steps run in pairs (bound fields -> buffer -> bound fields), an odd last
  * step with the two passes, so the state is in the bound fields and the
  * workspace after every call.  On periodic grids with edge classes bound,
- * stretches of at least four steps with no probes or non-finite checks (soft
- * sources are added inside the sweep, to both steps' E) run two time steps per
- * sweep (temporal blocking): each sweep reads
+ * stretches of at least four steps with no non-finite checks and no probe
+ * launches (soft sources are added inside the sweep to both steps' E, and
+ * folded probes copy both steps' E) run two time steps per sweep (temporal
+ * blocking): each sweep reads
  * E^n, H^{n-1/2}, Js^{n-1/2} from one set and writes E^{n+2}, H^{n+3/2},
  * Js^{n+3/2} to the other, so per step each cell's fields cross HBM half as
  * often; the results again equal those of the two passes bit for bit.  The buffer is caller-owned device memory,
@@ -183,8 +184,9 @@ int tfl_bind_fused_buffer(tfl_sim *sim, void *buffer);
  *  TFL_SWEEP_FUSED     the fused sweep wherever a buffer is bound, no
  *                      two-step sweep;
  *  TFL_SWEEP_TWO_STEP  the two-step sweep wherever it applies (periodic grid,
- *                      edge classes bound, buffer bound, no probes or
- *                      checks, stretches of four steps), whatever the size;
+ *                      edge classes bound, buffer bound, no checks, probes
+ *                      folded with two steps' copies in a half of the copy
+ *                      space, stretches of four steps), whatever the size;
  *                      the fused sweep elsewhere.
  * tfl_sweep_counts: steps the last tfl_step call ran on the two passes, the
  * fused sweep and the two-step sweep (counts[0..2]).  TFL_E_INVAL on a bad
@@ -252,8 +254,11 @@ int tfl_clear_sources_probes(tfl_sim *sim);
  * FP64 values over all boxes), each sweep also copies the new E on the boxes to
  * scratch and the next sweep sums the copies of the previous one (one probe
  * launch after the call's last step sums the last copies), so a step is one
- * launch; otherwise a probe launch follows every step.  The sums are formed in
- * the same order either way. */
+ * launch; otherwise a probe launch follows every step.  A two-step sweep
+ * copies both of its steps' E, each to a quarter of the space (224 KiB), and
+ * the next sweep records both samples in order; probes whose copies exceed a
+ * quarter keep the one-step sweeps.  The sums are formed in the same order
+ * every way. */
 int tfl_step(tfl_sim *sim, int64_t nsteps, void *stream);
 
 /* Optional non-finite check (a guard for long runs; off by default).  With

@@ -187,18 +187,21 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
     // halves of scratch: each sweep copies its new E on the boxes to one half and first sums the
     // copies the previous sweep left in the other; one probe launch after the last step sums the
     // last copies.  Otherwise a probe launch follows every step.
+    // A two-step sweep leaves two samples: its copies go to the two quarters of a half.
     size_t coff[kFoldProbes] = {};
     bool fold = np > 0 && np <= kFoldProbes;
-    {
-        size_t off = 0;
-        for (int p = 0; p < np && fold; ++p) {
-            const ProbeDesc &d = s->probe[p];
-            coff[p] = off;
-            off += round256((size_t)(d.i1 - d.i0) * (d.j1 - d.j0) * (d.k1 - d.k0) * sizeof(T));
-            fold = off <= kProbeCopyHalf;
-        }
+    size_t copy_bytes = 0;
+    for (int p = 0; p < np && fold; ++p) {
+        const ProbeDesc &d = s->probe[p];
+        coff[p] = copy_bytes;
+        copy_bytes += round256((size_t)(d.i1 - d.i0) * (d.j1 - d.j0) * (d.k1 - d.k0) * sizeof(T));
+        fold = copy_bytes <= kProbeCopyHalf;
     }
+    const bool fold2 = fold && copy_bytes <= kProbeCopyHalf / 2;
     char *const copy_base = (char *)s->scratch + kProbeCopyOffset;
+    auto copy_at = [&](int hf, int sample, int p) {
+        return copy_base + hf * kProbeCopyHalf + sample * (kProbeCopyHalf / 2) + coff[p];
+    };
     if (fold) {
         a.side.pdesc = pa.p;
         a.side.dt = s->cfg.dt;
@@ -209,26 +212,34 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
         }
     }
     int half = 0;          // copy half the next sweep writes
-    bool pending = false;  // copies of sample pending_n wait in the other half
+    bool pending = false;  // copies of samples pending_n .. pending_n + pending_cnt - 1 wait in the other half
     int64_t pending_n = 0;
+    int pending_cnt = 0;
+    auto probes_of = [&](StepArgs<T> &g) {
+        if (!fold) return;
+        g.side.nprobe = np;
+        g.side.nred = pending ? np : 0;
+        g.side.nsamp = pending_cnt;
+        g.side.rn = pending_n;
+        for (int p = 0; p < np; ++p) {
+            g.side.pcopy[p] = copy_at(half, 0, p);
+            g.side.pcopy2[p] = copy_at(half, 1, p);
+            g.side.rcopy[p] = copy_at(1 - half, 0, p);
+            g.side.rcopy2[p] = copy_at(1 - half, 1, p);
+        }
+    };
     // the side work of the sweep of step s->step -> s->step + 1
     auto side = [&](StepArgs<T> g) {
         source_values(s, g.side, (double)(s->step + 1) * s->cfg.dt);
-        if (fold) {
-            g.side.nprobe = np;
-            g.side.nred = pending ? np : 0;
-            g.side.rn = pending_n;
-            for (int p = 0; p < np; ++p) {
-                g.side.pcopy[p] = copy_base + half * kProbeCopyHalf + coff[p];
-                g.side.rcopy[p] = copy_base + (1 - half) * kProbeCopyHalf + coff[p];
-            }
-        }
+        probes_of(g);
         return g;
     };
-    auto side_done = [&]() {
+    // after a sweep whose cnt samples start at index first
+    auto side_done = [&](int64_t first, int cnt) {
         if (!fold) return;
         pending = true;
-        pending_n = s->step;  // after the increment: the sample index of the new E
+        pending_n = first;
+        pending_cnt = cnt;
         half = 1 - half;
     };
     // With a fused buffer bound, steps go A -> B -> A in pairs through the fused sweep (A the bound
@@ -236,10 +247,11 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
     // two passes in place on A.
     StepArgs<T> ab = a, ba = a;
     const bool fused = s->fused != nullptr && s->sweep != TFL_SWEEP_TWO_PASS;
-    // Two steps per sweep (periodic grids with edge classes) where nothing but soft sources happens
-    // between the steps: no probes or non-finite checks.  Launches go A -> B -> A (E, H and Js), four
-    // steps per round trip, so the state is back in A; the remaining steps take the paths below.
-    const bool two_applies = fused && np == 0 && !(s->checking && s->check_every > 0) &&
+    // Two steps per sweep (periodic grids with edge classes) where nothing but soft sources and folded
+    // probes happens between the steps: no probe launches or non-finite checks.  Launches go A -> B ->
+    // A (E, H and Js), four steps per round trip, so the state is back in A; the remaining steps take
+    // the paths below.
+    const bool two_applies = fused && (np == 0 || fold2) && !(s->checking && s->check_every > 0) &&
                              !(a.pml[0].on || a.pml[1].on || a.pml[2].on) && a.cls[0] != nullptr;
     const bool two = two_applies && (s->sweep == TFL_SWEEP_TWO_STEP || (s->sweep == TFL_SWEEP_AUTO &&
                                                                         two_step_pays<T>(a)));
@@ -287,12 +299,14 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
         for (; it + 4 <= nsteps; it += 4) {
             for (int h = 0; h < 2; ++h) {
                 if (ev && (e = hipEventRecord(ev[2 * (it + 2 * h)], st)) != hipSuccess) return hip_fail(s, e, "event");
-                // the sources' values at the launch's two steps
+                // the sources' values at the launch's two steps, the probes' copies of both
                 StepArgs<T> g = h == 0 ? ab2 : ba2;
                 source_values(s, g.side, (double)(s->step + 2 * h + 1) * s->cfg.dt);
                 for (int q = 0; q < g.side.nsrc; ++q)
                     g.side.sg2[q] = source_value(s->src[q], (double)(s->step + 2 * h + 2) * s->cfg.dt);
+                probes_of(g);
                 if ((e = launch_two_step<T>(g, st)) != hipSuccess) return hip_fail(s, e, "two steps");
+                side_done(s->step + 2 * h + 1, 2);
                 // the two steps' events: the sweep in the first interval, the others empty
                 for (int q = 1; q < 4 && ev; ++q)
                     if ((e = hipEventRecord(ev[2 * (it + 2 * h) + q], st)) != hipSuccess) return hip_fail(s, e, "event");
@@ -317,7 +331,7 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
         }
         for (int q = 0; q < 3; ++q) pa.E[q] = inB ? ab.Eout[q] : a.E[q];
         s->step += 1;
-        side_done();
+        side_done(s->step, 1);  // the sample index of the new E
         if (np > 0 && !fold) {
             pa.n = s->step;
             if ((e = launch_probes<T>(pa, np, st)) != hipSuccess) return hip_fail(s, e, "probe");
@@ -335,9 +349,9 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
             s->checked = true;
         }
     }
-    if (pending) {  // the last sweep's copies
-        pa.n = pending_n;
-        for (int p = 0; p < np; ++p) pa.copy[p] = (const T *)(copy_base + (1 - half) * kProbeCopyHalf + coff[p]);
+    for (int r = 0; pending && r < pending_cnt; ++r) {  // the last sweep's copies
+        pa.n = pending_n + r;
+        for (int p = 0; p < np; ++p) pa.copy[p] = (const T *)copy_at(1 - half, r, p);
         if ((e = launch_probes<T>(pa, np, st)) != hipSuccess) return hip_fail(s, e, "probe");
     }
     if (ev && nsteps > 0 && (e = hipEventRecord(ev[2 * nsteps], st)) != hipSuccess) return hip_fail(s, e, "event");

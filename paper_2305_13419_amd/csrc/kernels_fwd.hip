@@ -183,31 +183,41 @@ __device__ __forceinline__ T add_sources(const SideArgs &sd, const double *sg, u
 }
 
 template <typename T>
-__device__ __forceinline__ T side_e(const SideArgs &sd, uint64_t m, int q, int i, int j, int k, T v)
+__device__ __forceinline__ void probe_copy(const SideArgs &sd, void *const *copy, uint64_t m, int q, int i, int j,
+                                           int k, T v)
 {
-    v = add_sources(sd, sd.sg, m, q, i, j, k, v);
     for (uint32_t mp = (uint32_t)(m >> 32); mp != 0; mp &= mp - 1) {
         const int p = __builtin_ctz(mp);
         const int *b = sd.pbox[p];
         if (b[0] == q && k >= b[5] && k < b[6] && j >= b[3] && j < b[4] && i >= b[1] && i < b[2]) {
             const long long c = ((long long)(k - b[5]) * (b[4] - b[3]) + (j - b[3])) * (b[2] - b[1]) + (i - b[1]);
-            ((T *)sd.pcopy[p])[c] = v;
+            ((T *)copy[p])[c] = v;
         }
     }
+}
+
+template <typename T>
+__device__ __forceinline__ T side_e(const SideArgs &sd, uint64_t m, int q, int i, int j, int k, T v)
+{
+    v = add_sources(sd, sd.sg, m, q, i, j, k, v);
+    probe_copy(sd, sd.pcopy, m, q, i, j, k, v);
     return v;
 }
 
-// First thing of a sweep: blocks 0 .. nred-1 record the previous sweep's probe sample rn, one probe
-// per block, from the copies it left.
+// First thing of a sweep: blocks 0 .. nred-1 record the previous sweep's probe samples rn (and rn + 1
+// after a two-step sweep), one probe per block, from the copies it left, in sample order.
 template <typename T>
 __device__ __forceinline__ void side_reduce(const SideArgs &sd)
 {
     if ((int)blockIdx.x >= sd.nred) return;
     const ProbeDesc &p = sd.pdesc[blockIdx.x];
-    const T *c = (const T *)sd.rcopy[blockIdx.x];
     const long long cnt = (long long)(p.i1 - p.i0) * (p.j1 - p.j0) * (p.k1 - p.k0);
-    const double s = probe_sum(cnt, [c](long long idx) { return (double)c[idx]; });
-    probe_record(p, s, sd.rn, sd.dt);
+    for (int r = 0; r < sd.nsamp; ++r) {
+        if (r > 0) __syncthreads();  // every wavefront has read the previous sum's partials
+        const T *c = (const T *)(r == 0 ? sd.rcopy[blockIdx.x] : sd.rcopy2[blockIdx.x]);
+        const double s = probe_sum(cnt, [c](long long idx) { return (double)c[idx]; });
+        probe_record(p, s, sd.rn + r, sd.dt);
+    }
 }
 
 template <typename T, int TY, int TZ, bool CLS, int W>
@@ -803,9 +813,10 @@ struct TwoStepShared {
     T h2[3][TY][kTileX];        // H^{n+3/2} of the previous plane
 };
 
-template <typename T, int TY, int TZ, bool NT, bool SRC>
+template <typename T, int TY, int TZ, bool NT, bool SIDE>
 __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<T> a)
 {
+    if constexpr (SIDE) side_reduce<T>(a.side);
     constexpr int OX = kTwoStepOX, OY = TY - 2;
     using S = TwoStepShared<T, TY>;
     constexpr int RW = S::RW, NR = S::NR;
@@ -817,9 +828,9 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
     const int wave = __builtin_amdgcn_readfirstlane(row);
     const int xo = tx * OX + lane - 2, yo = ty * OY + row - 1;  // the cell's output coordinates
     const int i = wrap_index(xo, nx), j = wrap_index(yo, ny);
-    // soft sources whose boxes meet this wavefront's columns (any plane: the runs wrap along z); SRC:
-    // an instantiation of its own, so that the sweep without sources keeps its registers
-    [[maybe_unused]] const uint64_t side = SRC ? side_mask(a.side, i, j, 0, nz) : 0;
+    // soft sources and probes whose boxes meet this wavefront's columns (any plane: the runs wrap
+    // along z); SIDE: an instantiation of its own, so that the sweep without them keeps its registers
+    [[maybe_unused]] const uint64_t side = SIDE ? side_mask(a.side, i, j, 0, nz) : 0;
     const bool out = lane >= 2 && lane <= OX + 1 && xo < nx && row >= 1 && row <= OY && yo < ny;
     const int k0 = tz * TZ, k1 = min(k0 + TZ, nz);
     const long long sxy = a.g.sxy;
@@ -984,7 +995,7 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
             ex_n = qx.ca * ex0 + qx.cb * ((dyHz - dzHy) - jx);
             ey_n = qy.ca * ey0 + qy.cb * ((dzHx - dxHz) - jy);
             ez_n = qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz);
-            if (SRC && side != 0) {  // the first step's sources, on every lane (the halo lanes' copies too)
+            if (SIDE && (uint32_t)side != 0) {  // the first step's sources, on every lane (the halo lanes' copies too)
                 ex_n = add_sources(a.side, a.side.sg, side, 0, i, j, kc, ex_n);
                 ey_n = add_sources(a.side, a.side.sg, side, 1, i, j, kc, ey_n);
                 ez_n = add_sources(a.side, a.side.sg, side, 2, i, j, kc, ez_n);
@@ -1034,7 +1045,7 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
             T e2y = py_.ca * pey + py_.cb * ((dzHx - dxHz) - j2y);
             T e2z = pz_.ca * pez + pz_.cb * ((dxHy - dyHx) - j2z);
             const int kw = (kc == 0) ? nz - 1 : kc - 1;
-            if (SRC && side != 0) {  // the second step's sources
+            if (SIDE && (uint32_t)side != 0) {  // the second step's sources
                 e2x = add_sources(a.side, a.side.sg2, side, 0, i, j, kw, e2x);
                 e2y = add_sources(a.side, a.side.sg2, side, 1, i, j, kw, e2y);
                 e2z = add_sources(a.side, a.side.sg2, side, 2, i, j, kw, e2z);
@@ -1050,6 +1061,14 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
                 if (px_.cj > T(0)) stp(a.Jout[0] + bw, o00, j2x);
                 if (py_.cj > T(0)) stp(a.Jout[1] + bw, o00, j2y);
                 if (pz_.cj > T(0)) stp(a.Jout[2] + bw, o00, j2z);
+                if (SIDE && (side >> 32) != 0) {  // both steps' probe copies: E^{n+1} and E^{n+2}
+                    probe_copy(a.side, a.side.pcopy, side, 0, i, j, kw, pex);
+                    probe_copy(a.side, a.side.pcopy, side, 1, i, j, kw, pey);
+                    probe_copy(a.side, a.side.pcopy, side, 2, i, j, kw, pez);
+                    probe_copy(a.side, a.side.pcopy2, side, 0, i, j, kw, e2x);
+                    probe_copy(a.side, a.side.pcopy2, side, 1, i, j, kw, e2y);
+                    probe_copy(a.side, a.side.pcopy2, side, 2, i, j, kw, e2z);
+                }
             }
         }
         // carry to the next plane
@@ -1584,7 +1603,7 @@ struct TwoStepTiles<float> {
     static constexpr int ty = 16;
 };
 
-template <typename T, int TY, bool NT, bool SRC>
+template <typename T, int TY, bool NT, bool SIDE>
 static void launch_two_step_nt(const StepArgs<T> &a, hipStream_t s)
 {
     constexpr int OX = kTwoStepOX, OY = TY - 2;
@@ -1596,9 +1615,9 @@ static void launch_two_step_nt(const StepArgs<T> &a, hipStream_t s)
     const dim3 blk(kTileX, TY);
     const unsigned grd = (unsigned)(cols * ((a.g.nz + tz - 1) / tz));
     switch (tz) {
-    case 32: hipLaunchKernelGGL((two_step_kernel<T, TY, 32, NT, SRC>), dim3(grd), blk, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((two_step_kernel<T, TY, 16, NT, SRC>), dim3(grd), blk, 0, s, a); break;
-    default: hipLaunchKernelGGL((two_step_kernel<T, TY, 8, NT, SRC>), dim3(grd), blk, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((two_step_kernel<T, TY, 32, NT, SIDE>), dim3(grd), blk, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((two_step_kernel<T, TY, 16, NT, SIDE>), dim3(grd), blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((two_step_kernel<T, TY, 8, NT, SIDE>), dim3(grd), blk, 0, s, a); break;
     }
 }
 
@@ -1607,8 +1626,8 @@ hipError_t launch_two_step(const StepArgs<T> &a, hipStream_t s)
 {
     constexpr int TY = TwoStepTiles<T>::ty;
     const double touched = (double)a.g.sxy * a.g.nz * (15.0 * sizeof(T) + 6.0);
-    const bool nt = touched > 512.0 * 1024 * 1024, src = a.side.nsrc > 0;
-    if (src) {
+    const bool nt = touched > 512.0 * 1024 * 1024;
+    if (a.side.nsrc > 0 || a.side.nprobe > 0 || a.side.nred > 0) {
         if (nt) launch_two_step_nt<T, TY, true, true>(a, s);
         else launch_two_step_nt<T, TY, false, true>(a, s);
     } else {

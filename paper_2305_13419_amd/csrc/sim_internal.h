@@ -75,7 +75,8 @@ size_t fused_layout(const tfl_sim *s, size_t psi_at[3], size_t *total = nullptr)
 void class_pointers(const tfl_sim *s, const uint16_t *cls[3], const void **table);
 
 // scratch buffer layout: reduction partials, the objective DFT, probe descriptors, and two halves
-// for the sweeps' probe copies (a sweep writes one half while it sums the other)
+// for the sweeps' probe copies (a sweep writes one half while it sums the other; a two-step sweep
+// writes its two steps' copies to the two quarters of its half)
 constexpr size_t kScratchBytes = 1 << 20;
 constexpr int kRedBlocks = 1024;            // reductions use doubles [0, 5 * kRedBlocks)
 constexpr size_t kObjectiveSlot = 6144;     // doubles [6144, 6146): objective DFT

@@ -44,26 +44,32 @@ struct PmlAxis {
 
 struct ProbeDesc;
 
-// Work that rides along with the E update of a sweep (the fused sweep and the E pass), so that a
-// step with sources and probes is still one launch:
-//  - soft sources: the sweep adds sg[p] (the value source p adds at this step) to the new E of every
-//    edge of box p, in source order, after the PEC walls are zeroed;
+// Work that rides along with the E update of a sweep (the fused sweep, the E pass and the two-step
+// sweep), so that a step with sources and probes is still one launch:
+//  - soft sources: the sweep adds sg[p] (the value source p adds at this step; sg2[p] at the second
+//    step of a two-step sweep) to the new E of every edge of box p, in source order, after the PEC
+//    walls are zeroed;
 //  - probe copies: the new E of each edge of probe p's box goes to pcopy[p] in box order (x fastest);
-//  - probe sums: blocks 0 .. nred-1 first sum the copies rcopy[b] that the previous sweep wrote
-//    and record sample rn of probe b (series and DFT), with the probe kernel's summation order.
+//    a two-step sweep writes its first step's E there and its second step's to pcopy2[p];
+//  - probe sums: blocks 0 .. nred-1 first sum the copies rcopy[b] (and then rcopy2[b]) that the
+//    previous sweep wrote and record samples rn (and rn + 1) of probe b (series and DFT), with the
+//    probe kernel's summation order.
 constexpr int kFoldProbes = 4;
 struct SideArgs {
     int nsrc;
     int nprobe;
-    int nred;
+    int nred;                      // probes whose pending samples the sweep records first (0: none)
+    int nsamp;                     // pending samples per probe: 1 (rcopy) or 2 (rcopy, then rcopy2)
     int sbox[TFL_MAX_SOURCES][7];  // component, i0, i1, j0, j1, k0, k1
     double sg[TFL_MAX_SOURCES];
     double sg2[TFL_MAX_SOURCES];   // the values at the second step of a two-step sweep
     int pbox[kFoldProbes][7];
     void *pcopy[kFoldProbes];
+    void *pcopy2[kFoldProbes];     // the second step's copies (two-step sweep)
     const void *rcopy[kFoldProbes];
+    const void *rcopy2[kFoldProbes];
     const ProbeDesc *pdesc;        // descriptors of the probes (device memory)
-    long long rn;
+    long long rn;                  // sample index of the first pending sample
     double dt;
 };
 

@@ -28,12 +28,14 @@ def run(wl, steps, dtype, sweep="auto", chunks=None, fused=True):
     for s in wl["sources"]:
         sim.add_source(**s)
     pids = [sim.add_probe(p["comp"], p["box"], steps + 1, p.get("freqs", ())) for p in wl["probes"]]
+    counts = np.zeros(3, dtype=np.int64)
     for c in chunks or [steps]:
         sim.step(c)
+        counts += np.array(sim.sweep_counts())
     Eg, Hg, Jg = sim.integer_time_fields()
     torch.cuda.synchronize()
     out = ([t.double().cpu().numpy() for t in Eg], [t.double().cpu().numpy() for t in Hg],
-           [t.double().cpu().numpy() for t in Jg], [sim.probe(p) for p in pids])
+           [t.double().cpu().numpy() for t in Jg], [sim.probe(p) for p in pids], counts)
     sim.close()
     return out
 
@@ -78,6 +80,49 @@ def test_folded_probes_equal_probe_launches(dtype, sweep):
     c = run(wl, steps, dtype, sweep, chunks=[1, 6, 10])
     same(a, c)
     o = run_oracle(wl, steps, np.float64 if dtype == torch.float64 else np.float32)
+    res = compare(a, o)
+    print("  rel-L2:", {k: f"{v:.2e}" for k, v in res.items()}, flush=True)
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    for k, v in res.items():
+        assert v <= tol, (k, v)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_folded_probes_two_step(dtype):
+    """On a periodic grid with edge classes the two-step sweep copies both steps' E on the probe
+    boxes, and the next sweep (two-step, fused or the E pass) records both samples: the series and
+    DFTs equal those of probe launches after every step (five probes), and the fields those of the
+    fused sweep, with the steps in one call (four two-step launches, then the two passes) and split
+    over calls of 1, 6 and 10 steps (two-step launches followed by fused sweeps)."""
+    shape = (130, 33, 20)
+    wl = workloads.random_medium(shape, seed=23)
+    wl["maps"] = workloads.roofline_grid(shape)["maps"]  # few distinct materials: edge classes bind
+    wl["fields"] = (wl["fields"][0], wl["fields"][1], None)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    wl["fields"] = tuple(None if g is None else [np.asarray(a, dtype=npdt).astype(np.float64) for a in g]
+                         for g in wl["fields"])
+    wl["maps"] = tuple(np.asarray(m, dtype=npdt).astype(np.float64) for m in wl["maps"])
+    wl["sources"] = [
+        dict(comp=1, box=(60, 61, 0, 33, 5, 15), amplitude=2.0, waveform="mod_gauss", freq=3e14, t0=2e-15, tw=8e-16),
+        dict(comp=0, box=(0, 3, 0, 2, 0, 20), amplitude=0.5, waveform="sin", freq=1e14),
+    ]
+    wl["probes"] = [dict(comp=1, box=(90, 91, 0, 33, 0, 20), freqs=(3e14, 1e14)),
+                    dict(comp=0, box=(0, 1, 32, 33, 19, 20), freqs=(2e14,)),  # wrapped corner edge
+                    dict(comp=2, box=(0, 130, 0, 33, 10, 11)),
+                    dict(comp=1, box=(60, 61, 0, 33, 5, 15), freqs=(1e14,))]
+    steps = 17
+    print(f"case: two-step folded probes, {shape}, dtype={dtype}, steps={steps}", flush=True)
+    a = run(wl, steps, dtype, "two_step")
+    assert tuple(a[4]) == (1, 0, 16), a[4]
+    five = dict(wl, probes=wl["probes"] + [dict(comp=2, box=(3, 4, 3, 4, 3, 4))])
+    b = run(five, steps, dtype, "two_step")  # five probes: no fold, no two-step sweep
+    assert b[4][2] == 0, b[4]
+    b = (b[0], b[1], b[2], b[3][:4])
+    same(a, b)
+    c = run(wl, steps, dtype, "two_step", chunks=[1, 6, 10])
+    assert tuple(c[4]) == (1, 4, 12), c[4]
+    same(a, c)
+    o = run_oracle(wl, steps)
     res = compare(a, o)
     print("  rel-L2:", {k: f"{v:.2e}" for k, v in res.items()}, flush=True)
     tol = 1e-12 if dtype == torch.float64 else 1e-5

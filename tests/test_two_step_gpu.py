@@ -56,7 +56,8 @@ def test_two_step_equals_fused(shape, dtype):
 def test_two_step_is_automatic_on_large_periodic_grids():
     """The default policy takes the two-step sweep on a periodic grid with classes past the infinity
     cache (here 3.3 M cells), in both precisions, the fused sweep on a smaller one, still with soft
-    sources (which ride along with both steps), and not where probes record every step."""
+    sources and probes (which ride along with both steps), and not where the probes' copies of two
+    steps do not fit the scratch copy space."""
     from paper_2305_13419_amd import Simulation
     small = workloads.roofline_grid((128, 128, 128))
     for dtype in (torch.float32, torch.float64):
@@ -78,6 +79,9 @@ def test_two_step_is_automatic_on_large_periodic_grids():
         sim.step(10)
         assert sim.sweep_counts() == expect
         sim.add_probe(0, (5, 6, 0, 128, 7, 8), 0)
+        sim.step(10)
+        assert sim.sweep_counts() == expect
+        sim.add_probe(1, (0, 160, 0, 160, 7, 10), 0)  # 76 800 values: two copies exceed a half
         sim.step(10)
         assert sim.sweep_counts() == (0, 10, 0)
         sim.close()
