@@ -151,40 +151,40 @@ int tfl_bind_workspace(tfl_sim *sim, void *workspace, void *scratch, void *strea
 
 /* Optional second set of E, H and Js fields for the fused sweeps.
  * tfl_fused_buffer_bytes reports its size: 9 fields (E, H, Js), each padded
- * to 256 bytes, then on each CPML axis a second set of its two H-side
- * auxiliary variables (2 x the slab cells of the axis, padded to 256 bytes).
- * With a buffer bound, tfl_step runs H and E updates of a step in one sweep
- * (Algorithm 1, steps 1-5 of a time step fused): it reads E^n, H^{n-1/2} (and
- * the H-side CPML variables) from one set and writes E^{n+1}, H^{n+1/2} (and
- * the new variables) to the other, recomputing the few H values a cell needs
- * from its x-1 and y-1 neighbours, so each cell's fields cross HBM once per
- * step instead of twice; results equal those of the two passes bit for bit.
- * Steps run in pairs (bound fields -> buffer -> bound fields), an odd last
- * step with the two passes, so the state is in the bound fields and the
- * workspace after every call.  On periodic grids with edge classes bound,
- * stretches of at least four steps with no non-finite checks and no probe
- * launches (soft sources are added inside the sweep to both steps' E, and
- * folded probes copy both steps' E) run two time steps per sweep (temporal
- * blocking): each sweep reads
- * E^n, H^{n-1/2}, Js^{n-1/2} from one set and writes E^{n+2}, H^{n+3/2},
- * Js^{n+3/2} to the other, so per step each cell's fields cross HBM half as
- * often; the results again equal those of the two passes bit for bit.  The buffer is caller-owned device memory,
- * 256-byte aligned, holding nothing between calls; bind NULL to go back to
- * the two passes.  TFL_E_INVAL on a misaligned buffer. */
+ * to 256 bytes, then on each CPML axis a second set of its four auxiliary
+ * variables (two H-side, two E-side; 4 x the slab cells of the axis, padded
+ * to 256 bytes).  With a buffer bound, tfl_step runs H and E updates of a step
+ * in one sweep (Algorithm 1, steps 1-5 of a time step fused): it reads E^n,
+ * H^{n-1/2} (and the H-side CPML variables) from one set and writes E^{n+1},
+ * H^{n+1/2} (and the new variables) to the other, recomputing the few H values
+ * a cell needs from its x-1 and y-1 neighbours, so each cell's fields cross
+ * HBM once per step instead of twice; results equal those of the two passes
+ * bit for bit.  Steps run in pairs (bound fields -> buffer -> bound fields),
+ * an odd last step with the two passes, so the state is in the bound fields
+ * and the workspace after every call.  With edge classes bound, stretches of
+ * at least four steps with no non-finite checks and no probe launches (soft
+ * sources are added inside the sweep to both steps' E, and folded probes copy
+ * both steps' E) can run two time steps per sweep (temporal blocking): each
+ * sweep reads E^n, H^{n-1/2}, Js^{n-1/2} (and all CPML variables) from one set
+ * and writes E^{n+2}, H^{n+3/2}, Js^{n+3/2} (and the variables) to the other,
+ * so per step each cell's fields cross HBM half as often; the results again
+ * equal those of the two passes bit for bit.  The buffer is caller-owned
+ * device memory, 256-byte aligned, holding nothing between calls; bind NULL
+ * to go back to the two passes.  TFL_E_INVAL on a misaligned buffer. */
 int tfl_fused_buffer_bytes(const tfl_sim *sim, size_t *bytes);
 int tfl_bind_fused_buffer(tfl_sim *sim, void *buffer);
 
 /* Which sweeps a step may take (the results are the same bits on every path).
  *  TFL_SWEEP_AUTO      (default) the two-step sweep where it applies and pays
  *                      (grids of at least 3 * 2^20 cells, past the GPU's
- *                      infinity cache, nx >= 64, ny >= 32, nz >= 16), else
- *                      the fused sweep where a buffer is bound, else the
- *                      two passes;
+ *                      infinity cache, nx >= 64, ny >= 32, nz >= 16; on
+ *                      CPML grids in FP64 only), else the fused sweep where
+ *                      a buffer is bound, else the two passes;
  *  TFL_SWEEP_TWO_PASS  always the H and E passes;
  *  TFL_SWEEP_FUSED     the fused sweep wherever a buffer is bound, no
  *                      two-step sweep;
- *  TFL_SWEEP_TWO_STEP  the two-step sweep wherever it applies (periodic grid,
- *                      edge classes bound, buffer bound, no checks, probes
+ *  TFL_SWEEP_TWO_STEP  the two-step sweep wherever it applies (edge
+ *                      classes bound, buffer bound, no checks, probes
  *                      folded with two steps' copies in a half of the copy
  *                      space, stretches of four steps), whatever the size;
  *                      the fused sweep elsewhere.

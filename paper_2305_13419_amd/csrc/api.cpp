@@ -82,9 +82,9 @@ size_t fused_layout(const tfl_sim *s, size_t psi_at[3], size_t *total)
 {
     const size_t fb = round256((size_t)s->N * s->esz);
     size_t off = 9 * fb;  // second E, H and Js
-    for (int ax = 0; ax < 3; ++ax) {
+    for (int ax = 0; ax < 3; ++ax) {  // second set of the axis's variables: H side (two), E side (two)
         psi_at[ax] = off;
-        if (s->cfg.bc[ax] == TFL_CPML) off += round256(2 * s->psi_count[ax] * s->esz);
+        if (s->cfg.bc[ax] == TFL_CPML) off += round256(4 * s->psi_count[ax] * s->esz);
     }
     if (total) *total = off;
     return fb;
@@ -157,6 +157,7 @@ StepArgs<T> make_args(const tfl_sim *s)
         const size_t m = s->psi_count[ax];
         p.psiH[0] = ps; p.psiH[1] = ps + m; p.psiE[0] = ps + 2 * m; p.psiE[1] = ps + 3 * m;
         p.psiHo[0] = p.psiH[0]; p.psiHo[1] = p.psiH[1];
+        p.psiEo[0] = p.psiE[0]; p.psiEo[1] = p.psiE[1];
     }
     return a;
 }
@@ -252,7 +253,7 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
     // A (E, H and Js), four steps per round trip, so the state is back in A; the remaining steps take
     // the paths below.
     const bool two_applies = fused && (np == 0 || fold2) && !(s->checking && s->check_every > 0) &&
-                             !(a.pml[0].on || a.pml[1].on || a.pml[2].on) && a.cls[0] != nullptr;
+                             a.cls[0] != nullptr;
     const bool two = two_applies && (s->sweep == TFL_SWEEP_TWO_STEP || (s->sweep == TFL_SWEEP_AUTO &&
                                                                         two_step_pays<T>(a)));
     StepArgs<T> ab2 = a, ba2 = a;
@@ -295,6 +296,20 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
             ba2.Eout[q] = a.E[q];
             ba2.Hout[q] = a.H[q];
             ba2.Jout[q] = a.J[q];
+        }
+        // CPML axes: both sides' variables go A -> B -> A with the fields
+        for (int ax = 0; ax < 3; ++ax) {
+            if (!a.pml[ax].on || s->psi_count[ax] == 0) continue;
+            T *pb = (T *)((char *)s->fused + psi_at[ax]);
+            const size_t m = s->psi_count[ax];
+            for (int c = 0; c < 2; ++c) {
+                ab2.pml[ax].psiHo[c] = pb + c * m;
+                ab2.pml[ax].psiEo[c] = pb + (2 + c) * m;
+                ba2.pml[ax].psiH[c] = pb + c * m;
+                ba2.pml[ax].psiE[c] = pb + (2 + c) * m;
+                ba2.pml[ax].psiHo[c] = a.pml[ax].psiH[c];
+                ba2.pml[ax].psiEo[c] = a.pml[ax].psiE[c];
+            }
         }
         for (; it + 4 <= nsteps; it += 4) {
             for (int h = 0; h < 2; ++h) {

@@ -813,7 +813,7 @@ struct TwoStepShared {
     T h2[3][TY][kTileX];        // H^{n+3/2} of the previous plane
 };
 
-template <typename T, int TY, int TZ, bool NT, bool SIDE>
+template <typename T, int TY, int TZ, bool NT, bool SIDE, bool PML>
 __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<T> a)
 {
     if constexpr (SIDE) side_reduce<T>(a.side);
@@ -823,7 +823,9 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const int ntx = (nx + OX - 1) / OX, nty = (ny + OY - 1) / OY, ntz = (nz + TZ - 1) / TZ;
     const int t = logical_block(blockIdx.x, ntx * nty * ntz);
-    const int tx = t % ntx, tr = t / ntx, ty = tr % nty, tz = tr / nty;
+    const int tx = t % ntx, tr = t / ntx;
+    int ty, tz;
+    tile_yz(tr, nty, ntz, PML && a.pml[2].on, ty, tz);  // z-CPML grids: every XCD its share of the slab planes
     const int lane = threadIdx.x, row = threadIdx.y;
     const int wave = __builtin_amdgcn_readfirstlane(row);
     const int xo = tx * OX + lane - 2, yo = ty * OY + row - 1;  // the cell's output coordinates
@@ -840,8 +842,109 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
     const uint32_t oxp = uint32_t(j * nx + ip) * w, oyp = uint32_t(jp * nx + i) * w;
     const uint32_t oc = uint32_t(j * nx + i) * 2u;
     const T rdx = a.rd[0], rdy = a.rd[1], rdz = a.rd[2], hdt = a.hdt;
+    // CPML grids (PML): the slab slots (-1 outside) of the lane's column and of column x-1, of the row
+    // and of row y-1 (uniform over a wavefront), and the PEC walls; the auxiliary variables are read
+    // from the bound set and written to the other (a footprint's halo cells read the old values of
+    // cells another footprint writes), and the new values of the first step stay in registers
+    const PmlAxis<T> &px = a.pml[0], &py = a.pml[1], &pz = a.pml[2];
+    const int jw = __builtin_amdgcn_readfirstlane(j);
+    const int im = (i == 0) ? nx - 1 : i - 1, jmw = (jw == 0) ? ny - 1 : jw - 1;
+    [[maybe_unused]] int sx = -1, sxm = -1, sy = -1, sym = -1;
+    [[maybe_unused]] bool wall_x = false, wall_y = false;
+    [[maybe_unused]] const uint32_t oi = uint32_t(i) * w, oim = uint32_t(im) * w;
+    [[maybe_unused]] uint32_t osx = 0, osxm = 0;
+    if constexpr (PML) {
+        sx = px.on ? slab_slot(i, px.lo, px.hi, nx) : -1;
+        sxm = px.on ? slab_slot(im, px.lo, px.hi, nx) : -1;
+        sy = py.on ? slab_slot(jw, py.lo, py.hi, ny) : -1;
+        sym = py.on ? slab_slot(jmw, py.lo, py.hi, ny) : -1;
+        osx = uint32_t(sx) * w;
+        osxm = uint32_t(sxm) * w;
+        wall_x = px.on && i == 0;
+        wall_y = py.on && jw == 0;
+    }
+    auto zslot = [&](int kk) { return (PML && pz.on) ? slab_slot(kk, pz.lo, pz.hi, nz) : -1; };
+    // wavefronts with x-slab lanes (or x-1 neighbours in a slab): every wavefront of a block has the
+    // same columns
+    [[maybe_unused]] const bool xv = PML && px.on && px.P > 0 && __any(sx >= 0 || sxm >= 0);
+    [[maybe_unused]] const uint32_t osxc = uint32_t(sx >= 0 ? sx : 0) * w, osxmc = uint32_t(sxm >= 0 ? sxm : 0) * w;
+    // The auxiliary variables stage A and B read, loaded one plane ahead with the next plane's Js
+    // (a load consumed in the plane that issues it would also wait for the tile loads in flight):
+    // z slabs (the plane's): own faces, Hy's x-1 and Hx's y-1 neighbours, E side; x slabs (the
+    // lane's column, clamped into the slab): the same with the x-1 column, in FP32 only (FP64 has
+    // no registers left for them).  y slabs (and FP64 x slabs) read theirs in place.
+    constexpr bool XPRE = sizeof(T) == 4;
+    struct Psi {
+        T zh0, zh1, zh1xm, zh0ym, ze0, ze1, qh0, qh1, qh1ym, qm0, qm1, qe0, qe1;
+    };
+    auto load_psi = [&](int kk) {
+        Psi q{};
+        if constexpr (PML) {
+            const int sz = zslot(kk);
+            if (sz >= 0) {
+                const long long r = ((long long)sz * ny + jw) * nx, rym = ((long long)sz * ny + jmw) * nx;
+                q.zh0 = ldo(pz.psiH[0] + r, oi);
+                q.zh1 = ldo(pz.psiH[1] + r, oi);
+                q.zh1xm = ldo(pz.psiH[1] + r, oim);
+                q.zh0ym = ldo(pz.psiH[0] + rym, oi);
+                q.ze0 = ldo(pz.psiE[0] + r, oi);
+                q.ze1 = ldo(pz.psiE[1] + r, oi);
+            }
+            if (XPRE && xv) {
+                const long long r = ((long long)kk * ny + jw) * px.P, rym = ((long long)kk * ny + jmw) * px.P;
+                q.qh0 = ldo(px.psiH[0] + r, osxc);
+                q.qh1 = ldo(px.psiH[1] + r, osxc);
+                q.qh1ym = ldo(px.psiH[1] + rym, osxc);
+                q.qm0 = ldo(px.psiH[0] + r, osxmc);
+                q.qm1 = ldo(px.psiH[1] + r, osxmc);
+                q.qe0 = ldo(px.psiE[0] + r, osxc);
+                q.qe1 = ldo(px.psiE[1] + r, osxc);
+            }
+        }
+        return q;
+    };
 
     __shared__ S sh;
+    // CPML: the slab coefficients (bh, ch, kh, bn, cn, kn), read once per block (loads of them in the
+    // loop would wait for the tile loads in flight): x slabs of the lane's column and column x-1
+    // (bh, ch, kh), y slabs of the wavefront's row and row y-1 (bh, ch, kh), z slabs of the block's
+    // planes k0-2 .. k1 (entry t: plane k0-2+t)
+    __shared__ T xcf[PML ? 9 : 1][kTileX];
+    __shared__ T ycf[PML ? 9 : 1][TY];
+    __shared__ T zcf[PML ? 6 : 1][TZ + 3];
+    if constexpr (PML) {
+        if (lane == 0 && py.on) {
+            ycf[0][row] = py.bh[jw];
+            ycf[1][row] = py.ch[jw];
+            ycf[2][row] = py.kh[jw];
+            ycf[3][row] = py.bn[jw];
+            ycf[4][row] = py.cn[jw];
+            ycf[5][row] = py.kn[jw];
+            ycf[6][row] = py.bh[jmw];
+            ycf[7][row] = py.ch[jmw];
+            ycf[8][row] = py.kh[jmw];
+        }
+        if (row == 1 % TY && pz.on && lane < TZ + 3) {
+            const int kk = wrap_index(k0 - 2 + lane, nz);
+            zcf[0][lane] = pz.bh[kk];
+            zcf[1][lane] = pz.ch[kk];
+            zcf[2][lane] = pz.kh[kk];
+            zcf[3][lane] = pz.bn[kk];
+            zcf[4][lane] = pz.cn[kk];
+            zcf[5][lane] = pz.kn[kk];
+        }
+        if (row == 0 && px.on) {
+            xcf[0][lane] = ldo(px.bh, oi);
+            xcf[1][lane] = ldo(px.ch, oi);
+            xcf[2][lane] = ldo(px.kh, oi);
+            xcf[3][lane] = ldo(px.bn, oi);
+            xcf[4][lane] = ldo(px.cn, oi);
+            xcf[5][lane] = ldo(px.kn, oi);
+            xcf[6][lane] = ldo(px.bh, oim);
+            xcf[7][lane] = ldo(px.ch, oim);
+            xcf[8][lane] = ldo(px.kh, oim);
+        }
+    }
     const int lxp = min(lane + 1, kTileX - 1), lxm = max(lane - 1, 0);
     const int ryp = min(row + 1, TY - 1), rym = max(row - 1, 0);
 
@@ -921,8 +1024,22 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
         const T exk = ldp(Ex, o00), eyk = ldp(Ey, o00), ez = ldp(Ez, o00);
         const T exk1 = ldp(a.E[0] + b, o00), eyk1 = ldp(a.E[1] + b, o00);
         const T ez_x = ldp(Ez, oxp), ez_y = ldp(Ez, oyp);
-        const T dyEz = (ez_y - ez) * rdy, dzEy = (eyk1 - eyk) * rdz;
-        const T dzEx = (exk1 - exk) * rdz, dxEz = (ez_x - ez) * rdx;
+        T dyEz = (ez_y - ez) * rdy, dzEy = (eyk1 - eyk) * rdz;
+        T dzEx = (exk1 - exk) * rdz, dxEz = (ez_x - ez) * rdx;
+        if constexpr (PML) {  // the stretching at plane k0-2, without storing (another tile does)
+            if (sx >= 0)
+                dxEz = stretch_virtual_o(dxEz, px.psiH[0] + ((long long)km0 * ny + jw) * px.P, osx, ldo(px.bh, oi),
+                                         ldo(px.ch, oi), ldo(px.kh, oi));
+            if (sy >= 0)
+                dyEz = stretch_virtual_o(dyEz, py.psiH[1] + ((long long)km0 * py.P + sy) * nx, oi, py.bh[jw], py.ch[jw],
+                                         py.kh[jw]);
+            const int sz = zslot(km0);
+            if (sz >= 0) {
+                const long long r = ((long long)sz * ny + jw) * nx;
+                dzEy = stretch_virtual_o(dzEy, pz.psiH[0] + r, oi, pz.bh[km0], pz.ch[km0], pz.kh[km0]);
+                dzEx = stretch_virtual_o(dzEx, pz.psiH[1] + r, oi, pz.bh[km0], pz.ch[km0], pz.kh[km0]);
+            }
+        }
         hx_km = ldp(a.H[0] + bm, o00) - hdt * (dyEz - dzEy);
         hy_km = ldp(a.H[1] + bm, o00) - hdt * (dzEx - dxEz);
     }
@@ -938,6 +1055,7 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
         jny = ldp(a.J[1] + b, o00);
         jnz = ldp(a.J[2] + b, o00);
     }
+    [[maybe_unused]] Psi psn = load_psi(kb);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
@@ -947,6 +1065,10 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
     T pjx = T(0), pjy = T(0), pjz = T(0);
     EdgeCoef<T> px_ = {T(0), T(0), T(0)}, py_ = px_, pz_ = px_;
     T qhx_km = T(0), qhy_km = T(0);
+    // CPML: the first step's new variables of the previous plane, H side (x, y, z axis, two each) and
+    // E side
+    [[maybe_unused]] T pax0 = T(0), pax1 = T(0), pay0 = T(0), pay1 = T(0), paz0 = T(0), paz1 = T(0);
+    [[maybe_unused]] T pbx0 = T(0), pbx1 = T(0), pby0 = T(0), pby1 = T(0), pbz0 = T(0), pbz1 = T(0);
     const int L = lane + 1, R = row + 1;  // the lane's column and row slots in the tiles
 
     for (int it = 0; it < nit; ++it) {
@@ -954,7 +1076,12 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
         const int kn = (kc + 1 == nz) ? 0 : kc + 1;
         // ---- stages A and B at plane kc (the fused sweep's periodic arithmetic)
         const EdgeCoef<T> qx = cx, qy = cy, qz = cz;
-        T jx = qx.cj > T(0) ? jnx : T(0), jy = qy.cj > T(0) ? jny : T(0), jz = qz.cj > T(0) ? jnz : T(0);
+        // Js^{n-1/2} as loaded (masked to 0 off the superconducting edges in stage B, where the
+        // coefficients are first needed: a test here would wait for their table loads at once)
+        T jx = jnx, jy = jny, jz = jnz;
+        // CPML: this plane's auxiliary variables, and the next plane's (issued before the six loads)
+        [[maybe_unused]] const Psi ps = psn;
+        if constexpr (PML) psn = load_psi(kn);
         // the next plane's Js and classes: exactly six loads, issued after every load the wait below
         // is for
         {
@@ -976,25 +1103,109 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
         const T hx = H0[0][R][L], hx_ym = H0[0][R - 1][L];
         const T hy = H0[1][R][L], hy_xm = H0[1][R][L - 1];
         const T hz = H0[2][R][L], hz_xm = H0[2][R][L - 1], hz_ym = H0[2][R - 1][L];
+        // nothing of the arithmetic below moves above the tile reads: a test of this plane's edge
+        // coefficients scheduled next to their table loads would wait for them at once
+        __builtin_amdgcn_sched_barrier(0);
 
-        const T nhx = hx - hdt * ((ez_yp - ez) * rdy - (ey1 - ey0) * rdz);
-        const T nhy = hy - hdt * ((ex1 - ex0) * rdz - (ez_xp - ez) * rdx);
-        const T nhz = hz - hdt * ((ey_xp - ey0) * rdx - (ex_yp - ex0) * rdy);
-        const T nhz_xm = hz_xm - hdt * ((ey0 - ey_xm) * rdx - (exm_yp - exm) * rdy);
-        const T nhy_xm = hy_xm - hdt * ((exm1 - exm) * rdz - (ez - ez_xm) * rdx);
-        const T nhz_ym = hz_ym - hdt * ((eym_xp - eym) * rdx - (ex0 - ex_ym) * rdy);
-        const T nhx_ym = hx_ym - hdt * ((ez - ez_ym) * rdy - (eym1 - eym) * rdz);
+        T nhx, nhy, nhz, nhz_xm, nhy_xm, nhz_ym, nhx_ym;
+        [[maybe_unused]] T ax0 = T(0), ax1 = T(0), ay0 = T(0), ay1 = T(0), az0 = T(0), az1 = T(0);
+        [[maybe_unused]] T bx0 = T(0), bx1 = T(0), by0 = T(0), by1 = T(0), bz0 = T(0), bz1 = T(0);
+        [[maybe_unused]] const int szc = zslot(kc);
+        if constexpr (!PML) {
+            nhx = hx - hdt * ((ez_yp - ez) * rdy - (ey1 - ey0) * rdz);
+            nhy = hy - hdt * ((ex1 - ex0) * rdz - (ez_xp - ez) * rdx);
+            nhz = hz - hdt * ((ey_xp - ey0) * rdx - (ex_yp - ex0) * rdy);
+            nhz_xm = hz_xm - hdt * ((ey0 - ey_xm) * rdx - (exm_yp - exm) * rdy);
+            nhy_xm = hy_xm - hdt * ((exm1 - exm) * rdz - (ez - ez_xm) * rdx);
+            nhz_ym = hz_ym - hdt * ((eym_xp - eym) * rdx - (ex0 - ex_ym) * rdy);
+            nhx_ym = hx_ym - hdt * ((ez - ez_ym) * rdy - (eym1 - eym) * rdz);
+        } else {  // the fused sweep's CPML arithmetic; the lane's own new variables are kept (a*)
+            T dyEz = (ez_yp - ez) * rdy, dzEy = (ey1 - ey0) * rdz;              // Hx
+            T dzEx = (ex1 - ex0) * rdz, dxEz = (ez_xp - ez) * rdx;              // Hy
+            T dxEy = (ey_xp - ey0) * rdx, dyEx = (ex_yp - ex0) * rdy;           // Hz
+            T dxEy_xm = (ey0 - ey_xm) * rdx, dyEx_xm = (exm_yp - exm) * rdy;    // Hz at x-1
+            T dzEx_xm = (exm1 - exm) * rdz, dxEz_xm = (ez - ez_xm) * rdx;       // Hy at x-1
+            T dxEy_ym = (eym_xp - eym) * rdx, dyEx_ym = (ex0 - ex_ym) * rdy;    // Hz at y-1
+            T dyEz_ym = (ez - ez_ym) * rdy, dzEy_ym = (eym1 - eym) * rdz;       // Hx at y-1
+            const long long rx = ((long long)kc * ny + jw) * px.P, rxm = ((long long)kc * ny + jmw) * px.P;
+            if (sx >= 0) {
+                const T bh = xcf[0][lane], ch = xcf[1][lane], kh = xcf[2][lane];
+                T pv;
+                dxEz = stretch_v(dxEz, XPRE ? ps.qh0 : ldo(px.psiH[0] + rx, osx), bh, ch, kh, ax0);
+                dxEy = stretch_v(dxEy, XPRE ? ps.qh1 : ldo(px.psiH[1] + rx, osx), bh, ch, kh, ax1);
+                dxEy_ym = stretch_v(dxEy_ym, XPRE ? ps.qh1ym : ldo(px.psiH[1] + rxm, osx), bh, ch, kh, pv);
+            }
+            if (sxm >= 0) {
+                const T bh = xcf[6][lane], ch = xcf[7][lane], kh = xcf[8][lane];
+                T pv;
+                dxEy_xm = stretch_v(dxEy_xm, XPRE ? ps.qm1 : ldo(px.psiH[1] + rx, osxm), bh, ch, kh, pv);
+                dxEz_xm = stretch_v(dxEz_xm, XPRE ? ps.qm0 : ldo(px.psiH[0] + rx, osxm), bh, ch, kh, pv);
+            }
+            if (sy >= 0) {
+                const long long r = ((long long)kc * py.P + sy) * nx;
+                const T bh = ycf[0][row], ch = ycf[1][row], kh = ycf[2][row];
+                dyEx = stretch_v(dyEx, ldo(py.psiH[0] + r, oi), bh, ch, kh, ay0);
+                dyEz = stretch_v(dyEz, ldo(py.psiH[1] + r, oi), bh, ch, kh, ay1);
+                dyEx_xm = stretch_virtual_o(dyEx_xm, py.psiH[0] + r, oim, bh, ch, kh);
+            }
+            if (sym >= 0) {
+                const long long r = ((long long)kc * py.P + sym) * nx;
+                const T bh = ycf[6][row], ch = ycf[7][row], kh = ycf[8][row];
+                dyEx_ym = stretch_virtual_o(dyEx_ym, py.psiH[0] + r, oi, bh, ch, kh);
+                dyEz_ym = stretch_virtual_o(dyEz_ym, py.psiH[1] + r, oi, bh, ch, kh);
+            }
+            if (szc >= 0) {
+                const T bh = zcf[0][it + 1], ch = zcf[1][it + 1], kh = zcf[2][it + 1];
+                T pv;
+                dzEy = stretch_v(dzEy, ps.zh0, bh, ch, kh, az0);
+                dzEx = stretch_v(dzEx, ps.zh1, bh, ch, kh, az1);
+                dzEx_xm = stretch_v(dzEx_xm, ps.zh1xm, bh, ch, kh, pv);
+                dzEy_ym = stretch_v(dzEy_ym, ps.zh0ym, bh, ch, kh, pv);
+            }
+            nhx = hx - hdt * (dyEz - dzEy);
+            nhy = hy - hdt * (dzEx - dxEz);
+            nhz = hz - hdt * (dxEy - dyEx);
+            nhz_xm = hz_xm - hdt * (dxEy_xm - dyEx_xm);
+            nhy_xm = hy_xm - hdt * (dzEx_xm - dxEz_xm);
+            nhz_ym = hz_ym - hdt * (dxEy_ym - dyEx_ym);
+            nhx_ym = hx_ym - hdt * (dyEz_ym - dzEy_ym);
+        }
         T ex_n, ey_n, ez_n;  // E^{n+1} at plane kc
         {
-            const T dyHz = (nhz - nhz_ym) * rdy, dzHy = (nhy - hy_km) * rdz;
-            const T dzHx = (nhx - hx_km) * rdz, dxHz = (nhz - nhz_xm) * rdx;
-            const T dxHy = (nhy - nhy_xm) * rdx, dyHx = (nhx - nhx_ym) * rdy;
-            if (qx.cj > T(0)) jx = jx + qx.cj * ex0;
-            if (qy.cj > T(0)) jy = jy + qy.cj * ey0;
-            if (qz.cj > T(0)) jz = jz + qz.cj * ez;
+            T dyHz = (nhz - nhz_ym) * rdy, dzHy = (nhy - hy_km) * rdz;
+            T dzHx = (nhx - hx_km) * rdz, dxHz = (nhz - nhz_xm) * rdx;
+            T dxHy = (nhy - nhy_xm) * rdx, dyHx = (nhx - nhx_ym) * rdy;
+            if constexpr (PML) {  // E-side variables of the lane's own cell (new values kept: b*)
+                if (sx >= 0) {
+                    const long long r = ((long long)kc * ny + jw) * px.P;
+                    const T bn = xcf[3][lane], cn = xcf[4][lane], kn = xcf[5][lane];
+                    dxHz = stretch_v(dxHz, XPRE ? ps.qe0 : ldo(px.psiE[0] + r, osx), bn, cn, kn, bx0);  // Ey
+                    dxHy = stretch_v(dxHy, XPRE ? ps.qe1 : ldo(px.psiE[1] + r, osx), bn, cn, kn, bx1);  // Ez
+                }
+                if (sy >= 0) {
+                    const long long r = ((long long)kc * py.P + sy) * nx;
+                    const T bn = ycf[3][row], cn = ycf[4][row], kn = ycf[5][row];
+                    dyHx = stretch_v(dyHx, ldo(py.psiE[0] + r, oi), bn, cn, kn, by0);  // Ez
+                    dyHz = stretch_v(dyHz, ldo(py.psiE[1] + r, oi), bn, cn, kn, by1);  // Ex
+                }
+                if (szc >= 0) {
+                    const T bn = zcf[3][it + 1], cn = zcf[4][it + 1], kn = zcf[5][it + 1];
+                    dzHy = stretch_v(dzHy, ps.ze0, bn, cn, kn, bz0);  // Ex
+                    dzHx = stretch_v(dzHx, ps.ze1, bn, cn, kn, bz1);  // Ey
+                }
+            }
+            jx = qx.cj > T(0) ? jx + qx.cj * ex0 : T(0);
+            jy = qy.cj > T(0) ? jy + qy.cj * ey0 : T(0);
+            jz = qz.cj > T(0) ? jz + qz.cj * ez : T(0);
             ex_n = qx.ca * ex0 + qx.cb * ((dyHz - dzHy) - jx);
             ey_n = qy.ca * ey0 + qy.cb * ((dzHx - dxHz) - jy);
             ez_n = qz.ca * ez + qz.cb * ((dxHy - dyHx) - jz);
+            if constexpr (PML) {  // tangential E on the PEC walls
+                const bool wall_z = pz.on && kc == 0;
+                ex_n = (wall_y || wall_z) ? T(0) : ex_n;
+                ey_n = (wall_z || wall_x) ? T(0) : ey_n;
+                ez_n = (wall_x || wall_y) ? T(0) : ez_n;
+            }
             if (SIDE && (uint32_t)side != 0) {  // the first step's sources, on every lane (the halo lanes' copies too)
                 ex_n = add_sources(a.side, a.side.sg, side, 0, i, j, kc, ex_n);
                 ey_n = add_sources(a.side, a.side.sg, side, 1, i, j, kc, ey_n);
@@ -1017,13 +1228,40 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
 
         // ---- stage C: H^{n+3/2} at plane kc - 1 (the fused sweep's H arithmetic on E^{n+1})
         T h2x = T(0), h2y = T(0), h2z = T(0);
+        const int kw = (kc == 0) ? nz - 1 : kc - 1;
+        [[maybe_unused]] const int szw = zslot(kw);
+        [[maybe_unused]] T cx0 = T(0), cx1 = T(0), cy0 = T(0), cy1 = T(0), cz0 = T(0), cz1 = T(0);
         if (it >= 1) {
             const int pb = buf ^ 1;
             const T ez1_yp = sh.e1[pb][2][ryp][lane], ex1_yp = sh.e1[pb][0][ryp][lane];
             const T ey1_xp = sh.e1[pb][1][row][lxp], ez1_xp = sh.e1[pb][2][row][lxp];
-            h2x = phx - hdt * ((ez1_yp - pez) * rdy - (ey_n - pey) * rdz);
-            h2y = phy - hdt * ((ex_n - pex) * rdz - (ez1_xp - pez) * rdx);
-            h2z = phz - hdt * ((ey1_xp - pey) * rdx - (ex1_yp - pex) * rdy);
+            if constexpr (!PML) {
+                h2x = phx - hdt * ((ez1_yp - pez) * rdy - (ey_n - pey) * rdz);
+                h2y = phy - hdt * ((ex_n - pex) * rdz - (ez1_xp - pez) * rdx);
+                h2z = phz - hdt * ((ey1_xp - pey) * rdx - (ex1_yp - pex) * rdy);
+            } else {  // stretched with the first step's new variables (c*: the second step's)
+                T dyEz = (ez1_yp - pez) * rdy, dzEy = (ey_n - pey) * rdz;  // Hx
+                T dzEx = (ex_n - pex) * rdz, dxEz = (ez1_xp - pez) * rdx;  // Hy
+                T dxEy = (ey1_xp - pey) * rdx, dyEx = (ex1_yp - pex) * rdy;  // Hz
+                if (sx >= 0) {
+                    const T bh = xcf[0][lane], ch = xcf[1][lane], kh = xcf[2][lane];
+                    dxEz = stretch_v(dxEz, pax0, bh, ch, kh, cx0);
+                    dxEy = stretch_v(dxEy, pax1, bh, ch, kh, cx1);
+                }
+                if (sy >= 0) {
+                    const T bh = ycf[0][row], ch = ycf[1][row], kh = ycf[2][row];
+                    dyEx = stretch_v(dyEx, pay0, bh, ch, kh, cy0);
+                    dyEz = stretch_v(dyEz, pay1, bh, ch, kh, cy1);
+                }
+                if (szw >= 0) {
+                    const T bh = zcf[0][it], ch = zcf[1][it], kh = zcf[2][it];
+                    dzEy = stretch_v(dzEy, paz0, bh, ch, kh, cz0);
+                    dzEx = stretch_v(dzEx, paz1, bh, ch, kh, cz1);
+                }
+                h2x = phx - hdt * (dyEz - dzEy);
+                h2y = phy - hdt * (dzEx - dxEz);
+                h2z = phz - hdt * (dxEy - dyEx);
+            }
             sh.h2[0][row][lane] = h2x;
             sh.h2[1][row][lane] = h2y;
             sh.h2[2][row][lane] = h2z;
@@ -1034,9 +1272,27 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
         if (it >= 2) {
             const T h2z_xm = sh.h2[2][row][lxm], h2y_xm = sh.h2[1][row][lxm];
             const T h2z_ym = sh.h2[2][rym][lane], h2x_ym = sh.h2[0][rym][lane];
-            const T dyHz = (h2z - h2z_ym) * rdy, dzHy = (h2y - qhy_km) * rdz;
-            const T dzHx = (h2x - qhx_km) * rdz, dxHz = (h2z - h2z_xm) * rdx;
-            const T dxHy = (h2y - h2y_xm) * rdx, dyHx = (h2x - h2x_ym) * rdy;
+            T dyHz = (h2z - h2z_ym) * rdy, dzHy = (h2y - qhy_km) * rdz;
+            T dzHx = (h2x - qhx_km) * rdz, dxHz = (h2z - h2z_xm) * rdx;
+            T dxHy = (h2y - h2y_xm) * rdx, dyHx = (h2x - h2x_ym) * rdy;
+            [[maybe_unused]] T dx0 = T(0), dx1 = T(0), dy0 = T(0), dy1 = T(0), dz0 = T(0), dz1 = T(0);
+            if constexpr (PML) {  // the second step's E-side variables (d*)
+                if (sx >= 0) {
+                    const T bn = xcf[3][lane], cn = xcf[4][lane], kn = xcf[5][lane];
+                    dxHz = stretch_v(dxHz, pbx0, bn, cn, kn, dx0);
+                    dxHy = stretch_v(dxHy, pbx1, bn, cn, kn, dx1);
+                }
+                if (sy >= 0) {
+                    const T bn = ycf[3][row], cn = ycf[4][row], kn = ycf[5][row];
+                    dyHx = stretch_v(dyHx, pby0, bn, cn, kn, dy0);
+                    dyHz = stretch_v(dyHz, pby1, bn, cn, kn, dy1);
+                }
+                if (szw >= 0) {
+                    const T bn = zcf[3][it], cn = zcf[4][it], kn = zcf[5][it];
+                    dzHy = stretch_v(dzHy, pbz0, bn, cn, kn, dz0);
+                    dzHx = stretch_v(dzHx, pbz1, bn, cn, kn, dz1);
+                }
+            }
             T j2x = pjx, j2y = pjy, j2z = pjz;
             if (px_.cj > T(0)) j2x = j2x + px_.cj * pex;
             if (py_.cj > T(0)) j2y = j2y + py_.cj * pey;
@@ -1044,7 +1300,12 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
             T e2x = px_.ca * pex + px_.cb * ((dyHz - dzHy) - j2x);
             T e2y = py_.ca * pey + py_.cb * ((dzHx - dxHz) - j2y);
             T e2z = pz_.ca * pez + pz_.cb * ((dxHy - dyHx) - j2z);
-            const int kw = (kc == 0) ? nz - 1 : kc - 1;
+            if constexpr (PML) {  // tangential E on the PEC walls
+                const bool wall_z = pz.on && kw == 0;
+                e2x = (wall_y || wall_z) ? T(0) : e2x;
+                e2y = (wall_z || wall_x) ? T(0) : e2y;
+                e2z = (wall_x || wall_y) ? T(0) : e2z;
+            }
             if (SIDE && (uint32_t)side != 0) {  // the second step's sources
                 e2x = add_sources(a.side, a.side.sg2, side, 0, i, j, kw, e2x);
                 e2y = add_sources(a.side, a.side.sg2, side, 1, i, j, kw, e2y);
@@ -1061,6 +1322,29 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
                 if (px_.cj > T(0)) stp(a.Jout[0] + bw, o00, j2x);
                 if (py_.cj > T(0)) stp(a.Jout[1] + bw, o00, j2y);
                 if (pz_.cj > T(0)) stp(a.Jout[2] + bw, o00, j2z);
+                if constexpr (PML) {  // the second step's auxiliary variables, to the other set
+                    if (sx >= 0) {
+                        const long long r = ((long long)kw * ny + jw) * px.P;
+                        sto(px.psiHo[0] + r, osx, cx0);
+                        sto(px.psiHo[1] + r, osx, cx1);
+                        sto(px.psiEo[0] + r, osx, dx0);
+                        sto(px.psiEo[1] + r, osx, dx1);
+                    }
+                    if (sy >= 0) {
+                        const long long r = ((long long)kw * py.P + sy) * nx;
+                        sto(py.psiHo[0] + r, oi, cy0);
+                        sto(py.psiHo[1] + r, oi, cy1);
+                        sto(py.psiEo[0] + r, oi, dy0);
+                        sto(py.psiEo[1] + r, oi, dy1);
+                    }
+                    if (szw >= 0) {
+                        const long long r = ((long long)szw * ny + jw) * nx;
+                        sto(pz.psiHo[0] + r, oi, cz0);
+                        sto(pz.psiHo[1] + r, oi, cz1);
+                        sto(pz.psiEo[0] + r, oi, dz0);
+                        sto(pz.psiEo[1] + r, oi, dz1);
+                    }
+                }
                 if (SIDE && (side >> 32) != 0) {  // both steps' probe copies: E^{n+1} and E^{n+2}
                     probe_copy(a.side, a.side.pcopy, side, 0, i, j, kw, pex);
                     probe_copy(a.side, a.side.pcopy, side, 1, i, j, kw, pey);
@@ -1088,6 +1372,10 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
         pz_ = qz;
         hx_km = nhx;
         hy_km = nhy;
+        if constexpr (PML) {
+            pax0 = ax0; pax1 = ax1; pay0 = ay0; pay1 = ay1; paz0 = az0; paz1 = az1;
+            pbx0 = bx0; pbx1 = bx1; pby0 = by0; pby1 = by1; pbz0 = bz0; pbz1 = bz1;
+        }
         coefs(mn);
     }
 }
@@ -1603,7 +1891,7 @@ struct TwoStepTiles<float> {
     static constexpr int ty = 16;
 };
 
-template <typename T, int TY, bool NT, bool SIDE>
+template <typename T, int TY, bool NT, bool SIDE, bool PML>
 static void launch_two_step_nt(const StepArgs<T> &a, hipStream_t s)
 {
     constexpr int OX = kTwoStepOX, OY = TY - 2;
@@ -1615,32 +1903,45 @@ static void launch_two_step_nt(const StepArgs<T> &a, hipStream_t s)
     const dim3 blk(kTileX, TY);
     const unsigned grd = (unsigned)(cols * ((a.g.nz + tz - 1) / tz));
     switch (tz) {
-    case 32: hipLaunchKernelGGL((two_step_kernel<T, TY, 32, NT, SIDE>), dim3(grd), blk, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((two_step_kernel<T, TY, 16, NT, SIDE>), dim3(grd), blk, 0, s, a); break;
-    default: hipLaunchKernelGGL((two_step_kernel<T, TY, 8, NT, SIDE>), dim3(grd), blk, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((two_step_kernel<T, TY, 32, NT, SIDE, PML>), dim3(grd), blk, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((two_step_kernel<T, TY, 16, NT, SIDE, PML>), dim3(grd), blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((two_step_kernel<T, TY, 8, NT, SIDE, PML>), dim3(grd), blk, 0, s, a); break;
+    }
+}
+
+template <typename T, int TY, bool PML>
+static void launch_two_step_tiles(const StepArgs<T> &a, hipStream_t s)
+{
+    const double touched = (double)a.g.sxy * a.g.nz * (15.0 * sizeof(T) + 6.0);
+    const bool nt = touched > 512.0 * 1024 * 1024;
+    if (a.side.nsrc > 0 || a.side.nprobe > 0 || a.side.nred > 0) {
+        if (nt) launch_two_step_nt<T, TY, true, true, PML>(a, s);
+        else launch_two_step_nt<T, TY, false, true, PML>(a, s);
+    } else {
+        if (nt) launch_two_step_nt<T, TY, true, false, PML>(a, s);
+        else launch_two_step_nt<T, TY, false, false, PML>(a, s);
     }
 }
 
 template <typename T>
 hipError_t launch_two_step(const StepArgs<T> &a, hipStream_t s)
 {
-    constexpr int TY = TwoStepTiles<T>::ty;
-    const double touched = (double)a.g.sxy * a.g.nz * (15.0 * sizeof(T) + 6.0);
-    const bool nt = touched > 512.0 * 1024 * 1024;
-    if (a.side.nsrc > 0 || a.side.nprobe > 0 || a.side.nred > 0) {
-        if (nt) launch_two_step_nt<T, TY, true, true>(a, s);
-        else launch_two_step_nt<T, TY, false, true>(a, s);
-    } else {
-        if (nt) launch_two_step_nt<T, TY, true, false>(a, s);
-        else launch_two_step_nt<T, TY, false, false>(a, s);
-    }
+    // CPML grids: footprints of eight rows in both precisions (the first step's auxiliary variables
+    // ride in registers, which sixteen FP32 wavefronts per block do not leave)
+    if (a.pml[0].on || a.pml[1].on || a.pml[2].on) launch_two_step_tiles<T, 8, true>(a, s);
+    else launch_two_step_tiles<T, TwoStepTiles<T>::ty, false>(a, s);
     return hipGetLastError();
 }
 
 template <typename T>
 bool two_step_pays(const StepArgs<T> &a)
 {
-    if (a.pml[0].on || a.pml[1].on || a.pml[2].on || !a.cls[0]) return false;
+    if (!a.cls[0]) return false;
+    // CPML grids in FP32: the first step's auxiliary variables leave room for footprints of 8 rows,
+    // one block per CU (8 wavefronts instead of 16); fused / two-step ms per step: 512 x 256 x 128
+    // with x and z slabs 0.316 / 0.359, the paper's CPW 4.83 / 4.64.  In FP64 (8 wavefronts per CU
+    // either way) 0.631 / 0.557 and 9.01 / 8.16.
+    if ((a.pml[0].on || a.pml[1].on || a.pml[2].on) && sizeof(T) == 4) return false;
     // The footprints' overlap costs (64/60)(TY/(TY-2)) in cells computed, repaid once the grid's
     // traffic no longer stays in the 256 MB infinity cache.  Measured, ms per step fused / two-step:
     // 128^3 FP32 0.027 / 0.031, FP64 0.050 / 0.070; 160^3 FP32 0.069 / 0.053, FP64 0.172 / 0.114;

@@ -40,6 +40,7 @@ struct PmlAxis {
     T *psiH[2];             // H-side variables (two components)
     T *psiE[2];             // E-side variables (two components)
     T *psiHo[2];            // where the fused sweep writes the new H-side variables (psiH elsewhere)
+    T *psiEo[2];            // where the two-step sweep writes the new E-side variables (psiE elsewhere)
 };
 
 struct ProbeDesc;

@@ -138,8 +138,8 @@ def test_buffer_sizes_and_call_order(L):
 
 
 def test_fused_buffer_layout(L):
-    """9 padded fields (E, H, Js); with a CPML axis also a second set of that axis's two H-side
-    variables (y slabs: nz x (lo + hi) x nx each), padded to 256 bytes."""
+    """9 padded fields (E, H, Js); with a CPML axis also a second set of that axis's four auxiliary
+    variables (two H-side, two E-side; y slabs: nz x (lo + hi) x nx each), padded to 256 bytes."""
     c = good_config(L)
     rc, h = create(L, c)
     assert rc == 0
@@ -155,7 +155,7 @@ def test_fused_buffer_layout(L):
     rc, h = create(L, c)
     assert rc == 0
     assert L.lib().tfl_fused_buffer_bytes(h, ctypes.byref(b)) == 0
-    assert b.value == 9 * field + (2 * 8 * 5 * 20 * 8 + 255) // 256 * 256
+    assert b.value == 9 * field + (4 * 8 * 5 * 20 * 8 + 255) // 256 * 256
     assert L.lib().tfl_bind_fused_buffer(h, ctypes.c_void_p(0x1010)) == L.TFL_E_INVAL
     assert L.lib().tfl_bind_fused_buffer(h, None) == 0
     L.lib().tfl_destroy(h)
@@ -167,7 +167,7 @@ def test_fused_buffer_layout(L):
     assert rc == 0
     assert L.lib().tfl_fused_buffer_bytes(h, ctypes.byref(b)) == 0
     r256 = lambda n: (n + 255) // 256 * 256
-    assert b.value == 9 * field + r256(2 * 8 * 10 * 5 * 8) + r256(2 * 8 * 5 * 20 * 8) + r256(2 * 3 * 10 * 20 * 8)
+    assert b.value == 9 * field + r256(4 * 8 * 10 * 5 * 8) + r256(4 * 8 * 5 * 20 * 8) + r256(4 * 3 * 10 * 20 * 8)
     L.lib().tfl_destroy(h)
 
 

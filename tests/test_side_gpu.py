@@ -87,15 +87,17 @@ def test_folded_probes_equal_probe_launches(dtype, sweep):
         assert v <= tol, (k, v)
 
 
+@pytest.mark.parametrize("pml", [(None, None, None), ((5, 4), None, (3, 6))])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_folded_probes_two_step(dtype):
+def test_folded_probes_two_step(dtype, pml):
     """On a periodic grid with edge classes the two-step sweep copies both steps' E on the probe
     boxes, and the next sweep (two-step, fused or the E pass) records both samples: the series and
     DFTs equal those of probe launches after every step (five probes), and the fields those of the
     fused sweep, with the steps in one call (four two-step launches, then the two passes) and split
-    over calls of 1, 6 and 10 steps (two-step launches followed by fused sweeps)."""
+    over calls of 1, 6 and 10 steps (two-step launches followed by fused sweeps); periodic and with
+    CPML slabs."""
     shape = (130, 33, 20)
-    wl = workloads.random_medium(shape, seed=23)
+    wl = workloads.random_medium(shape, seed=23, pml=pml)
     wl["maps"] = workloads.roofline_grid(shape)["maps"]  # few distinct materials: edge classes bind
     wl["fields"] = (wl["fields"][0], wl["fields"][1], None)
     npdt = np.float64 if dtype == torch.float64 else np.float32
@@ -111,7 +113,7 @@ def test_folded_probes_two_step(dtype):
                     dict(comp=2, box=(0, 130, 0, 33, 10, 11)),
                     dict(comp=1, box=(60, 61, 0, 33, 5, 15), freqs=(1e14,))]
     steps = 17
-    print(f"case: two-step folded probes, {shape}, dtype={dtype}, steps={steps}", flush=True)
+    print(f"case: two-step folded probes, {shape}, pml={pml}, dtype={dtype}, steps={steps}", flush=True)
     a = run(wl, steps, dtype, "two_step")
     assert tuple(a[4]) == (1, 0, 16), a[4]
     five = dict(wl, probes=wl["probes"] + [dict(comp=2, box=(3, 4, 3, 4, 3, 4))])

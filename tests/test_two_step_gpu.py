@@ -1,7 +1,7 @@
-"""The two-step sweep (two time steps per sweep on periodic grids with edge classes) gives the fields
-and currents of the fused sweep bit for bit: footprints that do not tile the grid (ragged x, y and z
-ranges, grids narrower than a footprint), odd remainders after the four-step groups, both storage
-types; and it matches the FP64 oracle."""
+"""The two-step sweep (two time steps per sweep on grids with edge classes) gives the fields and
+currents of the fused sweep bit for bit: footprints that do not tile the grid (ragged x, y and z
+ranges, grids narrower than a footprint), odd remainders after the four-step groups, CPML slabs and
+PEC walls on any axes, both storage types; and it matches the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -57,7 +57,7 @@ def test_two_step_is_automatic_on_large_periodic_grids():
     """The default policy takes the two-step sweep on a periodic grid with classes past the infinity
     cache (here 3.3 M cells), in both precisions, the fused sweep on a smaller one, still with soft
     sources and probes (which ride along with both steps), and not where the probes' copies of two
-    steps do not fit the scratch copy space."""
+    steps do not fit the scratch copy space; on CPML grids in FP64 only."""
     from paper_2305_13419_amd import Simulation
     small = workloads.roofline_grid((128, 128, 128))
     for dtype in (torch.float32, torch.float64):
@@ -84,6 +84,14 @@ def test_two_step_is_automatic_on_large_periodic_grids():
         sim.add_probe(1, (0, 160, 0, 160, 7, 10), 0)  # 76 800 values: two copies exceed a half
         sim.step(10)
         assert sim.sweep_counts() == (0, 10, 0)
+        sim.close()
+    # CPML grids: the two-step sweep in FP64, the fused sweep in FP32
+    for dtype, expect in ((torch.float32, (0, 10, 0)), (torch.float64, (0, 2, 8))):
+        sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, (None, (4, 4), (8, 8)))
+        sim.set_materials(*wl["maps"])
+        sim.set_fields(E, H)
+        sim.step(10)
+        assert sim.sweep_counts() == expect, (dtype, sim.sweep_counts())
         sim.close()
 
 
@@ -150,3 +158,61 @@ def test_two_step_with_sources(dtype):
     r = compare(g, o)
     print(f"two-step with sources {dtype} vs oracle, 11 steps: {r}", flush=True)
     assert max(r.values()) <= (1e-12 if dtype == torch.float64 else 1e-5)
+
+
+CPML_CASES = [
+    ((130, 33, 40), ((5, 4), None, (3, 6))),
+    ((200, 50, 40), (None, (4, 4), None)),
+    ((62, 10, 20), ((3, 3), (2, 2), (4, 4))),
+    ((256, 64, 32), ((8, 8), None, (8, 8))),
+    ((70, 40, 24), ((2, 7), (6, 1), None)),
+]
+
+
+def cpml_workload(shape, pml, seed=29):
+    wl = workloads.random_medium(shape, seed=seed, pml=pml)
+    wl["maps"] = workloads.roofline_grid(shape)["maps"]  # few distinct materials: edge classes bind
+    wl["fields"] = (wl["fields"][0], wl["fields"][1], None)
+    return wl
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape,pml", CPML_CASES)
+def test_two_step_cpml_equals_fused(shape, pml, dtype):
+    """CPML slabs (x-slab columns inside and across footprints, y-slab rows, z-slab planes, slabs on
+    every axis of a grid narrower than a footprint) and the PEC walls at their node planes: the
+    two-step sweep carries the first step's auxiliary variables in registers and writes the second
+    step's to the other set, with the fused sweep's arithmetic."""
+    wl = cpml_workload(shape, pml)
+    print(f"case: two-step vs fused with CPML, {shape}, pml={pml}, {dtype}, chunks 8, 3", flush=True)
+    a, ca, sa = run(wl, 11, dtype, "two_step", [8, 3])
+    b, cb, sb = run(wl, 11, dtype, "fused", [8, 3])
+    assert ca[2] == 8 and cb[2] == 0, (ca, cb)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    sa.close()
+    sb.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_two_step_cpml_matches_oracle(dtype, tol):
+    wl = cpml_workload((130, 33, 40), ((5, 4), (3, 3), (3, 6)), seed=37)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    wl["fields"] = tuple(None if g is None else [np.asarray(a, dtype=npdt).astype(np.float64) for a in g]
+                         for g in wl["fields"])
+    wl["maps"] = tuple(np.asarray(m, dtype=npdt).astype(np.float64) for m in wl["maps"])
+    wl["sources"] = [dict(comp=1, box=(20, 21, 0, 33, 5, 35), amplitude=1.0, waveform="mod_gauss", freq=3e14,
+                          t0=2e-15, tw=8e-16)]
+    steps = 16
+    print(f"case: two-step with CPML vs oracle, {dtype}, {steps} steps", flush=True)
+    a, counts, sim = run(wl, steps, dtype, "two_step")
+    assert counts[2] == 16
+    Eg, Hg, Jg = sim.integer_time_fields()
+    torch.cuda.synchronize()
+    g = ([t.double().cpu().numpy() for t in Eg], [t.double().cpu().numpy() for t in Hg],
+         [t.double().cpu().numpy() for t in Jg], [])
+    sim.close()
+    o = run_oracle(wl, steps)
+    r = compare(g, o)
+    print(f"two-step with CPML {dtype} vs oracle, {steps} steps: {r}", flush=True)
+    assert max(r.values()) <= tol
