@@ -178,8 +178,10 @@ int tfl_bind_fused_buffer(tfl_sim *sim, void *buffer);
  *  TFL_SWEEP_AUTO      (default) the two-step sweep where it applies and pays
  *                      (grids of at least 3 * 2^20 cells, past the GPU's
  *                      infinity cache, nx >= 64, ny >= 32, nz >= 16; on
- *                      CPML grids in FP64 only), else the fused sweep where
- *                      a buffer is bound, else the two passes;
+ *                      CPML grids in FP64, and in FP32 where rows of 64
+ *                      cells leave a fifth of their lanes idle), else the
+ *                      fused sweep where a buffer is bound, else the two
+ *                      passes;
  *  TFL_SWEEP_TWO_PASS  always the H and E passes;
  *  TFL_SWEEP_FUSED     the fused sweep wherever a buffer is bound, no
  *                      two-step sweep;

@@ -18,12 +18,20 @@ static __device__ __forceinline__ int logical_block(int b, int nblocks)
 // wavefronts per row) and TZ planes along z.  Tiles are numbered x fastest,
 // then y, then z, and blocks are renumbered so that each XCD takes a contiguous
 // range: the blocks of one XCD sweep neighbouring columns of the same planes at
-// the same time.  With zmix (the fused and adjoint sweeps on grids with CPML
-// slabs along z) z is numbered before y: the slab planes cost more, and with z
-// last the XCDs would take one z range each, the two at the ends all the slab
-// planes (measured: 1-3 % faster for those sweeps on 16-cell z slabs, 2-5 %
-// slower for the two passes, which keep z last).  Returns false for lanes
+// the same time.  With zmix (the fused, two-step and adjoint sweeps on grids
+// whose CPML z slabs hold at least an eighth of the planes: zmix_of) z is
+// numbered before y: the slab planes cost more, and with z last the XCDs would
+// take one z range each, the two at the ends all the slab planes (measured on
+// 32 of 128 planes: 1-7 % faster for those sweeps; 2-5 % slower for the two
+// passes, which keep z last; on the paper's CPW, 32 of 1312 planes, 6 % slower,
+// y halo rows being shared less within an XCD).  Returns false for lanes
 // outside the grid.
+template <typename P>
+static __device__ __forceinline__ bool zmix_of(const P &pz, int nz)
+{
+    return pz.on && pz.P * 8 >= nz;
+}
+
 static __device__ __forceinline__ void tile_yz(int tr, int nty, int ntz, bool zmix, int &ty, int &tz)
 {
     if (zmix) {

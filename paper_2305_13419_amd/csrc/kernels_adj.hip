@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kTileX *TY) void adj_face_kernel(const AdjArgs<T> A
 {
     const int nx = A.f.g.nx, ny = A.f.g.ny, nz = A.f.g.nz;
     int i, j, k0, k1;
-    if (!tile_of<TY, TZ>(nx, ny, nz, i, j, k0, k1, A.f.pml[2].on)) return;
+    if (!tile_of<TY, TZ>(nx, ny, nz, i, j, k0, k1, zmix_of(A.f.pml[2], nz))) return;
     const long long sxy = A.f.g.sxy;
     const int ip = (i + 1 == nx) ? 0 : i + 1;
     const int jp = (j + 1 == ny) ? 0 : j + 1;
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kTileX *TY) void adj_edge_kernel(const AdjArgs<T> A
 {
     const int nx = A.f.g.nx, ny = A.f.g.ny, nz = A.f.g.nz;
     int i, j, k0, k1;
-    if (!tile_of<TY, TZ>(nx, ny, nz, i, j, k0, k1, A.f.pml[2].on)) return;
+    if (!tile_of<TY, TZ>(nx, ny, nz, i, j, k0, k1, zmix_of(A.f.pml[2], nz))) return;
     const long long sxy = A.f.g.sxy;
     const int im = (i == 0) ? nx - 1 : i - 1;
     const int jm = (j == 0) ? ny - 1 : j - 1;

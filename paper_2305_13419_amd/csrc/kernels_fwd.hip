@@ -397,7 +397,7 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
     side_reduce<T>(a.side);
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     int i, j, k0, k1;
-    if (!tile_of<TY, TZ, TX>(nx, ny, nz, i, j, k0, k1, PML && a.pml[2].on)) return;
+    if (!tile_of<TY, TZ, TX>(nx, ny, nz, i, j, k0, k1, PML && zmix_of(a.pml[2], nz))) return;
     const uint64_t side = side_mask(a.side, i, j, k0, k1);
     const long long sxy = a.g.sxy;
     const int im = (i == 0) ? nx - 1 : i - 1, ip = (i + 1 == nx) ? 0 : i + 1;
@@ -825,7 +825,7 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
     const int t = logical_block(blockIdx.x, ntx * nty * ntz);
     const int tx = t % ntx, tr = t / ntx;
     int ty, tz;
-    tile_yz(tr, nty, ntz, PML && a.pml[2].on, ty, tz);  // z-CPML grids: every XCD its share of the slab planes
+    tile_yz(tr, nty, ntz, PML && zmix_of(a.pml[2], nz), ty, tz);  // every XCD its share of the z-slab planes
     const int lane = threadIdx.x, row = threadIdx.y;
     const int wave = __builtin_amdgcn_readfirstlane(row);
     const int xo = tx * OX + lane - 2, yo = ty * OY + row - 1;  // the cell's output coordinates
@@ -1938,10 +1938,14 @@ bool two_step_pays(const StepArgs<T> &a)
 {
     if (!a.cls[0]) return false;
     // CPML grids in FP32: the first step's auxiliary variables leave room for footprints of 8 rows,
-    // one block per CU (8 wavefronts instead of 16); fused / two-step ms per step: 512 x 256 x 128
-    // with x and z slabs 0.316 / 0.359, the paper's CPW 4.83 / 4.64.  In FP64 (8 wavefronts per CU
-    // either way) 0.631 / 0.557 and 9.01 / 8.16.
-    if ((a.pml[0].on || a.pml[1].on || a.pml[2].on) && sizeof(T) == 4) return false;
+    // one block per CU (8 wavefronts instead of 16), which pays only where the fused sweep's rows of
+    // 64 cells leave a fifth or more of their lanes idle; fused / two-step ms per step: 512 x 256 x
+    // 128 with x and z slabs 0.316 / 0.351, the paper's CPW (nx = 146: 24 % idle) 4.58 / 4.18.  In
+    // FP64 (8 wavefronts per CU either way) 0.634 / 0.572 and 8.43 / 7.62.
+    if ((a.pml[0].on || a.pml[1].on || a.pml[2].on) && sizeof(T) == 4) {
+        const int lanes = (a.g.nx + 63) / 64 * 64;
+        if ((lanes - a.g.nx) * 5 < lanes) return false;
+    }
     // The footprints' overlap costs (64/60)(TY/(TY-2)) in cells computed, repaid once the grid's
     // traffic no longer stays in the 256 MB infinity cache.  Measured, ms per step fused / two-step:
     // 128^3 FP32 0.027 / 0.031, FP64 0.050 / 0.070; 160^3 FP32 0.069 / 0.053, FP64 0.172 / 0.114;

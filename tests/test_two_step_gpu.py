@@ -57,7 +57,8 @@ def test_two_step_is_automatic_on_large_periodic_grids():
     """The default policy takes the two-step sweep on a periodic grid with classes past the infinity
     cache (here 3.3 M cells), in both precisions, the fused sweep on a smaller one, still with soft
     sources and probes (which ride along with both steps), and not where the probes' copies of two
-    steps do not fit the scratch copy space; on CPML grids in FP64 only."""
+    steps do not fit the scratch copy space; on CPML grids in FP64, and in FP32 where the fused sweep's
+    rows leave many lanes idle."""
     from paper_2305_13419_amd import Simulation
     small = workloads.roofline_grid((128, 128, 128))
     for dtype in (torch.float32, torch.float64):
@@ -85,13 +86,16 @@ def test_two_step_is_automatic_on_large_periodic_grids():
         sim.step(10)
         assert sim.sweep_counts() == (0, 10, 0)
         sim.close()
-    # CPML grids: the two-step sweep in FP64, the fused sweep in FP32
-    for dtype, expect in ((torch.float32, (0, 10, 0)), (torch.float64, (0, 2, 8))):
-        sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, (None, (4, 4), (8, 8)))
-        sim.set_materials(*wl["maps"])
-        sim.set_fields(E, H)
+    # CPML grids: the two-step sweep in FP64; in FP32 only where 64-cell rows leave a fifth of their
+    # lanes idle (nx = 146: 46 of 192; nx = 160: 32 of 192)
+    narrow = workloads.roofline_grid((146, 160, 160))
+    for w, dtype, expect in ((wl, torch.float32, (0, 10, 0)), (wl, torch.float64, (0, 2, 8)),
+                             (narrow, torch.float32, (0, 2, 8))):
+        sim = Simulation(w["shape"], w["spacing"], w["dt"], w["theta"], dtype, (None, (4, 4), (8, 8)))
+        sim.set_materials(*w["maps"])
+        sim.set_fields(*w["fields"][:2])
         sim.step(10)
-        assert sim.sweep_counts() == expect, (dtype, sim.sweep_counts())
+        assert sim.sweep_counts() == expect, (w["shape"], dtype, sim.sweep_counts())
         sim.close()
 
 
