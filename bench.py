@@ -14,7 +14,8 @@ against its checkpointed forward run.  Prints one JSON line.
                                  # gradient over 512 steps (several minutes)
     python bench.py --table1     # the paper's skin-depth sweep, 12 rows (about 8 minutes)
     python bench.py --paper-cpw  # step rate on the paper's CPW resonator at its own size, 4 film cases
-    python bench.py --paper-cpw-q 1,2   # Q and f of film cases 1 and 2 at dz = 200 nm (~7 min per case)
+    python bench.py --paper-cpw-q 1,2   # Q and f of film cases 1 and 2 at dz = 200 nm (~6 min per case)
+    python bench.py --paper-cpw-q 1 --q-dz 100 --q-end 112   # dz = 100 nm to 112 ps (~15 min)
 """
 import argparse
 import hashlib
@@ -412,11 +413,12 @@ def paper_cpw_run(steps=200, warmup=10, cases=(1, 2, 3, 4), fused=True):
     return rows
 
 
-def paper_cpw_q_run(cases=(1, 2, 3, 4), dz=200e-9, t_end=134e-12, t_fit=80e-12):
-    """Q and resonance of the paper's CPW (Sec. 5, Table 7) at a coarser z resolution (dz = 200 nm, the
-    film one cell thick; the paper's 50 nm needs 850 000 steps of 196 M cells): FP32 fields, FP64 probe
-    series, run to t_end; ESPRIT (and the linear predictor) on the Ex probe at the resonator's front edge
-    from t_fit on, decimated to ~32 samples per period of the DFT peak."""
+def paper_cpw_q_run(cases=(1, 2, 3, 4), dz=200e-9, t_end=134e-12, t_fit=80e-12, fit_ends=None):
+    """Q and resonance of the paper's CPW (Sec. 5, Table 7) at a coarser z resolution (dz = 200 nm: the
+    film one cell thick; 100 nm: two cells; the paper's 50 nm needs 850 000 steps of 196 M cells): FP32
+    fields, FP64 probe series, run to t_end; ESPRIT (and the linear predictor) on the Ex probe at the
+    resonator's front edge over [t_fit, te] for each te of fit_ends (default: t_end), decimated to ~32
+    samples per period of the DFT peak."""
     import numpy as np
     import torch
 
@@ -444,23 +446,28 @@ def paper_cpw_q_run(cases=(1, 2, 3, 4), dz=200e-9, t_end=134e-12, t_fit=80e-12):
         el = time.perf_counter() - t0
         series = np.asarray(sim.probe(pids[1])[0])
         start = int(t_fit / wl["dt"])
-        tail = series[start:]
-        freqs = np.linspace(50e9, 150e9, 2001)
-        t = np.arange(tail.size) * wl["dt"]
-        spec = np.abs(np.exp(-2j * np.pi * np.outer(freqs, t)) @ tail)
-        fh = float(freqs[np.argmax(spec)])
-        decim = max(1, int(round(1.0 / fh / wl["dt"] / 32)))
-        count = (steps - start) // decim
-        esp = sim.esprit_fit(pids[1], start, count, decim, 0, 0, f_hint=fh)
-        lp = sim.ringdown_fit(pids[1], start, count, decim, 0, f_hint=fh)
+        fits = []
+        for te in (fit_ends or (t_end,)):
+            stop = min(steps, int(np.ceil(te / wl["dt"])))
+            tail = series[start:stop + 1]
+            freqs = np.linspace(50e9, 150e9, 2001)
+            t = np.arange(tail.size) * wl["dt"]
+            spec = np.abs(np.exp(-2j * np.pi * np.outer(freqs, t)) @ tail)
+            fh = float(freqs[np.argmax(spec)])
+            decim = max(1, int(round(1.0 / fh / wl["dt"] / 32)))
+            count = (stop - start) // decim
+            esp = sim.esprit_fit(pids[1], start, count, decim, 0, 0, f_hint=fh)
+            lp = sim.ringdown_fit(pids[1], start, count, decim, 0, f_hint=fh)
+            fits.append(dict(window_ps=[t_fit * 1e12, te * 1e12], dft_peak_GHz=fh / 1e9,
+                             esprit=dict(f_GHz=esp["f0"] / 1e9, Q=esp["Q"], order=esp["order"]),
+                             linear_prediction=dict(f_GHz=lp["f0"] / 1e9, Q=lp["Q"], order=lp["order"]),
+                             window=dict(start=start, count=count, decim=decim)))
         sim.close()
         _, _, q_paper, f_paper = workloads.PAPER_CPW_CASES[case]
-        rows.append(dict(case=case, dz=dz, cells=int(np.prod(wl["shape"])), steps=steps, seconds=el, dft_peak_GHz=fh / 1e9,
-                         esprit=dict(f_GHz=esp["f0"] / 1e9, Q=esp["Q"], order=esp["order"]),
-                         linear_prediction=dict(f_GHz=lp["f0"] / 1e9, Q=lp["Q"], order=lp["order"]),
-                         paper=dict(f_GHz=f_paper, Q=q_paper), window=dict(start=start, count=count, decim=decim)))
+        rows.append(dict(case=case, dz=dz, cells=int(np.prod(wl["shape"])), steps=steps, seconds=el, fits=fits,
+                         paper=dict(f_GHz=f_paper, Q=q_paper)))
         print(f"# {rows[-1]}", file=sys.stderr, flush=True)
-        np.save(os.path.join(ROOT, "gpurun_out", f"paper_cpw_q_case{case}.npy"), series[::16])
+        np.save(os.path.join(ROOT, "gpurun_out", f"paper_cpw_q_case{case}_dz{int(round(dz * 1e9))}nm.npy"), series[::16])
         del sim
         torch.cuda.empty_cache()
     return rows
@@ -480,6 +487,9 @@ def main():
     ap.add_argument("--table1", action="store_true")
     ap.add_argument("--paper-cpw", action="store_true")
     ap.add_argument("--paper-cpw-q", type=str, default="", help="comma-separated film cases, e.g. 1,2")
+    ap.add_argument("--q-dz", type=float, default=200.0, help="cell size along z of the Q runs (nm)")
+    ap.add_argument("--q-end", type=float, default=134.0, help="end time of the Q runs (ps)")
+    ap.add_argument("--q-fit-ends", type=str, default="", help="comma-separated ends of the fit windows (ps)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1).", file=sys.stderr)
@@ -494,7 +504,9 @@ def main():
         return
     if args.paper_cpw_q:
         cases = tuple(int(c) for c in args.paper_cpw_q.split(","))
-        print(json.dumps({"metric": "Q and f of the paper's CPW at dz = 200 nm", "paper_cpw_q": paper_cpw_q_run(cases)}),
+        ends = tuple(float(e) * 1e-12 for e in args.q_fit_ends.split(",")) if args.q_fit_ends else None
+        q = paper_cpw_q_run(cases, dz=args.q_dz * 1e-9, t_end=args.q_end * 1e-12, fit_ends=ends)
+        print(json.dumps({"metric": f"Q and f of the paper's CPW at dz = {args.q_dz:g} nm", "paper_cpw_q": q}),
               flush=True)
         return
     if args.paper_cpw:

@@ -744,7 +744,7 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
 }
 
 // ---------------------------------------------------------------------------
-// Two time steps in one sweep (temporal blocking; periodic grids, edge classes)
+// Two time steps in one sweep (temporal blocking; grids with edge classes)
 // ---------------------------------------------------------------------------
 // A block covers a footprint of 64 x TY columns of the x-y plane (one wavefront per row) and marches
 // along z, one plane per iteration, the second step one plane behind the first:
@@ -772,6 +772,13 @@ __global__ __launch_bounds__(TX *TY, TFL_MIN_WAVES) void fused_step_kernel(const
 // step on two planes before its range.  Per cell the sweep reads E, H, Js (on superconducting edges)
 // and the classes once and writes them once for two steps.  Every expression is the fused sweep's,
 // so the results equal two fused steps bit for bit.
+// Soft sources (both steps' values) and probe copies (of E^{n+1} and E^{n+2}) ride along in the SIDE
+// instantiation.  On CPML grids (PML) the stages stretch their differences as the fused sweep does:
+// A and B with the stored auxiliary variables, keeping the lane's new ones in registers, C and D with
+// those; D stores the second step's variables for the footprint's interior to the other set (halo
+// cells read the old ones).  No global load may be consumed between the issue of the tile loads and
+// their wait (waiting for it would also wait for them): the slab coefficients come from LDS tables
+// filled once per block, and the auxiliary variables are loaded one plane ahead with the Js.
 static __device__ __forceinline__ int wrap_index(int v, int n)
 {
     const int r = v % n;
@@ -830,11 +837,17 @@ __global__ __launch_bounds__(kTileX *TY, 1) void two_step_kernel(const StepArgs<
     const int wave = __builtin_amdgcn_readfirstlane(row);
     const int xo = tx * OX + lane - 2, yo = ty * OY + row - 1;  // the cell's output coordinates
     const int i = wrap_index(xo, nx), j = wrap_index(yo, ny);
-    // soft sources and probes whose boxes meet this wavefront's columns (any plane: the runs wrap
-    // along z); SIDE: an instantiation of its own, so that the sweep without them keeps its registers
-    [[maybe_unused]] const uint64_t side = SIDE ? side_mask(a.side, i, j, 0, nz) : 0;
     const bool out = lane >= 2 && lane <= OX + 1 && xo < nx && row >= 1 && row <= OY && yo < ny;
     const int k0 = tz * TZ, k1 = min(k0 + TZ, nz);
+    // soft sources and probes whose boxes meet this wavefront's columns on the planes the run touches
+    // (k0-1 .. k1, wrapped along z); SIDE: an instantiation of its own, so that the sweep without them
+    // keeps its registers
+    uint64_t side = 0;
+    if constexpr (SIDE) {
+        side = side_mask(a.side, i, j, max(k0 - 1, 0), min(k1 + 1, nz));
+        if (k0 == 0) side |= side_mask(a.side, i, j, nz - 1, nz);
+        if (k1 == nz) side |= side_mask(a.side, i, j, 0, 1);
+    }
     const long long sxy = a.g.sxy;
     const int jp = (j + 1 == ny) ? 0 : j + 1, ip = (i + 1 == nx) ? 0 : i + 1;
     constexpr uint32_t w = sizeof(T);
@@ -1875,11 +1888,10 @@ hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s)
 }
 
 // Two-step sweep: footprints of 64 x TY cells (the rows of a block share LDS), TZ output planes per
-// block.  Measured on 256^3 (TY 4 to 16, TZ 16 to 64): FP32 is fastest with TY = 16 (4 wavefronts per
-// SIMD, one block per CU) and TZ = 32, 0.250 ms per step against the fused sweep's 0.273; FP64 (168
-// VGPRs, 3 wavefronts per SIMD) with TY = 8 and TZ = 32, 0.554 against 0.562 ms: a block's wavefronts
-// wait for each other at the two barriers of every plane and no other block on the CU covers the
-// wait, which takes back most of what the halved traffic gains.
+// block.  Measured on 256^3 (TY 4 to 16, TZ 16 to 64): FP32 is fastest with TY = 16 (126 VGPRs, 4
+// wavefronts per SIMD, one block per CU) and TZ = 32, 0.196 ms per step against the fused sweep's
+// 0.274; FP64 (178 VGPRs, 2 wavefronts per SIMD) with TY = 8 and TZ = 32, 0.371 against 0.553.  The
+// CPML instantiations need 181-185 (FP32) and 248-256 (FP64) VGPRs: TY = 8 in both.
 template <typename T>
 struct TwoStepTiles;
 template <>
