@@ -248,10 +248,10 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
     // two passes in place on A.
     StepArgs<T> ab = a, ba = a;
     const bool fused = s->fused != nullptr && s->sweep != TFL_SWEEP_TWO_PASS;
-    // Two steps per sweep (periodic grids with edge classes) where nothing but soft sources and folded
-    // probes happens between the steps: no probe launches or non-finite checks.  Launches go A -> B ->
-    // A (E, H and Js), four steps per round trip, so the state is back in A; the remaining steps take
-    // the paths below.
+    // Two steps per sweep (grids with edge classes) where nothing but soft sources and folded probes
+    // happens between the steps: no probe launches or non-finite checks.  Launches go A -> B -> A (E,
+    // H, Js and the CPML variables), four steps per round trip, so the state is back in A; the
+    // remaining steps take the paths below.
     const bool two_applies = fused && (np == 0 || fold2) && !(s->checking && s->check_every > 0) &&
                              a.cls[0] != nullptr;
     const bool two = two_applies && (s->sweep == TFL_SWEEP_TWO_STEP || (s->sweep == TFL_SWEEP_AUTO &&

@@ -229,11 +229,12 @@ template <typename T> hipError_t launch_e_pass(const StepArgs<T> &a, hipStream_t
 // H^{n+1/2} (Hout), and on CPML axes the H-side variables from psiH to psiHo; Js and the E-side
 // variables in place.  E, Eout, H, Hout and psiH, psiHo must not overlap.
 template <typename T> hipError_t launch_fused_step(const StepArgs<T> &a, hipStream_t s);
-// Two time steps in one sweep (periodic grids with edge classes, no sources or probes in between):
-// reads E^n, H^{n-1/2}, Js^{n-1/2} from E, H, J and writes E^{n+2}, H^{n+3/2}, Js^{n+3/2} to Eout,
-// Hout, Jout, which must not overlap the inputs.  Results equal two fused steps bit for bit.
+// Two time steps in one sweep (edge classes bound; soft sources and folded probes ride along): reads
+// E^n, H^{n-1/2}, Js^{n-1/2} from E, H, J and writes E^{n+2}, H^{n+3/2}, Js^{n+3/2} to Eout, Hout,
+// Jout, and on CPML axes all four auxiliary variables from psiH, psiE to psiHo, psiEo; outputs must
+// not overlap the inputs.  Results equal two fused steps bit for bit.
 template <typename T> hipError_t launch_two_step(const StepArgs<T> &a, hipStream_t s);
-// Whether the two-step sweep applies (periodic on every axis, edge classes bound) and pays on this grid.
+// Whether the two-step sweep (edge classes bound) pays on this grid and storage type.
 template <typename T> bool two_step_pays(const StepArgs<T> &a);
 // Class table of the edge-coefficient path: entry c = coefficients of the four cells
 // mat[(tuple[c] >> 16 q) & 0xffff], q = 0..3 (mat: eps_r, sigma, ell per cell material).

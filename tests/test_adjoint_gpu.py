@@ -229,3 +229,39 @@ def test_autograd_rejects_backward_after_a_later_forward():
     assert rel_l2(L2.grad.cpu().numpy(), glo) <= 1e-10 and rel_l2(S2.grad.cpu().numpy(), gso) <= 1e-10
     with pytest.raises(RuntimeError, match="another forward pass"):
         J1.backward()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_two_step_sweep_in_checkpointed_forward_and_nested_recomputation(dtype):
+    """Where the two-step sweep runs (forced here on a small CPML grid with edge classes) it serves the
+    checkpointed forward, the objective probe folded into it, and the three-level schedule's outer
+    recomputation, with the sources only: objective and gradients equal those of the fused sweep bit
+    for bit."""
+    from paper_2305_13419_amd import Simulation
+    c = dict(shape=(130, 20, 40), pml=((5, 4), None, (3, 6)), theta=1.0, fields=True)
+    wl, obj = make_case(c)
+    wl["maps"] = workloads.roofline_grid(c["shape"])["maps"]  # few distinct materials: edge classes bind
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    N, seg, seg2 = 40, 20, 8
+    res = {}
+    for sweep in ("two_step", "fused"):
+        print(f"case: checkpointed forward and nested adjoint, sweep={sweep}, {dtype}", flush=True)
+        sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], dtype, wl["pml"])
+        sim.set_materials(*[np.asarray(m, dtype=npdt) for m in wl["maps"]])
+        assert sim.edge_classes > 0
+        sim.set_fields(*[[np.asarray(a, dtype=npdt) for a in grp] for grp in wl["fields"]])
+        for s in wl["sources"]:
+            sim.add_source(**s)
+        sim.set_sweep(sweep)
+        ckpt, ckpt2, snap, work = sim.adjoint_nested_buffers(N, seg, seg2)
+        F = sim.forward_checkpointed(obj, N, seg, ckpt)
+        forward_counts = sim.sweep_counts()
+        gl, gs = sim.adjoint_nested(obj, N, seg, seg2, ckpt, F, ckpt2, snap, work)
+        torch.cuda.synchronize()
+        res[sweep] = (F, gl.cpu().numpy(), gs.cpu().numpy(), forward_counts, sim.sweep_counts())
+        sim.close()
+    two, fused = res["two_step"], res["fused"]
+    assert two[3][2] == N and fused[3][2] == 0, (two[3], fused[3])  # the forward's segments, 5 x 4 steps each
+    assert two[4][2] > two[3][2], two[4]  # the outer recomputation too
+    assert two[0] == fused[0]
+    assert np.array_equal(two[1], fused[1]) and np.array_equal(two[2], fused[2])
