@@ -222,11 +222,11 @@ int do_step(tfl_sim *s, int64_t nsteps, hipStream_t st, hipEvent_t *ev, bool pro
         g.side.nred = pending ? np : 0;
         g.side.nsamp = pending_cnt;
         g.side.rn = pending_n;
-        for (int p = 0; p < np; ++p) {
+        for (int p = 0; p < np; ++p) {  // second samples only where two copies fit a half
             g.side.pcopy[p] = copy_at(half, 0, p);
-            g.side.pcopy2[p] = copy_at(half, 1, p);
+            g.side.pcopy2[p] = fold2 ? copy_at(half, 1, p) : nullptr;
             g.side.rcopy[p] = copy_at(1 - half, 0, p);
-            g.side.rcopy2[p] = copy_at(1 - half, 1, p);
+            g.side.rcopy2[p] = fold2 ? copy_at(1 - half, 1, p) : nullptr;
         }
     };
     // the side work of the sweep of step s->step -> s->step + 1
