@@ -1792,11 +1792,15 @@ static void launch_e_pass_w(const StepArgs<T> &a, hipStream_t s)
     using C = FwdTiles<T>;
     const int tz = pick_tile_z_w(a.g, C::ey, C::e_waves, C::ez_max, W);
     const dim3 blk(kTileX, C::ey), grd((unsigned)(row_tiles(a.g, C::ey, W) * ((a.g.nz + tz - 1) / tz)));
+    // FP32: 28 KiB of (unused) LDS per block, so that a CU takes at most 5 blocks of 4 wavefronts: at
+    // 80 VGPRs the hardware would run 6 per SIMD, measured 0.261 ms at 256^3 with edge classes
+    // against 0.235 ms with 5
+    const size_t lds = sizeof(T) == 4 ? 28 * 1024 : 0;
     switch (tz) {
-    case 64: hipLaunchKernelGGL((e_pass_kernel<T, C::ey, 64, CLS, W>), grd, blk, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((e_pass_kernel<T, C::ey, 32, CLS, W>), grd, blk, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((e_pass_kernel<T, C::ey, 16, CLS, W>), grd, blk, 0, s, a); break;
-    default: hipLaunchKernelGGL((e_pass_kernel<T, C::ey, 8, CLS, W>), grd, blk, 0, s, a); break;
+    case 64: hipLaunchKernelGGL((e_pass_kernel<T, C::ey, 64, CLS, W>), grd, blk, lds, s, a); break;
+    case 32: hipLaunchKernelGGL((e_pass_kernel<T, C::ey, 32, CLS, W>), grd, blk, lds, s, a); break;
+    case 16: hipLaunchKernelGGL((e_pass_kernel<T, C::ey, 16, CLS, W>), grd, blk, lds, s, a); break;
+    default: hipLaunchKernelGGL((e_pass_kernel<T, C::ey, 8, CLS, W>), grd, blk, lds, s, a); break;
     }
 }
 
