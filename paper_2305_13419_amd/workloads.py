@@ -109,25 +109,27 @@ def random_medium(shape, seed, pml=(None, None, None), d=(20e-9, 17e-9, 23e-9), 
 def cpw_grid(scale=1, steps=None, dtype_note="FP32 fields + FP64 probes"):
     """Coplanar-waveguide resonator shaped like the paper's device (Sec. 5), at reduced size.
 
-    scale=1: 512 x 256 x 128 cells of 0.5 um; scale=2 halves every length (256 x 128 x 64).
+    scale=1: 512 x 256 x 128 cells of 0.5 um; scale=2 halves every length (256 x 128 x 64), scale=4
+    quarters it (128 x 64 x 32, the film one cell thick: the generator at a size the oracle steps 20 000
+    times in about a minute).
     eps_r = 11.7 substrate below the film; a 4-cell (2 at scale 2) superconducting film
     (lambda_L = 100 nm, sigma_n = 1e4 S/m) patterned as a centre strip with two gaps and ground
     planes reaching the periodic y edges; the strip is cut by two coupling gaps into input port,
     half-wave resonator and output port; the pattern stops one PML width short of the x-PML.
     CPML on the x and z faces.  Excitation: opposite soft Ey Gaussian-modulated pulses in the two
-    gaps near the input end (f = 0.96 THz at scale 1, doubled at scale 2; tw = 1/(2f), t0 = 4 tw).
+    gaps near the input end (f = 0.96 THz x scale; tw = 1/(2f), t0 = 4 tw).
     dt = 0.95 x the stable limit with the London term."""
     s = scale
     nx, ny, nz = 512 // s, 256 // s, 128 // s
     d = 0.5e-6
     npml = 16 // s
     k_film0, k_film1 = 48 // s, 52 // s
-    strip = (118 // s, 138 // s) if s == 1 else (59, 69)
-    gap_lo = (106 // s, strip[0]) if s == 1 else (53, 59)
-    gap_hi = (strip[1], 150 // s) if s == 1 else (69, 75)
+    strip = (118 // s, 138 // s)
+    gap_lo = (106 // s, strip[0])
+    gap_hi = (strip[1], 150 // s)
     x0, x1 = 32 // s, 480 // s
-    cg1 = (190 // s, 194 // s) if s == 1 else (95, 97)
-    cg2 = (318 // s, 322 // s) if s == 1 else (159, 161)
+    cg1 = (190 // s, 194 // s)
+    cg2 = (318 // s, 322 // s)
     shp = (nz, ny, nx)
     eps = np.ones(shp)
     eps[:k_film0] = 11.7
