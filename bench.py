@@ -2,11 +2,15 @@
 
 Workload: the 256^3 roofline grid (dx = 20 nm, periodic, random
 superconducting boxes on ~30 % of the cells, E and H ~ N(0, 1)), stepped in
-FP64 and in FP32.  A step is one full time step of Algorithm 1: one fused
-sweep (the product path), and for comparison the two passes (H pass, E + Js
-pass) it replaces.  Also timed: the adjoint gradient on the half-size CPW
-workload (256 x 128 x 64 cells, 4096 steps, 64-step checkpoint segments)
-against its checkpointed forward run.  Prints one JSON line.
+FP64 and in FP32.  A step is one full time step of Algorithm 1.  The product
+path is the library's automatic sweep choice (on this grid two time steps per
+sweep with edge classes); for comparison the one-step fused sweep (with edge
+classes and on the per-cell maps) and the two passes (H pass, E + Js pass).
+Also timed: the CPW-shaped 512 x 256 x 128 grid (CPML, two sources, two
+probes every step), the adjoint gradient on the half-size CPW workload
+(256 x 128 x 64 cells, 4096 steps, 64-step checkpoint segments) against its
+checkpointed forward run, and the oracle on a bounded sample on the host
+cores.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--n 256] [--no-cpu] [--no-adjoint]
     python bench.py --large      # the 1024 x 512 x 256 workload: FP32 forward 8192 steps and the
