@@ -220,3 +220,31 @@ def test_two_step_cpml_matches_oracle(dtype, tol):
     r = compare(g, o)
     print(f"two-step with CPML {dtype} vs oracle, {steps} steps: {r}", flush=True)
     assert max(r.values()) <= tol
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.7])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_two_step_theta_below_one(theta, dtype):
+    """theta of Algorithm 1 step 3 below 1 (the centred Ohmic term and a weighted one): the two-step
+    sweep equals the fused sweep bit for bit on a periodic grid and on one with CPML slabs, and in FP64
+    its integer-time fields match the oracle."""
+    cases = (dict(workloads.roofline_grid((130, 40, 24))), cpml_workload((130, 33, 40), ((5, 4), None, (3, 6))))
+    for wl in cases:
+        wl["theta"] = theta
+        print(f"case: two-step vs fused, {wl['shape']}, pml={wl['pml']}, theta {theta}, {dtype}, chunks 8, 3",
+              flush=True)
+        a, ca, sa = run(wl, 11, dtype, "two_step", [8, 3])
+        b, cb, sb = run(wl, 11, dtype, "fused", [8, 3])
+        assert ca[2] == 8 and cb[2] == 0, (ca, cb)
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+        if dtype == torch.float64:
+            Eg, Hg, Jg = sa.integer_time_fields()
+            torch.cuda.synchronize()
+            g = ([t.cpu().numpy() for t in Eg], [t.cpu().numpy() for t in Hg], [t.cpu().numpy() for t in Jg], [])
+            o = run_oracle(wl, 11)
+            r = compare(g, o)
+            print(f"  two-step theta {theta} vs oracle, 11 steps: {r}", flush=True)
+            assert max(r.values()) <= 1e-12
+        sa.close()
+        sb.close()
