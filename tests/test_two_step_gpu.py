@@ -248,3 +248,19 @@ def test_two_step_theta_below_one(theta, dtype):
             assert max(r.values()) <= 1e-12
         sa.close()
         sb.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", [(1, 1, 40), (40, 1, 1), (1, 30, 1), (70, 1, 33), (64, 17, 1), (1, 9, 21)])
+def test_two_step_degenerate_axes(shape, dtype):
+    """Axes of one cell (the wrapped neighbour is the cell itself, so the derivatives along them vanish):
+    the two-step sweep, taken on request, equals the fused sweep bit for bit."""
+    wl = workloads.roofline_grid(shape)
+    print(f"case: two-step vs fused, degenerate {shape}, {dtype}, chunks 8, 3", flush=True)
+    a, ca, sa = run(wl, 11, dtype, "two_step", [8, 3])
+    b, cb, sb = run(wl, 11, dtype, "fused", [8, 3])
+    assert ca[2] == 8 and cb[2] == 0, (ca, cb)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    sa.close()
+    sb.close()
