@@ -14,7 +14,9 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# TFL_ORACLE_LIB points the wrapper at another build of the same source (the planted-mistake tests
+# build altered copies and run the pins against them)
+LIB_PATH = os.environ.get("TFL_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "tfl_oracle.c")
 SRC_ADJ_PATH = os.path.join(HERE, "tfl_oracle_adjoint.c")
 
