@@ -417,7 +417,7 @@ def paper_cpw_run(steps=200, warmup=10, cases=(1, 2, 3, 4), fused=True):
     return rows
 
 
-def paper_cpw_q_run(cases=(1, 2, 3, 4), dz=200e-9, t_end=134e-12, t_fit=80e-12, fit_ends=None):
+def paper_cpw_q_run(cases=(1, 2, 3, 4), dz=200e-9, t_end=134e-12, t_fit=80e-12, fit_ends=None, save_dir=None):
     """Q and resonance of the paper's CPW (Sec. 5, Table 7) at a coarser z resolution (dz = 200 nm: the
     film one cell thick; 100 nm: two cells; the paper's 50 nm needs 850 000 steps of 196 M cells): FP32
     fields, FP64 probe series, run to t_end; ESPRIT (and the linear predictor) on the Ex probe at the
@@ -471,7 +471,9 @@ def paper_cpw_q_run(cases=(1, 2, 3, 4), dz=200e-9, t_end=134e-12, t_fit=80e-12, 
         rows.append(dict(case=case, dz=dz, cells=int(np.prod(wl["shape"])), steps=steps, seconds=el, fits=fits,
                          paper=dict(f_GHz=f_paper, Q=q_paper)))
         print(f"# {rows[-1]}", file=sys.stderr, flush=True)
-        np.save(os.path.join(ROOT, "gpurun_out", f"paper_cpw_q_case{case}_dz{int(round(dz * 1e9))}nm.npy"), series[::16])
+        if save_dir:  # every 16th sample of the FP64 probe series, for fits outside the library
+            os.makedirs(save_dir, exist_ok=True)
+            np.save(os.path.join(save_dir, f"paper_cpw_q_case{case}_dz{int(round(dz * 1e9))}nm.npy"), series[::16])
         del sim
         torch.cuda.empty_cache()
     return rows
@@ -494,6 +496,7 @@ def main():
     ap.add_argument("--q-dz", type=float, default=200.0, help="cell size along z of the Q runs (nm)")
     ap.add_argument("--q-end", type=float, default=134.0, help="end time of the Q runs (ps)")
     ap.add_argument("--q-fit-ends", type=str, default="", help="comma-separated ends of the fit windows (ps)")
+    ap.add_argument("--save-series", type=str, default="", help="directory for the Q runs' probe series (.npy)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1).", file=sys.stderr)
@@ -509,7 +512,8 @@ def main():
     if args.paper_cpw_q:
         cases = tuple(int(c) for c in args.paper_cpw_q.split(","))
         ends = tuple(float(e) * 1e-12 for e in args.q_fit_ends.split(",")) if args.q_fit_ends else None
-        q = paper_cpw_q_run(cases, dz=args.q_dz * 1e-9, t_end=args.q_end * 1e-12, fit_ends=ends)
+        q = paper_cpw_q_run(cases, dz=args.q_dz * 1e-9, t_end=args.q_end * 1e-12, fit_ends=ends,
+                            save_dir=args.save_series)
         print(json.dumps({"metric": f"Q and f of the paper's CPW at dz = {args.q_dz:g} nm", "paper_cpw_q": q}),
               flush=True)
         return
