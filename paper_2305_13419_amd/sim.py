@@ -5,6 +5,8 @@ memory and streams only) and forwards every operation to the C ABI of
 ``libtfl.so``; all arithmetic of the time step runs in the HIP kernels.
 """
 import ctypes
+import hashlib
+import json
 
 import numpy as np
 import torch
@@ -96,6 +98,7 @@ class Simulation:
         self.class_buffer = None
         self.edge_classes = 0
         self._probes = []
+        self._probe_desc = []
         self._sources = []
 
     # -- plumbing -----------------------------------------------------------
@@ -184,6 +187,7 @@ class Simulation:
         pid = ctypes.c_int()
         self._call("tfl_add_probe", ctypes.byref(p), ctypes.byref(pid))
         self._probes.append((series, dft, int(capacity), int(freqs.size)))
+        self._probe_desc.append([int(comp), [int(v) for v in box], int(capacity), [float(f) for f in freqs]])
         return pid.value
 
     # -- running ------------------------------------------------------------
@@ -251,6 +255,52 @@ class Simulation:
 
     def load_state(self, src):
         self._call("tfl_load_state", ctypes.c_void_p(src.data_ptr()), _stream())
+
+    # -- restart files --------------------------------------------------------
+    def _run_description(self):
+        """What a saved state belongs to: the problem statement (grid, spacing, dt, theta, storage type,
+        boundaries), a hash of the bound maps, the sources and the probes."""
+        c = self._cfg
+        h = hashlib.sha256()
+        for m in self.maps or []:
+            h.update(m.cpu().numpy().tobytes())
+        src = [[x.comp, list(x.box), x.amplitude, x.waveform, x.freq, x.t0, x.tw] for x in self._sources]
+        return dict(shape=[self.nx, self.ny, self.nz], spacing=list(self.spacing), dt=self.dt, theta=self.theta,
+                    dtype=str(self.dtype), bc=list(c.bc), pml_lo=list(c.pml_lo), pml_hi=list(c.pml_hi),
+                    pml=[c.pml_order, c.pml_scale, c.kappa_max, c.alpha_max], maps_sha256=h.hexdigest(),
+                    sources=src, probes=self._probe_desc)
+
+    def save_checkpoint(self, path):
+        """Write the run to `path` (NumPy .npz of plain arrays, nothing pickled): the state of
+        tfl_save_state (E, H, Js and the CPML variables), the step index, every probe's FP64 series and
+        DFT accumulators, and the run's description, which load_checkpoint checks."""
+        state = self.save_state().cpu().numpy()
+        arrays = {"state": state, "step": np.array([self.step_index], dtype=np.int64),
+                  "description": np.frombuffer(json.dumps(self._run_description()).encode(), dtype=np.uint8)}
+        for q, (series, dft, _, _) in enumerate(self._probes):
+            arrays[f"series{q}"] = series.cpu().numpy()
+            arrays[f"dft{q}"] = dft.cpu().numpy()
+        with open(path, "wb") as f:
+            np.savez(f, **arrays)
+
+    def load_checkpoint(self, path):
+        """Continue a run written by save_checkpoint: this simulation must describe the same run (grid,
+        spacing, dt, theta, storage type, boundaries, maps, sources and probes, added in the same order);
+        the state, step index and probe buffers are replaced.  Raises ValueError on a mismatch."""
+        with np.load(path, allow_pickle=False) as z:
+            saved = json.loads(z["description"].tobytes().decode())
+            mine = json.loads(json.dumps(self._run_description()))
+            if saved != mine:
+                diff = sorted(k for k in set(saved) | set(mine) if saved.get(k) != mine.get(k))
+                raise ValueError(f"checkpoint belongs to another run (differs in: {', '.join(diff)})")
+            state = z["state"]
+            if state.size != self.state_bytes:
+                raise ValueError(f"checkpoint state has {state.size} bytes, this run {self.state_bytes}")
+            self.load_state(torch.from_numpy(np.ascontiguousarray(state)).to(self.device))
+            self.set_step(int(z["step"][0]))
+            for q, (series, dft, _, _) in enumerate(self._probes):
+                series.copy_(torch.from_numpy(z[f"series{q}"]).to(self.device))
+                dft.copy_(torch.from_numpy(z[f"dft{q}"]).to(self.device))
 
     def ringdown_fit(self, pid, start, count, decim=1, order=0, f_hint=0.0):
         """Linear-prediction fit of probe pid's series window; returns dict(f0, alpha, Q, residual,
