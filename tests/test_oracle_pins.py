@@ -75,6 +75,29 @@ def test_stability_bound_is_sharp():
         assert (rho <= 1 + 1e-12) == stable
 
 
+def test_oracle_run_above_the_bound_blows_up():
+    """The oracle itself on a 3-D grid (superconducting everywhere, lambda_L = 50 nm, random fields):
+    at 0.95 x the London-aware bound the discrete energy stays at its initial value (lossless), at
+    1.2 x it grows without bound (the scheme's amplification exceeds one at the Nyquist mode)."""
+    d, n = 20e-9, 16
+    shp = (n, n, n)
+    ell = 1 / (50e-9) ** 2
+    dtm = cf.stable_dt([d, d, d], ell)
+    rng = np.random.default_rng(5)
+    E0 = [rng.standard_normal(shp) for _ in range(3)]
+    B0 = [1.25663706212e-6 * rng.standard_normal(shp) / 377.0 for _ in range(3)]
+    grow = {}
+    for f in (0.95, 1.2):
+        sim = OracleSim((n, n, n), (d, d, d), f * dtm, 1.0)
+        sim.set_materials(np.ones(shp), np.zeros(shp), np.full(shp, ell))
+        sim.set_fields(E0, B0, zeros(shp))
+        W0 = sim.energy()
+        sim.step(300)
+        grow[f] = sim.energy() / W0
+    assert abs(grow[0.95] - 1) < 1e-10
+    assert not np.isfinite(grow[1.2]) or grow[1.2] > 1e6  # 300 steps overflow to inf / nan
+
+
 # ---------------------------------------------------------------------------
 # Discrete energy identity on heterogeneous periodic media
 # ---------------------------------------------------------------------------
