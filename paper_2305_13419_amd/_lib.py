@@ -11,7 +11,8 @@ import os
 import torch  # noqa: F401  (loads the HIP runtime that the library binds to)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtfl.so")
+# TFL_LIB points the binding at another build of the library (the host-sanitizer test loads one)
+LIB_PATH = os.environ.get("TFL_LIB") or os.path.join(HERE, "libtfl.so")
 
 TFL_OK = 0
 TFL_E_INVAL = -1

@@ -9,7 +9,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "tfl.h")
-LIB = os.path.join(ROOT, "paper_2305_13419_amd", "libtfl.so")
+LIB = os.environ.get("TFL_LIB") or os.path.join(ROOT, "paper_2305_13419_amd", "libtfl.so")
 
 
 def declared():
