@@ -1,5 +1,5 @@
-"""The paper's three-dimensional convergence study (Sec. 4.3.3, Tables 5 and 6) on the HIP path at the
-paper's sizes: a cube of superconductor (lambda_L = 40 nm, sigma_n = 1e4 S/m, the paper's case (d)) from
+"""The paper's convergence studies (Sec. 4.3, Tables 2-6) on the HIP path at the paper's sizes.  Tables
+5 and 6 (Sec. 4.3.3): a cube of superconductor (lambda_L = 40 nm, sigma_n = 1e4 S/m, the paper's case (d)) from
 -40 to 40 nm in a periodic vacuum domain [-640, 640] nm^3, hit by the plane Gaussian pulse
 Ex = exp(-(z - z0)^2 / L^2), By = Ex / c (z0 = -320 nm, L = 80 nm), theta = 0.5 (the scheme's
 second-order form, as for Tables 2-4), to t = 1.73 fs.
@@ -41,19 +41,28 @@ def tables():
     return rows
 
 
-def cube_run(n, dt, steps):
-    """Integer-time (Ex, Ey, Ez, Bx, By, Bz) on the device after `steps` steps on n^3 cells."""
+def cube_run(n, dt, steps, region="cube", zp=-320e-9):
+    """Integer-time (Ex, Ey, Ez, Bx, By, Bz) on the device after `steps` steps on n^3 cells.  The
+    superconductor fills the cube (Tables 5-6), the strip -40 < z < 40 nm over all x and y (Tables 3-4)
+    or the whole domain (Table 2); zp is the pulse's initial centre."""
     from paper_2305_13419_amd import Simulation
     d = 1280e-9 / n
     sim = Simulation((n, n, n), (d, d, d), dt, 0.5, torch.float64)
     dev = sim.device
     c = -640e-9 + (torch.arange(n, device=dev, dtype=torch.float64) + 0.5) * d  # cell centres
     inside = (c > -40e-9) & (c < 40e-9)
-    cube = inside[:, None, None] & inside[None, :, None] & inside[None, None, :]
+    every = torch.ones_like(inside)
+    if region == "cube":
+        sc = inside[:, None, None] & inside[None, :, None] & inside[None, None, :]
+    elif region == "strip":
+        sc = inside[:, None, None] & every[None, :, None] & every[None, None, :]
+    else:
+        sc = every[:, None, None] & every[None, :, None] & every[None, None, :]
+    cube = sc
     z0 = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
     sim.set_materials(torch.ones_like(z0), torch.where(cube, 1e4, 0.0), torch.where(cube, 1.0 / (40e-9) ** 2, 0.0))
     zn = -640e-9 + torch.arange(n, device=dev, dtype=torch.float64) * d  # z of node k
-    L, zp = 80e-9, -320e-9
+    L = 80e-9
     ex = torch.exp(-((zn - zp) ** 2) / L**2)[:, None, None].expand(n, n, n).contiguous()
     hy = (torch.exp(-((zn + d / 2 - zp) ** 2) / L**2) / (C0 * MU0))[:, None, None].expand(n, n, n).contiguous()
     sim.set_fields([ex, z0, z0], [z0, hy, z0], [z0, z0, z0])
@@ -121,3 +130,48 @@ def test_table6_cube_space_convergence():
         a, b, r = ref[("table6", comp)]
         assert abs(np.log2(e1 / e2) - r) < 0.10, comp
         assert abs(e1 / a - 1) < 0.15 and abs(e2 / b - 1) < 0.15, comp
+
+
+# Tables 2-4: plane pulses through a homogeneous superconductor or a strip, on the paper's 3-D grids (the
+# fields are uniform in x and y, so the L1 means equal those of the 1-D reductions the oracle pins run)
+def space_errors(runs):
+    """(e_coarse^medium, e_medium^fine) of Ex and By from runs on 128^3, 256^3, 512^3 (finer restricted)."""
+    errs = {"Ex": [], "By": []}
+    prev = None
+    for cur in runs:
+        if prev is not None:
+            for comp in errs:
+                errs[comp].append(l1(restrict(cur[comp], comp), prev[comp]))
+        prev = {k: cur[k] for k in errs}
+        del cur
+    return errs
+
+
+def check_table(name, errs, tol_err, tol_rate):
+    ref = tables()
+    for comp, fld in (("Ex", "E"), ("By", "B")):
+        e1, e2 = errs[comp]
+        a, b, r = ref[(name, fld)]
+        rate = np.log2(e1 / e2)
+        print(f"{name} {fld}: {e1:.3e} {e2:.3e} rate {rate:.3f}  (paper {a:.3e} {b:.3e} {r:.2f})", flush=True)
+        assert abs(e1 / a - 1) < tol_err and abs(e2 / b - 1) < tol_err, (name, fld)
+        assert abs(rate - r) < tol_rate, (name, fld)
+
+
+def test_table2_homogeneous_space_time_convergence():
+    runs = (cube_run(n, 0.9 * (1280e-9 / n) / (C0 * np.sqrt(3)), st, region="all", zp=0.0)
+            for n, st in ((128, 50), (256, 100), (512, 200)))
+    check_table("table2", space_errors(runs), 0.01, 0.02)
+
+
+def test_table3_strip_time_convergence():
+    dt09 = 0.9 * 5e-9 / (C0 * np.sqrt(3))
+    sols = [cube_run(256, dt09 * f, st, region="strip") for f, st in ((1.0, 200), (0.5, 400), (0.25, 800))]
+    errs = {comp: [l1(sols[1][comp], sols[0][comp]), l1(sols[2][comp], sols[1][comp])] for comp in ("Ex", "By")}
+    check_table("table3", errs, 0.10, 0.02)
+
+
+def test_table4_strip_space_convergence():
+    dt = 0.9 * 2.5e-9 / (C0 * np.sqrt(3))
+    runs = (cube_run(n, dt, 400, region="strip") for n in (128, 256, 512))
+    check_table("table4", space_errors(runs), 0.02, 0.03)
