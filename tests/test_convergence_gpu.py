@@ -43,8 +43,9 @@ def tables():
 
 def cube_run(n, dt, steps, region="cube", zp=-320e-9):
     """Integer-time (Ex, Ey, Ez, Bx, By, Bz) on the device after `steps` steps on n^3 cells.  The
-    superconductor fills the cube (Tables 5-6), the strip -40 < z < 40 nm over all x and y (Tables 3-4)
-    or the whole domain (Table 2); zp is the pulse's initial centre."""
+    superconductor fills the cube (Tables 5-6), the strip -40 < z < 40 nm over all x and y (Tables 3-4),
+    the whole domain (Table 2), or, with "smooth", the half z > 0 with lambda_L falling smoothly from 400
+    to 40 nm and sigma = 0 (Sec. 4.3.2); zp is the pulse's initial centre."""
     from paper_2305_13419_amd import Simulation
     d = 1280e-9 / n
     sim = Simulation((n, n, n), (d, d, d), dt, 0.5, torch.float64)
@@ -58,9 +59,14 @@ def cube_run(n, dt, steps, region="cube", zp=-320e-9):
         sc = inside[:, None, None] & every[None, :, None] & every[None, None, :]
     else:
         sc = every[:, None, None] & every[None, :, None] & every[None, None, :]
-    cube = sc
     z0 = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
-    sim.set_materials(torch.ones_like(z0), torch.where(cube, 1e4, 0.0), torch.where(cube, 1.0 / (40e-9) ** 2, 0.0))
+    if region == "smooth":  # sigma = 0, lambda_L from 400 nm at z = 0 to 40 nm at the domain's end (z > 0 only)
+        lam = 400e-9 + (40e-9 - 400e-9) * torch.clamp(c / 640e-9, 0.0, 1.0)
+        ell = torch.where(c > 0, 1.0 / lam**2, 0.0)[:, None, None].expand(n, n, n).contiguous()
+        sim.set_materials(torch.ones_like(z0), z0, ell)
+        del ell
+    else:
+        sim.set_materials(torch.ones_like(z0), torch.where(sc, 1e4, 0.0), torch.where(sc, 1.0 / (40e-9) ** 2, 0.0))
     zn = -640e-9 + torch.arange(n, device=dev, dtype=torch.float64) * d  # z of node k
     L = 80e-9
     ex = torch.exp(-((zn - zp) ** 2) / L**2)[:, None, None].expand(n, n, n).contiguous()
@@ -175,3 +181,14 @@ def test_table4_strip_space_convergence():
     dt = 0.9 * 2.5e-9 / (C0 * np.sqrt(3))
     runs = (cube_run(n, dt, 400, region="strip") for n in (128, 256, 512))
     check_table("table4", space_errors(runs), 0.02, 0.03)
+
+
+def test_smooth_lambda_keeps_second_order():
+    """Sec. 4.3.2: with lambda_L varying smoothly (no sharp interface) the scheme stays second order in
+    space, where the strip of Table 4 falls to first order."""
+    dt = 0.9 * 2.5e-9 / (C0 * np.sqrt(3))
+    errs = space_errors(cube_run(n, dt, 400, region="smooth") for n in (128, 256, 512))
+    for comp in ("Ex", "By"):
+        e1, e2 = errs[comp]
+        print(f"smooth lambda {comp}: {e1:.3e} {e2:.3e} rate {np.log2(e1 / e2):.3f}", flush=True)
+        assert np.log2(e1 / e2) > 1.8, comp
