@@ -1,11 +1,12 @@
-"""The paper's skin-depth sweep (Sec. 4.1, Table 1), all twelve rows on the GPU (FP64): the skin
+"""The paper's skin-depth sweep (Sec. 4.1, Table 1) on the GPU (FP64), ten of its twelve rows: the skin
 depth measured from the simulated field, z0 / ln(A(0) / A(z0)) with steady-state amplitudes over the
 last two of five periods, against the discrete scheme's prediction 1 / Im k (oracle closed form) and
 the paper's computed column.  The undamped 100 THz row sits 16 % below the medium's cutoff (119 THz):
 the sudden start of the sine excites waves just above the cutoff whose group velocity is near zero and
 which stay at the source for tens of periods (the paper's own value there is 0.7 % off the theory), so
 that row runs 200 periods and fits the last 50.  The 100 GHz rows take 1.7 M steps and the 25 GHz rows
-6.7 M steps each (about 12 and 45 s on one GPU: the 6065-cell line is launch-bound).  One row per
+6.7 M steps each (about 12 and 49 s on one GPU: the 6065-cell line is launch-bound); the two 25 GHz rows
+left out (sigma = 0 and 1e4, both 400.010 nm) pass the same check in `bench.py --table1`.  One row per
 conductivity (100 THz, five periods) is also compared with the oracle, field by field and sample by
 sample."""
 import numpy as np
@@ -19,8 +20,13 @@ torch = pytest.importorskip("torch")
 ELL = 1.0 / (400e-9) ** 2
 
 
+# every row at 100 GHz and above, and of the 25 GHz rows (6.7 M steps, about 50 s each) the one whose
+# skin depth differs from lambda_L (sigma = 1e7: 395 nm); the other two run in `bench.py --table1`
+ROWS = [r for r in workloads.TABLE1_ROWS if r[1] >= 1e11 or r[0] == 1e7]
+
+
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("sigma,freq,paper", workloads.TABLE1_ROWS)
+@pytest.mark.parametrize("sigma,freq,paper", ROWS)
 def test_table1_row(sigma, freq, paper):
     from paper_2305_13419_amd import Simulation
     theory = float(cf.skin_depth(freq, 1.0, sigma, ELL))
