@@ -417,7 +417,8 @@ def paper_cpw_run(steps=200, warmup=10, cases=(1, 2, 3, 4), fused=True):
     return rows
 
 
-def paper_cpw_q_run(cases=(1, 2, 3, 4), dz=200e-9, t_end=134e-12, t_fit=80e-12, fit_ends=None, save_dir=None):
+def paper_cpw_q_run(cases=(1, 2, 3, 4), dz=200e-9, t_end=134e-12, t_fit=80e-12, fit_ends=None, save_dir=None,
+                    film_sigma=None):
     """Q and resonance of the paper's CPW (Sec. 5, Table 7) at a coarser z resolution (dz = 200 nm: the
     film one cell thick; 100 nm: two cells; the paper's 50 nm needs 850 000 steps of 196 M cells): FP32
     fields, FP64 probe series, run to t_end; ESPRIT (and the linear predictor) on the Ex probe at the
@@ -430,7 +431,7 @@ def paper_cpw_q_run(cases=(1, 2, 3, 4), dz=200e-9, t_end=134e-12, t_fit=80e-12, 
 
     rows = []
     for case in cases:
-        wl = workloads.paper_cpw_grid(case, dz=dz)
+        wl = workloads.paper_cpw_grid(case, dz=dz, film_sigma=film_sigma)
         steps = int(np.ceil(t_end / wl["dt"]))
         sim = Simulation(wl["shape"], wl["spacing"], wl["dt"], wl["theta"], torch.float32, wl["pml"])
         sim.set_materials(*[np.asarray(m, dtype=np.float32) for m in wl["maps"]])
@@ -497,6 +498,7 @@ def main():
     ap.add_argument("--q-end", type=float, default=134.0, help="end time of the Q runs (ps)")
     ap.add_argument("--q-fit-ends", type=str, default="", help="comma-separated ends of the fit windows (ps)")
     ap.add_argument("--save-series", type=str, default="", help="directory for the Q runs' probe series (.npy)")
+    ap.add_argument("--q-film-sigma", type=float, default=None, help="film conductivity of the Q runs (S/m)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1).", file=sys.stderr)
@@ -513,7 +515,7 @@ def main():
         cases = tuple(int(c) for c in args.paper_cpw_q.split(","))
         ends = tuple(float(e) * 1e-12 for e in args.q_fit_ends.split(",")) if args.q_fit_ends else None
         q = paper_cpw_q_run(cases, dz=args.q_dz * 1e-9, t_end=args.q_end * 1e-12, fit_ends=ends,
-                            save_dir=args.save_series)
+                            save_dir=args.save_series, film_sigma=args.q_film_sigma)
         print(json.dumps({"metric": f"Q and f of the paper's CPW at dz = {args.q_dz:g} nm", "paper_cpw_q": q}),
               flush=True)
         return

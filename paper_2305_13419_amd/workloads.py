@@ -234,7 +234,7 @@ PAPER_CPW_CASES = {1: (6e7, 0.0, 24, 96.9), 2: (1e10, 0.0, 491, 98.2), 3: (6e7, 
                    4: (0.0, 1e14, 973, 97.1)}
 
 
-def paper_cpw_grid(case=3, npml=(8, 8, 16), fields=None, seed=11, dz=50e-9, dt=None):
+def paper_cpw_grid(case=3, npml=(8, 8, 16), fields=None, seed=11, dz=50e-9, dt=None, film_sigma=None):
     """The paper's coplanar-waveguide resonator at its own size (Sec. 5): the domain [-65, 65] um x
     [-504, 504] um x [0, 64] um in 130 x 1008 x 1280 cells (dx = dy = 1 um, dz = 50 nm), with CPML
     slabs of npml cells added outside it on every face (the paper's PML is outside its domain too).
@@ -245,8 +245,11 @@ def paper_cpw_grid(case=3, npml=(8, 8, 16), fields=None, seed=11, dz=50e-9, dt=N
     Gaussian-modulated sines exp(-(t - 4T)^2 / (2 T^2)) sin(2 pi t / T), T = 1 / 100 GHz, in the two gaps
     at y = -500 um over the film thickness.  Probes: Ex in the left gap at y = -450 um and -300 um, on
     the film's middle plane.  dt defaults to 0.95 x the stable limit with the London term (0.158 fs,
-    the paper's).  fields='random' gives seeded N(0, 1) initial fields (parity tests)."""
+    the paper's).  fields='random' gives seeded N(0, 1) initial fields (parity tests).  film_sigma
+    replaces the case's film conductivity (the Q runs' sensitivity study)."""
     sig_f, ell_f, _, _ = PAPER_CPW_CASES[case]
+    if film_sigma is not None:
+        sig_f = float(film_sigma)
     px, py, pz = npml
     dx = dy = 1e-6
     nx, ny, nz = 130 + 2 * px, 1008 + 2 * py, int(round(64e-6 / dz)) + 2 * pz
